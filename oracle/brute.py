@@ -1,0 +1,125 @@
+"""Pure-Python brute force of the stacking definition, for tiny inputs only.
+
+TEST INFRASTRUCTURE ONLY.  A second, independently written implementation of the same
+definition as ``vista_oracle.c`` (scalar ``math`` in double precision, dictionaries for
+the grid), used to check the C oracle on small random cases.  It follows the paper's
+steps directly: rest-frame edges (Sec. 3.1), the Eq. 2 phase shift with
+(dl, dm, dn) = (-l, -m, 1-n), the Eq. 3-4 overlap fractions with centred-difference
+widths, and a nearest-cell (u, v, nu_rest) accumulation.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+
+def _widths(freq, width):
+    n = len(freq)
+    if width is not None:
+        return [float(x) for x in width]
+    out = []
+    for k in range(n):
+        if k == 0:
+            out.append(abs(freq[1] - freq[0]))
+        elif k == n - 1:
+            out.append(abs(freq[n - 1] - freq[n - 2]))
+        else:
+            out.append(abs(freq[k + 1] - freq[k - 1]) / 2.0)
+    return out
+
+
+def overlap_pairs(grid, freq, width, z):
+    """For each input channel the list of (j, f_kj) with f_kj > 1e-9 (Eq. 4)."""
+    opz = 1.0 + z
+    Ws = _widths([float(x) for x in freq], width)
+    pairs = []
+    for k, nu in enumerate(freq):
+        nu = float(nu)
+        if grid.get("flags", 0) & 4:
+            x = math.floor((nu * opz - grid["freq_lo"]) / grid["dfreq"])
+            pairs.append([(int(x), 1.0)] if 0 <= x < grid["nchan"] else [])
+            continue
+        lo = (nu - 0.5 * Ws[k]) * opz
+        hi = (nu + 0.5 * Ws[k]) * opz
+        wr = Ws[k] * opz
+        lst = []
+        for j in range(grid["nchan"]):
+            ej = grid["freq_lo"] + float(j) * grid["dfreq"]
+            ej1 = grid["freq_lo"] + float(j + 1) * grid["dfreq"]
+            ov = min(hi, ej1) - max(lo, ej)
+            if ov / wr > 1e-9:
+                lst.append((j, ov / wr))
+        pairs.append(lst)
+    return pairs
+
+
+def stack(grid: dict, targets) -> dict:
+    """Returns {(j, iv, iu): [S (complex), W, A, N]} and the sample classification."""
+    cells = {}
+    st = dict(n_samples=0, n_flagged=0, n_bad_weight=0, n_outside_uv=0, n_outside_band=0, n_used=0,
+              n_contrib=0)
+    nu_, nv_ = grid["nu"], grid["nv"]
+    for t in targets:
+        uvw = np.asarray(t["uvw"], np.float64)
+        vis = np.asarray(t["vis"])
+        if not np.iscomplexobj(vis):
+            vis = vis.view(np.complex64)[..., 0] if vis.shape[-1] == 2 else vis
+        flag = t.get("flag")
+        weight = np.asarray(t["weight"], np.float32)
+        freq = [float(x) for x in t["chan_freq"]]
+        pairs = overlap_pairs(grid, freq, t.get("chan_width"), float(t["z"]))
+        l, m = float(t["l"]), float(t["m"])
+        n_minus_1 = -(l * l + m * m) / (1.0 + math.sqrt(1.0 - (l * l + m * m)))
+        npol = vis.shape[2]
+        for r in range(uvw.shape[0]):
+            for k in range(len(freq)):
+                a = freq[k] / C_LIGHT
+                u, v, w = float(uvw[r, 0]) * a, float(uvw[r, 1]) * a, float(uvw[r, 2]) * a
+                ru = round_half_even(u * (1.0 / grid["du"]))
+                rv = round_half_even(v * (1.0 / grid["dv"]))
+                inside = (-(nu_ // 2) <= ru < nu_ - nu_ // 2) and (-(nv_ // 2) <= rv < nv_ - nv_ // 2)
+                turns = u * l + v * m + w * n_minus_1
+                ph = 2.0 * math.pi * (turns - round_half_even(turns))
+                rot = complex(math.cos(ph), math.sin(ph))
+                for p in range(npol):
+                    st["n_samples"] += 1
+                    if not pairs[k]:
+                        st["n_outside_band"] += 1
+                        continue
+                    if not inside:
+                        st["n_outside_uv"] += 1
+                        continue
+                    if flag is not None and flag[r, k, p]:
+                        st["n_flagged"] += 1
+                        continue
+                    wt = float(weight[r, k, p] if t.get("weight_per_chan") else weight[r, p])
+                    if not (wt > 0.0 and math.isfinite(wt)):
+                        st["n_bad_weight"] += 1
+                        continue
+                    st["n_used"] += 1
+                    vv = complex(float(vis[r, k, p].real), float(vis[r, k, p].imag)) * rot
+                    for j, f in pairs[k]:
+                        key = (j, int(rv) + nv_ // 2, int(ru) + nu_ // 2)
+                        c = cells.setdefault(key, [0j, 0.0, 0.0, 0])
+                        c[0] += wt * f * vv
+                        c[1] += wt * f
+                        c[2] += wt * f * abs(vv)
+                        c[3] += 1
+                        st["n_contrib"] += 1
+    return dict(cells=cells, stats=st)
+
+
+def round_half_even(x: float) -> float:
+    """IEEE round-to-nearest-even of a double (math.floor based, exact for |x| < 2^52)."""
+    if not math.isfinite(x):
+        return x
+    f = math.floor(x)
+    d = x - f
+    if d > 0.5:
+        return f + 1.0
+    if d < 0.5:
+        return f
+    return f if (f % 2.0) == 0.0 else f + 1.0

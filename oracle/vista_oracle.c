@@ -1,0 +1,418 @@
+/*
+ * FP64 CPU oracle for the ViSta stacking hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference the GPU library is checked against.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it; the product library
+ * never does.  It shares no code, header or table with the GPU path.
+ *
+ * What it computes (Torsello et al., "The ViSta method ...", Proc. SPIE 14153):
+ *   for every target, row, channel and polarisation, in that order,
+ *     - the channel is moved to the rest frame, nu_rest = nu_obs (1+z) (Sec. 3.1);
+ *     - the uvw are taken to wavelengths at the sample's own frequency,
+ *       u_lambda = u_m nu_obs / c, which is the 1/(1+z) baseline scaling of Eq. 1
+ *       paired with the rest-frame frequency;
+ *     - the visibility is multiplied by the phase-centre shift of Eq. 2, with
+ *       (dl, dm, dn) = (0 - l, 0 - m, 1 - n), i.e. by exp(+2 pi i t),
+ *       t = u l + v m + w (n - 1) in turns;
+ *     - the rotated value is split over the common rest channels with the
+ *       channel-overlap weights of Eq. 3-4 (input width: the given width, else a
+ *       centred finite difference, one-sided at the ends);
+ *     - each (weight * fraction)-weighted value is added to the nearest uv cell of a
+ *       common (u, v, nu_rest) grid holding sum(w f V'), sum(w f), the number of
+ *       contributions and sum(w f |V'|) (the last is only a scale for error norms).
+ *   The paper casts visibilities to double before the phase multiply (Sec. 3.2, last
+ *   paragraph); so does this file, and everything else is double too.
+ *
+ * Build with -ffp-contract=off and without fast-math: the cell and channel indices
+ * must follow exactly the operation sequence written here.
+ *
+ * Parallelism: ora_stack splits the requested rest-channel range into contiguous
+ * slabs, one per OpenMP thread.  Each cell is owned by one thread, which adds its
+ * contributions in (target, row, channel, polarisation) order, so the result does
+ * not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_C 299792458.0
+#define ORA_SLIVER 1e-9
+#define ORA_PI 3.14159265358979323846
+#define ORA_NEAREST 4u          /* grid flag: one output channel per input channel */
+
+typedef struct {
+    int32_t nu, nv, nchan;
+    double du, dv, freq_lo, dfreq;
+    uint32_t flags;
+} ora_grid;
+
+typedef struct {
+    int64_t nrow;
+    int32_t nchan, npol;
+    const double* uvw;        /* [nrow][3] metres */
+    const float* vis;         /* [nrow][kend-kbeg][npol][2] (re, im) */
+    const float* weight;      /* [nrow][npol], or [nrow][kend-kbeg][npol] if weight_per_chan */
+    const uint8_t* flag;      /* [nrow][kend-kbeg][npol] or NULL */
+    const double* chan_freq;  /* [nchan], all channels */
+    const double* chan_width; /* [nchan] or NULL */
+    double l, m, z;
+    int32_t weight_per_chan;
+    int32_t kbeg, kend;       /* the data arrays hold channels [kbeg, kend) */
+} ora_target;
+
+/* Per-channel rest-frame table of one target: a_k = nu_k / c and the contributing set
+ * J_k = {(j, f_kj)} stored as a CSR list. */
+typedef struct {
+    int32_t nchan;
+    double* a;        /* [nchan] */
+    double* width;    /* [nchan] W_k */
+    double* lo;       /* [nchan] rest-frame lower edge */
+    double* hi;       /* [nchan] rest-frame upper edge */
+    int32_t* start;   /* [nchan+1] */
+    int32_t* j;       /* [start[nchan]] */
+    double* f;        /* [start[nchan]] */
+} ora_table;
+
+/* Input channel width W_k (Eq. 4's Delta nu_k): the given width, else a centred
+ * finite difference |nu_{k+1} - nu_{k-1}| / 2, one-sided at the two ends. */
+static double ora_width(const double* f, const double* w, int32_t n, int32_t k) {
+    if (w) return w[k];
+    if (n < 2) return NAN;
+    if (k == 0) return fabs(f[1] - f[0]);
+    if (k == n - 1) return fabs(f[n - 1] - f[n - 2]);
+    return fabs(f[k + 1] - f[k - 1]) / 2.0;
+}
+
+/* Build the table of one target (Sec. 3.1 rest frame; Eq. 3-4 overlaps). */
+static int ora_build_table(const ora_grid* g, const ora_target* t, ora_table* tb) {
+    int32_t n = t->nchan;
+    double opz = 1.0 + t->z;
+    int32_t cap = 0, k, j;
+    memset(tb, 0, sizeof(*tb));
+    tb->nchan = n;
+    tb->a = (double*)malloc(sizeof(double) * n);
+    tb->width = (double*)malloc(sizeof(double) * n);
+    tb->lo = (double*)malloc(sizeof(double) * n);
+    tb->hi = (double*)malloc(sizeof(double) * n);
+    tb->start = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+    if (!tb->a || !tb->width || !tb->lo || !tb->hi || !tb->start) return -3;
+    for (k = 0; k < n; ++k) {
+        double W = ora_width(t->chan_freq, t->chan_width, n, k);
+        tb->a[k] = t->chan_freq[k] / ORA_C;
+        tb->width[k] = W;
+        tb->lo[k] = (t->chan_freq[k] - 0.5 * W) * opz;
+        tb->hi[k] = (t->chan_freq[k] + 0.5 * W) * opz;
+    }
+    /* Two passes over every (k, j): count, then fill. */
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t pos = 0;
+        for (k = 0; k < n; ++k) {
+            tb->start[k] = pos;
+            if (g->flags & ORA_NEAREST) {
+                double x = floor((t->chan_freq[k] * opz - g->freq_lo) / g->dfreq);
+                if (x >= 0.0 && x < (double)g->nchan) {
+                    if (pass) { tb->j[pos] = (int32_t)x; tb->f[pos] = 1.0; }
+                    ++pos;
+                }
+                continue;
+            }
+            double Wr = tb->width[k] * opz;
+            for (j = 0; j < g->nchan; ++j) {
+                double e0 = g->freq_lo + (double)j * g->dfreq;
+                double e1 = g->freq_lo + (double)(j + 1) * g->dfreq;
+                double ov = fmin(tb->hi[k], e1) - fmax(tb->lo[k], e0);
+                double f = ov / Wr;
+                if (f > ORA_SLIVER) {
+                    if (pass) { tb->j[pos] = j; tb->f[pos] = f; }
+                    ++pos;
+                }
+            }
+        }
+        tb->start[n] = pos;
+        if (!pass) {
+            cap = pos > 0 ? pos : 1;
+            tb->j = (int32_t*)malloc(sizeof(int32_t) * cap);
+            tb->f = (double*)malloc(sizeof(double) * cap);
+            if (!tb->j || !tb->f) return -3;
+        }
+    }
+    return 0;
+}
+
+static void ora_free_table(ora_table* tb) {
+    free(tb->a); free(tb->width); free(tb->lo); free(tb->hi);
+    free(tb->start); free(tb->j); free(tb->f);
+    memset(tb, 0, sizeof(*tb));
+}
+
+/* n - 1 for direction cosines (l, m), in the form free of cancellation:
+ * sqrt(1-q) - 1 = -q / (1 + sqrt(1-q)), q = l^2 + m^2. */
+static double ora_n_minus_1(double l, double m) {
+    double q = l * l + m * m;
+    return -q / (1.0 + sqrt(1.0 - q));
+}
+
+/* Nearest uv cell of a (row, channel): u = u_m a_k in wavelengths, index
+ * rint(u / du) counted from the centre cell n/2.  The bounds test is made on the
+ * rounded value in double, so a non-finite or huge coordinate is simply outside;
+ * iu/iv get INT64_MIN when the rounded value does not fit.  Returns 1 if inside. */
+static int ora_cell(const ora_grid* g, const double* uvw_row, double a, int64_t* iu, int64_t* iv) {
+    double inv_du = 1.0 / g->du, inv_dv = 1.0 / g->dv;
+    double u = uvw_row[0] * a;
+    double v = uvw_row[1] * a;
+    double ru = rint(u * inv_du);
+    double rv = rint(v * inv_dv);
+    *iu = fabs(ru) < 4.0e18 ? (int64_t)ru + g->nu / 2 : INT64_MIN;
+    *iv = fabs(rv) < 4.0e18 ? (int64_t)rv + g->nv / 2 : INT64_MIN;
+    return ru >= -(double)(g->nu / 2) && ru < (double)(g->nu - g->nu / 2) &&
+           rv >= -(double)(g->nv / 2) && rv < (double)(g->nv - g->nv / 2);
+}
+
+/* Eq. 2 phasor: exp(+2 pi i t) with t = u l + v m + w (n-1) in turns, reduced to
+ * t - rint(t) before the trigonometry. */
+static void ora_phasor(const double* uvw_row, double a, double l, double m, double nm1,
+                       double* c, double* s) {
+    double u = uvw_row[0] * a, v = uvw_row[1] * a, w = uvw_row[2] * a;
+    double t = u * l + v * m + w * nm1;
+    double ph = 2.0 * ORA_PI * (t - rint(t));
+    *c = cos(ph);
+    *s = sin(ph);
+}
+
+static double ora_weight(const ora_target* t, int64_t r, int32_t kk, int32_t p) {
+    int32_t nk = t->kend - t->kbeg;
+    if (t->weight_per_chan) return (double)t->weight[((size_t)r * nk + kk) * t->npol + p];
+    return (double)t->weight[(size_t)r * t->npol + p];
+}
+
+/* ------------------------------------------------------------------------------- */
+
+int ora_check(const ora_grid* g, int32_t ntgt, const ora_target* tg) {
+    if (!g || g->nu < 1 || g->nv < 1 || g->nchan < 1) return -1;
+    if (!(g->du > 0 && isfinite(g->du) && g->dv > 0 && isfinite(g->dv))) return -1;
+    if (!(g->dfreq > 0 && isfinite(g->dfreq) && isfinite(g->freq_lo))) return -1;
+    for (int32_t i = 0; i < ntgt; ++i) {
+        const ora_target* t = &tg[i];
+        if (t->nrow < 0 || t->nchan < 1 || (t->npol != 1 && t->npol != 2 && t->npol != 4)) return -1;
+        if (t->kbeg < 0 || t->kend > t->nchan || t->kbeg > t->kend) return -1;
+        if (t->nchan == 1 && !t->chan_width) return -1;
+        if (!(t->z > -1.0 && isfinite(t->z))) return -1;
+        if (!(t->l * t->l + t->m * t->m < 1.0)) return -1;
+    }
+    return 0;
+}
+
+/* The stack over rest channels [jlo, jhi).  Outputs are dense over that slab:
+ * S [jhi-jlo][nv][nu][2], W, A [jhi-jlo][nv][nu], N likewise (uint64).  Any of
+ * them may be NULL.  stats (7 x uint64, may be NULL) classifies every sample of
+ * every target, whatever the slab:
+ *   [0] samples  [1] flagged  [2] bad weight  [3] outside uv  [4] outside band
+ *   [5] used     [6] contributions (pairs (sample, j) over all j).
+ * Classification order: outside band (J_k empty) -> outside uv -> flagged ->
+ * weight not finite or not > 0 -> used. */
+int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo, int32_t jhi,
+              double* S, double* W, double* A, uint64_t* N, uint64_t* stats, int nthreads) {
+    if (ora_check(g, ntgt, tg)) return -1;
+    if (jlo < 0 || jhi > g->nchan || jlo > jhi) return -1;
+    size_t plane = (size_t)g->nu * g->nv;
+    size_t ncell = plane * (size_t)(jhi - jlo);
+    if (S) memset(S, 0, sizeof(double) * 2 * ncell);
+    if (W) memset(W, 0, sizeof(double) * ncell);
+    if (A) memset(A, 0, sizeof(double) * ncell);
+    if (N) memset(N, 0, sizeof(uint64_t) * ncell);
+    if (stats) memset(stats, 0, sizeof(uint64_t) * 7);
+
+    ora_table* tabs = (ora_table*)calloc(ntgt > 0 ? ntgt : 1, sizeof(ora_table));
+    if (!tabs) return -3;
+    int rc = 0;
+    for (int32_t i = 0; i < ntgt && !rc; ++i) rc = ora_build_table(g, &tg[i], &tabs[i]);
+    if (rc) { for (int32_t i = 0; i < ntgt; ++i) ora_free_table(&tabs[i]); free(tabs); return rc; }
+
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    if (nth > jhi - jlo) nth = jhi - jlo > 0 ? jhi - jlo : 1;
+
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nth)
+#endif
+    {
+        int th = 0;
+#ifdef _OPENMP
+        th = omp_get_thread_num();
+#endif
+        /* this thread's rest-channel slab */
+        int32_t span = jhi - jlo;
+        int32_t ja = jlo + (int32_t)((int64_t)span * th / nth);
+        int32_t jb = jlo + (int32_t)((int64_t)span * (th + 1) / nth);
+        for (int32_t i = 0; i < ntgt; ++i) {
+            const ora_target* t = &tg[i];
+            const ora_table* tb = &tabs[i];
+            double nm1 = ora_n_minus_1(t->l, t->m);
+            int32_t nk = t->kend - t->kbeg;
+            for (int64_t r = 0; r < t->nrow; ++r) {
+                const double* uvw = t->uvw + 3 * r;
+                for (int32_t k = t->kbeg; k < t->kend; ++k) {
+                    int32_t q0 = tb->start[k], q1 = tb->start[k + 1], q;
+                    int mine = 0;
+                    for (q = q0; q < q1; ++q) mine |= (tb->j[q] >= ja && tb->j[q] < jb);
+                    if (!mine) continue;
+                    int64_t iu, iv;
+                    if (!ora_cell(g, uvw, tb->a[k], &iu, &iv)) continue;
+                    double pc, ps;
+                    ora_phasor(uvw, tb->a[k], t->l, t->m, nm1, &pc, &ps);
+                    int32_t kk = k - t->kbeg;
+                    for (int32_t p = 0; p < t->npol; ++p) {
+                        size_t e = ((size_t)r * nk + kk) * t->npol + p;
+                        if (t->flag && t->flag[e]) continue;
+                        double wt = ora_weight(t, r, kk, p);
+                        if (!(wt > 0.0 && isfinite(wt))) continue;
+                        double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
+                        double xr = vr * pc - vi * ps;      /* V' = V * (pc + i ps) */
+                        double xi = vr * ps + vi * pc;
+                        double mag = sqrt(xr * xr + xi * xi);
+                        for (q = q0; q < q1; ++q) {
+                            int32_t j = tb->j[q];
+                            if (j < ja || j >= jb) continue;
+                            double wf = wt * tb->f[q];
+                            size_t c = (size_t)(j - jlo) * plane + (size_t)iv * g->nu + (size_t)iu;
+                            if (S) { S[2 * c] += wf * xr; S[2 * c + 1] += wf * xi; }
+                            if (W) W[c] += wf;
+                            if (A) A[c] += wf * mag;
+                            if (N) N[c] += 1;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if (stats) {
+        for (int32_t i = 0; i < ntgt; ++i) {
+            const ora_target* t = &tg[i];
+            const ora_table* tb = &tabs[i];
+            int32_t nk = t->kend - t->kbeg;
+            for (int64_t r = 0; r < t->nrow; ++r) {
+                for (int32_t k = t->kbeg; k < t->kend; ++k) {
+                    int32_t nj = tb->start[k + 1] - tb->start[k];
+                    int64_t iu, iv;
+                    int inside = nj > 0 ? ora_cell(g, t->uvw + 3 * r, tb->a[k], &iu, &iv) : 0;
+                    int32_t kk = k - t->kbeg;
+                    for (int32_t p = 0; p < t->npol; ++p) {
+                        size_t e = ((size_t)r * nk + kk) * t->npol + p;
+                        stats[0]++;
+                        if (nj == 0) { stats[4]++; continue; }
+                        if (!inside) { stats[3]++; continue; }
+                        if (t->flag && t->flag[e]) { stats[1]++; continue; }
+                        double wt = ora_weight(t, r, kk, p);
+                        if (!(wt > 0.0 && isfinite(wt))) { stats[2]++; continue; }
+                        stats[5]++;
+                        stats[6] += (uint64_t)nj;
+                    }
+                }
+            }
+        }
+    }
+    for (int32_t i = 0; i < ntgt; ++i) ora_free_table(&tabs[i]);
+    free(tabs);
+    return 0;
+}
+
+/* Per (row, channel) indices of one target for channels [kbeg, kend): the uv cell
+ * (iu, iv) as computed before the grid-bounds test, and the first rest channel and
+ * size of J_k (j0 = -1, nj = 0 when J_k is empty). */
+int ora_indices(const ora_grid* g, const ora_target* t, int64_t* iu, int64_t* iv, int32_t* j0,
+                int32_t* nj) {
+    if (ora_check(g, 1, t)) return -1;
+    ora_table tb;
+    int rc = ora_build_table(g, t, &tb);
+    if (rc) { ora_free_table(&tb); return rc; }
+    int32_t nk = t->kend - t->kbeg;
+    for (int64_t r = 0; r < t->nrow; ++r) {
+        for (int32_t k = t->kbeg; k < t->kend; ++k) {
+            size_t e = (size_t)r * nk + (k - t->kbeg);
+            int64_t a, b;
+            ora_cell(g, t->uvw + 3 * r, tb.a[k], &a, &b);
+            iu[e] = a;
+            iv[e] = b;
+            int32_t n = tb.start[k + 1] - tb.start[k];
+            nj[e] = n;
+            j0[e] = n ? tb.j[tb.start[k]] : -1;
+        }
+    }
+    ora_free_table(&tb);
+    return 0;
+}
+
+/* The rotated visibilities V' = V exp(+2 pi i t) of every sample (Eq. 2), regardless
+ * of flags and weights: out [nrow][kend-kbeg][npol][2]. */
+int ora_rotate(const ora_target* t, double* out) {
+    if (t->nchan < 1 || t->kbeg < 0 || t->kend > t->nchan || t->kbeg > t->kend) return -1;
+    double nm1 = ora_n_minus_1(t->l, t->m);
+    int32_t nk = t->kend - t->kbeg;
+    for (int64_t r = 0; r < t->nrow; ++r) {
+        for (int32_t k = t->kbeg; k < t->kend; ++k) {
+            double pc, ps;
+            ora_phasor(t->uvw + 3 * r, t->chan_freq[k] / ORA_C, t->l, t->m, nm1, &pc, &ps);
+            for (int32_t p = 0; p < t->npol; ++p) {
+                size_t e = ((size_t)r * nk + (k - t->kbeg)) * t->npol + p;
+                double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
+                out[2 * e] = vr * pc - vi * ps;
+                out[2 * e + 1] = vr * ps + vi * pc;
+            }
+        }
+    }
+    return 0;
+}
+
+/* The channel table of one target: a_k, W_k, rest edges, and J_k as CSR
+ * (start[nchan+1], j[], f[]).  Call with j == NULL first to get the pair count in
+ * *npairs, then again with arrays of that size. */
+int ora_channel_table(const ora_grid* g, const ora_target* t, double* a, double* width, double* lo,
+                      double* hi, int32_t* start, int32_t* j, double* f, int32_t* npairs) {
+    if (ora_check(g, 1, t)) return -1;
+    ora_table tb;
+    int rc = ora_build_table(g, t, &tb);
+    if (rc) { ora_free_table(&tb); return rc; }
+    int32_t n = tb.nchan, np = tb.start[n];
+    if (j && f && *npairs >= np) {
+        memcpy(j, tb.j, sizeof(int32_t) * np);
+        memcpy(f, tb.f, sizeof(double) * np);
+    }
+    if (a) memcpy(a, tb.a, sizeof(double) * n);
+    if (width) memcpy(width, tb.width, sizeof(double) * n);
+    if (lo) memcpy(lo, tb.lo, sizeof(double) * n);
+    if (hi) memcpy(hi, tb.hi, sizeof(double) * n);
+    if (start) memcpy(start, tb.start, sizeof(int32_t) * (n + 1));
+    *npairs = np;
+    ora_free_table(&tb);
+    return 0;
+}
+
+/* The paper's common output grid (Sec. 3.1): the rest channel width is the widest
+ * rest-frame input channel of all targets, Delta nu_new = max_i Delta nu_rf,i, and the
+ * nchan_out channels are centred on central_freq. */
+int ora_plan_spectral_grid(int32_t n, const double* const* chan_freq, const double* const* chan_width,
+                           const int32_t* nchan, const double* z, double central_freq,
+                           int32_t nchan_out, double* freq_lo, double* dfreq) {
+    if (n < 1 || nchan_out < 1) return -1;
+    double wmax = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (nchan[i] < 1 || (nchan[i] == 1 && !(chan_width && chan_width[i]))) return -1;
+        for (int32_t k = 0; k < nchan[i]; ++k) {
+            double W = ora_width(chan_freq[i], chan_width ? chan_width[i] : NULL, nchan[i], k);
+            double Wr = W * (1.0 + z[i]);
+            if (Wr > wmax) wmax = Wr;
+        }
+    }
+    if (!(wmax > 0.0)) return -1;
+    *dfreq = wmax;
+    *freq_lo = central_freq - 0.5 * (double)nchan_out * wmax;
+    return 0;
+}
