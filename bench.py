@@ -1,0 +1,199 @@
+"""Benchmark of the stacking hot path on one MI355X.
+
+A step is one whole pass of the hot path over one synthetic workload already resident
+in HBM: create a stack, add every target (host planning), finalize (binning, LDS
+accumulation with the Eq. 2 rotation and Eq. 3-4 rebinning, every output cell written).
+
+Default workload: 50 targets x 43 antennas (903 baselines) x 120 integrations x 4 spws x
+240 channels x 2 polarisations, z ~ U(1.5, 3.5), onto a 512 x 512 x 960 grid.
+
+Prints one JSON line: throughput in stacked vis*chan*pol samples/s, the accumulation
+kernel against the HBM roofline (algorithmic bytes / its hipEvent-timed duration), and
+the FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stacked vis·chan·pol/s + HBM GB/s vs peak; batched/compensated vs plain speedup"
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, AMD public specification
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "accum_c2_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_01897_amd", "csrc", "vista_kernels.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(targets, grid, kahan=False):
+    """Bytes the method must move: 8 B vis + 1 B flag per sample, uvw (24 B) and weights
+    (4 B per pol) per row, and one write of the grid state (16 B per cell)."""
+    nb = 0
+    ns = 0
+    for t in targets:
+        nrow, nch, npol = int(t.vis.shape[0]), int(t.vis.shape[1]), int(t.vis.shape[2])
+        s = nrow * nch * npol
+        ns += s
+        nb += s * (8 + (1 if t.flag is not None else 0))
+        nb += nrow * (24 + 4 * npol) if not t.weight_per_chan else nrow * 24 + s * 4
+    ncell = int(grid["nu"]) * int(grid["nv"]) * int(grid["nchan"])
+    nb += ncell * 16
+    return nb, ns
+
+
+def counter_traffic():
+    """Counter-measured HBM bytes of one accumulation launch, if the committed summary was
+    taken on the current kernel source."""
+    try:
+        d = json.load(open(PROFILE_COUNTERS))
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if d.get("kernel_sha256") == h:
+            return d.get("hbm_bytes_per_launch")
+    except Exception:
+        pass
+    return None
+
+
+def cpu_baseline(targets_dev, grid, n_targets):
+    """The FP64 oracle on the first n_targets targets (all rows and channels)."""
+    import oracle
+    hosts = [t.to("cpu") for t in targets_dev[:n_targets]]
+    ns = sum(int(t.vis.numel()) for t in hosts)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.stack(grid, hosts, stats=False, threads=threads, want=("S", "W", "N"))
+    dt = time.perf_counter() - t0
+    return dict(value=ns / dt, unit="vis·chan·pol/s", cores=threads, kind="oracle",
+                sample="%d of %d targets of the workload (all rows, channels, pols; %d samples), %.1f s"
+                % (n_targets, len(targets_dev), ns, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--targets", type=int, default=0, help="use only this many targets (0 = all)")
+    ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32")
+    ap.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes "
+              "for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2609_01897_amd import vista
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    vista.lib()
+    cfg = synth.config(args.config)
+    ntg = args.targets or cfg.n_targets
+    grid = synth.make_grid(cfg)
+    flags = 0
+    for f in filter(None, args.flags.split(",")):
+        flags |= {"kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC,
+                  "phase_fp32": vista.F_PHASE_FP32}[f]
+    tuning = None
+    if args.tuning:
+        a = [int(x) for x in args.tuning.split(",")]
+        tuning = dict(tile_u=a[0], tile_v=a[1], jblock=a[2], waves=a[3])
+
+    t0 = time.perf_counter()
+    targets = []
+    for i in range(ntg):
+        targets.append(synth.make_target(cfg, i, device="cuda"))
+    torch.cuda.synchronize()
+    log("generated %d targets on the GPU in %.1f s" % (ntg, time.perf_counter() - t0))
+    nbytes, nsamp = algorithmic_bytes(targets, grid)
+    out = vista.alloc_outputs(grid)
+
+    def step():
+        s = vista.Stack(grid, flags=flags, tuning=tuning)
+        for t in targets:
+            s.add(t)
+        st = s.finalize(out)
+        tim = s.timings()
+        s.close()
+        return st, tim
+
+    for i in range(args.warmup):
+        st, tim = step()
+        log("warmup %d: total %.2f ms (bin %.2f, accum %.2f), %d records" % (
+            i, tim["total_ms"], tim["bin_ms"], tim["accum_ms"], tim["n_records"]))
+    torch.cuda.synchronize()
+    accum = []
+    binms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, tim = step()
+        accum.append(tim["accum_ms"])
+        binms.append(tim["bin_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    value = nsamp / (ms / 1e3)
+    acc_ms = sum(accum) / len(accum)
+    achieved = nbytes / (acc_ms / 1e3) / 1e9
+    log("step %.2f ms, accumulate %.2f ms, binning %.2f ms; %.3e samples/s; %.0f GB/s algorithmic" % (
+        ms, acc_ms, sum(binms) / len(binms), value, achieved))
+    assert st["n_samples"] == nsamp, (st, nsamp)
+    traffic = counter_traffic()
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "vis·chan·pol/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d targets x %d baselines x %d integrations x %d chan x %d pol, grid %dx%dx%d"
+                        % (cfg.name, ntg, cfg.n_ant[0] * (cfg.n_ant[0] - 1) // 2, cfg.n_int, cfg.nchan[0],
+                           cfg.npol, grid["nu"], grid["nv"], grid["nchan"]),
+            "samples": nsamp,
+            "algorithmic_bytes": nbytes,
+            "flags": args.flags or "plain",
+            "phase_argument": "f64" if not (flags & vista.F_PHASE_FP32) else "f32",
+            "accumulate_ms": acc_ms,
+            "binning_ms": sum(binms) / len(binms),
+            "records": tim["n_records"],
+            "units": tim["n_units"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu:
+        log("timing the FP64 oracle on %d targets" % args.cpu_targets)
+        res["cpu_baseline"] = cpu_baseline(targets, grid, args.cpu_targets)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * vista.h -- C ABI of the MI355X (gfx950) ViSta stacking library.
+ *
+ * The library stacks interferometric target datasets in the visibility domain, as
+ * described by Torsello et al., "The ViSta method for optimized stacking of broadband
+ * interferometric data in the Fourier domain", Proc. SPIE 14153 (2026):
+ *   - each target's visibilities are phase-rotated to the target's own position
+ *     (Sec. 3.2, Eq. 2, with (dl, dm, dn) = (0 - l, 0 - m, 1 - n));
+ *   - each channel is moved to the rest frame, nu_rest = nu_obs (1 + z) (Sec. 3.1), and
+ *     its uvw are taken to wavelengths at the sample's own frequency, which is Eq. 1's
+ *     1/(1+z) baseline scaling paired with the rest-frame frequency;
+ *   - every (row, channel, polarisation) sample is split over the common rest channels
+ *     with the channel-overlap weights of Eq. 3-4 and added, weighted, into the nearest
+ *     cell of one (u, v, nu_rest) grid holding sum(w f V'), sum(w f) and counts.
+ *
+ * Conventions
+ *   - Every function returns int: VISTA_OK (0) or a negative VISTA_E_* code.  On error a
+ *     thread-local message is available from vista_last_error().  No C++ exception
+ *     crosses this interface.
+ *   - hip streams are passed as void* (a hipStream_t; NULL = the null stream).
+ *   - All arrays are C order (row-major); complex values are interleaved (re, im) float.
+ *   - Arguments are validated before any device work.  A validation failure returns
+ *     VISTA_E_ARG and leaves the handle unchanged.  A HIP failure returns VISTA_E_HIP and
+ *     poisons the handle: afterwards every call except *_destroy returns VISTA_E_STATE.
+ *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef VISTA_H
+#define VISTA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VISTA_OK = 0,
+    VISTA_E_ARG = -1,    /* invalid argument; nothing was changed */
+    VISTA_E_STATE = -2,  /* call not allowed in the handle's state (finalized, poisoned) */
+    VISTA_E_NOMEM = -3,  /* device or host allocation failed */
+    VISTA_E_HIP = -4,    /* a HIP runtime call failed; the handle is poisoned */
+    VISTA_E_RANGE = -5   /* a result does not fit its output type (a count above 2^32-1) */
+};
+
+/* Where a buffer lives. */
+enum { VISTA_MEM_HOST = 0, VISTA_MEM_HOST_PINNED = 1, VISTA_MEM_DEVICE = 2 };
+
+/* Grid flags. */
+enum {
+    VISTA_F_KAHAN = 1u << 0,            /* compensated FP32 accumulation (ordered path) */
+    VISTA_F_DETERMINISTIC = 1u << 1,    /* bit-identical results from run to run */
+    VISTA_F_SPECTRAL_NEAREST = 1u << 2, /* each input channel goes whole to the rest
+                                           channel holding nu_obs (1+z) */
+    VISTA_F_PHASE_FP32 = 1u << 3        /* ablation: form u_lambda and the phase turns in
+                                           FP32 with full-range sincos (cell indices still
+                                           come from FP64) */
+};
+
+/* The common stack grid.
+ *   uv cell (iu, iv) has centre ((iu - nu/2) du, (iv - nv/2) dv) wavelengths (integer
+ *   division n/2); a sample goes to iu = rint(u_lambda / du) + nu/2 with
+ *   u_lambda = u_m * (nu_obs / c), rint rounding half to even.
+ *   Rest channel j spans [freq_lo + j dfreq, freq_lo + (j+1) dfreq) Hz. */
+typedef struct {
+    int32_t nu, nv;      /* uv cells, 1..65535 each */
+    double du, dv;       /* cell size [wavelengths], finite > 0 */
+    int32_t nchan;       /* rest channels, >= 1 */
+    double freq_lo;      /* rest-frame lower edge of channel 0 [Hz], finite */
+    double dfreq;        /* rest channel width [Hz], finite > 0 */
+    uint32_t flags;      /* VISTA_F_* */
+} vista_grid_desc;
+
+/* One target = one dataset selection (an MS, field and spectral window; Sec. 3.1). */
+typedef struct {
+    int64_t nrow;                /* >= 0 rows (0 = nothing to add) */
+    int32_t nchan;               /* 1..65535 channels */
+    int32_t npol;                /* 1, 2 or 4 */
+    const double* uvw;           /* [nrow][3] baseline coordinates [m] (MS UVW) */
+    const void* vis;             /* complex64 [nrow][nchan][npol] (MS DATA) */
+    const float* weight;         /* [nrow][npol] (MS WEIGHT), or [nrow][nchan][npol] when
+                                    weight_per_chan; samples with !(w > 0) or a non-finite
+                                    w are skipped */
+    const uint8_t* flag;         /* [nrow][nchan][npol], nonzero = flagged; NULL = none */
+    const double* chan_freq;     /* [nchan] observed frequencies [Hz], finite > 0,
+                                    strictly monotonic in either direction; host memory */
+    const double* chan_width;    /* [nchan] widths [Hz] > 0, or NULL: centred finite
+                                    difference, one-sided at the ends (Eq. 4's Delta nu_k);
+                                    required when nchan == 1; host memory */
+    double l, m;                 /* direction cosines of the target relative to the phase
+                                    centre, l*l + m*m < 1 */
+    double z;                    /* redshift, finite, > -1 */
+    int32_t weight_per_chan;     /* 0 or 1 */
+    int32_t mem;                 /* VISTA_MEM_* of uvw, vis, weight and flag */
+} vista_target;
+
+/* Outputs, dense [nchan][nv][nu] over the whole grid.  Any pointer may be NULL to skip
+ * that output.  sum_wvis is complex64, sum_w float, count uint32 (contributions, one per
+ * (sample, rest channel) pair).  sum_wvis64 (complex128) and sum_w64 (double) receive
+ * the compensated sums s - c in FP64 when VISTA_F_KAHAN is set, the FP32 sums widened
+ * otherwise. */
+typedef struct {
+    void* sum_wvis;
+    void* sum_w;
+    void* count;
+    void* sum_wvis64;
+    void* sum_w64;
+    int32_t mem;                 /* VISTA_MEM_* of every non-NULL pointer */
+} vista_output;
+
+/* Classification of every input sample (n_samples is their total):
+ *   outside band -> no rest channel overlaps the sample's channel (Eq. 4 all zero);
+ *   outside uv   -> the nearest cell is off the grid;
+ *   flagged      -> flag != 0;
+ *   bad weight   -> weight not finite or not > 0;
+ *   used         -> everything else; n_contrib counts its (sample, rest channel) pairs.
+ * Each sample lands in the first category that applies, in that order. */
+typedef struct {
+    uint64_t n_samples, n_flagged, n_bad_weight, n_outside_uv, n_outside_band, n_used, n_contrib;
+} vista_stats;
+
+/* Launch shape of the binned accumulation.  Zero fields take the library default or
+ * the autotuned value.  tile_u * tile_v * jblock cells of grid state are held in LDS
+ * per workgroup. */
+typedef struct {
+    int32_t tile_u, tile_v;      /* uv tile in cells */
+    int32_t jblock;              /* rest channels per LDS pass */
+    int32_t waves;               /* wavefronts per workgroup */
+    int32_t wg_per_cu;           /* resident workgroups per compute unit */
+} vista_tuning;
+
+/* Device-event timings of the last finalize / batch run, in milliseconds. */
+typedef struct {
+    double bin_ms;               /* tracks, counting sort, work list */
+    double accum_ms;             /* the LDS accumulation kernel(s) */
+    double finalize_ms;          /* output conversion (Kahan, FP64, host copies) */
+    double total_ms;             /* first to last event */
+    double h2d_ms;               /* streamed input copies (batch waves) */
+    int64_t n_records;           /* (row, tile) track segments binned */
+    int64_t n_units;             /* (tile, rest-channel block) work units */
+    int32_t n_accum_launches;    /* accumulation launches timed in accum_ms */
+    int32_t n_waves;             /* batch waves */
+} vista_timings;
+
+typedef struct vista_stack vista_stack;
+typedef struct vista_batch vista_batch;
+
+/* Create a stack on `hip_stream` (the current device).  The grid state is allocated
+ * when the stack is finalized.  Errors: VISTA_E_ARG (NULL pointer, bad grid), NOMEM. */
+int vista_stack_create(const vista_grid_desc* g, void* hip_stream, vista_stack** out);
+
+/* Add one target.  Host planning runs here (rest-frame edges, Eq. 3-4 overlap table,
+ * a_k = nu_k / c); device work is deferred to vista_stack_finalize, which stacks all
+ * targets in one pass.  VISTA_MEM_HOST data are copied to library staging before the
+ * call returns; VISTA_MEM_HOST_PINNED and VISTA_MEM_DEVICE data must stay valid and
+ * unchanged until finalize returns.  Errors: ARG (see vista_target), STATE (after
+ * finalize or poisoned), NOMEM, HIP. */
+int vista_stack_add_target(vista_stack* s, const vista_target* t);
+
+/* Select the launch shape (NULL = defaults).  Only before finalize. */
+int vista_stack_set_tuning(vista_stack* s, const vista_tuning* tu);
+
+/* Stack every added target, write the outputs, synchronise the stream and return the
+ * classification in *st (may be NULL).  Every output cell is written.  A stack is
+ * finalized once; later add/finalize calls return VISTA_E_STATE.  Errors: ARG, STATE,
+ * NOMEM, HIP, RANGE (a count above 2^32-1; outputs are then undefined). */
+int vista_stack_finalize(vista_stack* s, const vista_output* o, vista_stats* st);
+
+/* Timings of the finalize of this stack (zeros before it). */
+int vista_stack_timings(const vista_stack* s, vista_timings* t);
+
+/* Release everything the stack owns.  Always succeeds for a non-NULL handle. */
+int vista_stack_destroy(vista_stack* s);
+
+/* Batched form: n_stacks independent stacks (each with its own grid g[i]) run in one
+ * persistent, hipGraph-replayed launch sequence per wave.  Targets are recorded by
+ * vista_batch_add_target; vista_batch_run stacks them all.  When the inputs exceed
+ * device memory (VISTA_MEM_HOST_PINNED targets beyond the device budget), they are
+ * streamed in waves through double-buffered device staging on a copy stream, and the
+ * grid state is carried across waves (compensated when VISTA_F_KAHAN). */
+int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_stream, vista_batch** out);
+int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t);
+int vista_batch_set_tuning(vista_batch* b, const vista_tuning* tu);
+/* Device memory the batch may use for streamed input staging (bytes; 0 = default). */
+int vista_batch_set_stream_budget(vista_batch* b, int64_t bytes);
+int vista_batch_run(vista_batch* b);
+int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, vista_stats* st);
+int vista_batch_timings(const vista_batch* b, vista_timings* t);
+int vista_batch_destroy(vista_batch* b);
+
+/* The paper's common rest grid (Sec. 3.1): dfreq = max over targets and channels of the
+ * rest-frame width W_k (1+z) (W_k as for vista_target.chan_width), and the nchan_out
+ * channels centred on central_freq: freq_lo = central_freq - nchan_out dfreq / 2.
+ * chan_width may be NULL, or hold NULL entries.  Host memory.  Errors: ARG. */
+int vista_plan_spectral_grid(int32_t n_targets, const double* const* chan_freq,
+                             const double* const* chan_width, const int32_t* nchan, const double* z,
+                             double central_freq, int32_t nchan_out, double* freq_lo, double* dfreq);
+
+/* Per (row, channel) indices the GPU computes for one target, for bit-exact checks:
+ * iu, iv (the nearest cell before the bounds test, INT32_MIN when not representable),
+ * j0 (first rest channel of the channel's overlap set, -1 if empty) and nj (its size).
+ * Outputs [nrow][nchan] in host memory; the target's data follow t->mem. */
+int vista_debug_indices(const vista_grid_desc* g, const vista_target* t, void* hip_stream,
+                        int32_t* iu, int32_t* iv, int32_t* j0, int32_t* nj);
+
+/* The GPU's rotated visibilities V' = V exp(+2 pi i t) of one target (Eq. 2), complex64
+ * [nrow][nchan][npol], written to device memory `out` (stream-ordered on hip_stream).
+ * Flags and weights are ignored.  The target must be VISTA_MEM_DEVICE. */
+int vista_debug_rotate(const vista_grid_desc* g, const vista_target* t, void* hip_stream, void* out);
+
+/* Autotune the launch shape for the stack's targets: times the candidate shapes on the
+ * real data and keeps the fastest whose counts equal the default shape's.  The result
+ * is applied to the stack and returned in *best (may be NULL).  Only before finalize;
+ * the stack's targets must be VISTA_MEM_DEVICE. */
+int vista_stack_autotune(vista_stack* s, vista_tuning* best);
+
+const char* vista_last_error(void);
+const char* vista_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VISTA_H */

@@ -1,0 +1,39 @@
+// Host planning of one target (rest-frame channel table) and argument validation.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vista.h"
+#include "vista_internal.h"
+
+namespace vista {
+
+// Per-target rest-frame plan (Sec. 3.1 and Eq. 3-4), computed in FP64 on the host.
+struct ChannelPlan {
+    std::vector<DevChan> chan;     // [nchan]
+    std::vector<float> fval;       // overlap fractions, CSR by DevChan::foff / nj
+    std::vector<int32_t> inband;   // [nchan+1] prefix count of channels with nj > 0
+    int32_t kin_lo = 0, kin_hi = 0;  // hull of channels with nj > 0
+    int32_t nphase = 1;            // channel distance with disjoint rest-channel sets
+    int64_t n_inband = 0;          // channels with nj > 0
+    double nm1 = 0.0;              // n - 1 for (l, m)
+};
+
+// Validation; on failure returns false and fills *why.
+bool check_grid(const vista_grid_desc* g, std::string* why);
+bool check_target(const vista_grid_desc* g, const vista_target* t, std::string* why);
+
+// Build the plan of target t on grid g.
+ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t);
+
+// k ranges [lo, hi) of the channels reaching each rest-channel block of size jsub:
+// out[2b], out[2b+1]; empty blocks get lo = hi = 0.
+std::vector<int32_t> block_ranges(const ChannelPlan& p, int32_t nchan_grid, int32_t jsub);
+
+// Input channel width W_k (Eq. 4's Delta nu_k): given width, else centred difference.
+double channel_width(const double* f, const double* w, int32_t n, int32_t k);
+
+}  // namespace vista

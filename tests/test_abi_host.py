@@ -1,0 +1,156 @@
+"""Host-side checks of the C ABI that need no GPU: every declared symbol is exported,
+argument validation rejects bad inputs before any device work, and handle states."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2609_01897_amd import vista
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vista.h")).read()
+    return sorted(set(re.findall(r"\b(vista_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = vista.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(vista.SYMBOLS), set(names) ^ set(vista.SYMBOLS)
+
+
+def test_version():
+    assert "gfx950" in vista.version()
+
+
+def _grid(**kw):
+    g = synth.make_grid("tiny")
+    g.update(kw)
+    return g
+
+
+def _create(g):
+    d = vista.grid_desc(g)
+    h = C.c_void_p()
+    return vista.lib().vista_stack_create(C.byref(d), None, C.byref(h)), h
+
+
+@pytest.mark.parametrize("bad", [dict(nu=0), dict(nv=-3), dict(du=0.0), dict(dv=float("nan")), dict(nchan=0),
+                                 dict(dfreq=-1.0), dict(freq_lo=float("inf")), dict(flags=1 << 9)])
+def test_bad_grid_rejected(bad):
+    rc, h = _create(_grid(**bad))
+    assert rc == vista.VISTA_E_ARG
+    assert vista.lib().vista_last_error()
+
+
+def _target_variants():
+    t = synth.make_target("tiny", 0)
+    yield "z", dict(z=-1.0)
+    yield "z_nan", dict(z=float("nan"))
+    yield "lm", dict(l=0.8, m=0.6)
+    f = t.chan_freq.copy(); f[3] = f[2]
+    yield "nonmonotonic", dict(chan_freq=f)
+    f = t.chan_freq.copy(); f[1] = -f[1]
+    yield "negative_freq", dict(chan_freq=f)
+    yield "single_no_width", dict(chan_freq=t.chan_freq[:1])
+    yield "bad_width", dict(chan_width=np.full(t.nchan, -1.0))
+
+
+@pytest.mark.parametrize("name,change", list(_target_variants()), ids=[n for n, _ in _target_variants()])
+def test_bad_target_rejected(name, change):
+    rc, h = _create(_grid())
+    assert rc == 0
+    t = synth.make_target("tiny", 0)
+    for k, v in change.items():
+        setattr(t, k, v)
+    if name == "single_no_width":
+        t.vis = t.vis[:, :1].contiguous(); t.flag = t.flag[:, :1].contiguous(); t.chan_width = None
+    keep = []
+    d = vista.target_desc(t, keep)
+    assert vista.lib().vista_stack_add_target(h, C.byref(d)) == vista.VISTA_E_ARG
+    # a rejected target changes nothing: the handle stays open
+    good = synth.make_target("tiny", 1)
+    d2 = vista.target_desc(good, keep)
+    assert vista.lib().vista_stack_add_target(h, C.byref(d2)) == vista.VISTA_OK
+    vista.lib().vista_stack_destroy(h)
+
+
+def test_null_and_misaligned_arguments():
+    L = vista.lib()
+    g = vista.grid_desc(_grid())
+    assert L.vista_stack_create(None, None, None) == vista.VISTA_E_ARG
+    assert L.vista_stack_add_target(None, None) == vista.VISTA_E_ARG
+    rc, h = _create(_grid())
+    assert L.vista_stack_add_target(h, None) == vista.VISTA_E_ARG
+    t = synth.make_target("tiny", 0)
+    keep = []
+    d = vista.target_desc(t, keep)
+    d.vis = d.vis + 4            # complex64 pairs are read 16 bytes at a time
+    assert L.vista_stack_add_target(h, C.byref(d)) == vista.VISTA_E_ARG
+    d = vista.target_desc(t, keep)
+    d.npol = 3
+    assert L.vista_stack_add_target(h, C.byref(d)) == vista.VISTA_E_ARG
+    d = vista.target_desc(t, keep)
+    d.mem = 7
+    assert L.vista_stack_add_target(h, C.byref(d)) == vista.VISTA_E_ARG
+    tu = vista.Tuning(3, 3, 7, 4, 0)
+    assert L.vista_stack_set_tuning(h, C.byref(tu)) == vista.VISTA_E_ARG
+    assert L.vista_stack_destroy(h) == vista.VISTA_OK
+    assert L.vista_stack_destroy(None) == vista.VISTA_E_ARG
+    del g
+
+
+def test_plan_spectral_grid_matches_paper_rule():
+    f1 = 30e9 + np.arange(64) * 15.625e6
+    f2 = (40e9 + np.arange(200) * 7.8125e6)[::-1].copy()
+    lo, df = vista.plan_spectral_grid([f1, f2], [None, None], [2.5, 3.0], 115.2712018e9, 64)
+    assert df == 15.625e6 * 3.5
+    assert lo == 115.2712018e9 - 32 * df
+    with pytest.raises(vista.VistaError):
+        vista.plan_spectral_grid([f1[:1]], [None], [1.0], 1e9, 4)
+
+
+def test_batch_validation():
+    L = vista.lib()
+    g1 = _grid()
+    g2 = _grid(flags=vista.F_KAHAN)
+    arr = (vista.GridDesc * 2)(vista.grid_desc(g1), vista.grid_desc(g2))
+    h = C.c_void_p()
+    assert L.vista_batch_create(2, arr, None, C.byref(h)) == vista.VISTA_E_ARG
+    arr = (vista.GridDesc * 2)(vista.grid_desc(g1), vista.grid_desc(g1))
+    assert L.vista_batch_create(2, arr, None, C.byref(h)) == vista.VISTA_OK
+    t = synth.make_target("tiny", 0)
+    keep = []
+    d = vista.target_desc(t, keep)
+    assert L.vista_batch_add_target(h, 5, C.byref(d)) == vista.VISTA_E_ARG
+    assert L.vista_batch_add_target(h, 1, C.byref(d)) == vista.VISTA_OK
+    out = vista.Output()
+    assert L.vista_batch_finalize(h, 0, C.byref(out), None) == vista.VISTA_E_STATE
+    assert L.vista_batch_destroy(h) == vista.VISTA_OK
+
+
+def test_failure_paths_forced_from_host(monkeypatch):
+    """Without a device (or with the injected faults) finalize fails cleanly, poisons the
+    handle, and destroy still succeeds."""
+    for env in ({"VISTA_FAULT_INJECT": "alloc"}, {"VISTA_DEVICE_MEM_LIMIT": "16"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        s = vista.Stack(_grid(), stream=None)
+        s.add(synth.make_target("tiny", 0))
+        with pytest.raises(vista.VistaError) as e:
+            s.finalize(vista.alloc_outputs(_grid(), device="cpu"))
+        assert e.value.code == vista.VISTA_E_NOMEM
+        with pytest.raises(vista.VistaError) as e:
+            s.add(synth.make_target("tiny", 1))
+        assert e.value.code == vista.VISTA_E_STATE
+        s.close()
+        for k in env:
+            monkeypatch.delenv(k)

@@ -1,0 +1,231 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Indices and counts must be identical; stacked sums within 1e-5 of the oracle (relative to
+the cell scale A = sum |w f V'| for S, and to W for W).  Cases span several tiles and
+rest-channel blocks with ragged edges, the edge layouts of the channel axis, every
+accumulation mode, and the batched form.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2609_01897_amd import vista  # noqa: E402
+from tests.gpu_util import compare, gpu_stack, targets_on_gpu  # noqa: E402
+
+MODES = {"atomic": 0, "deterministic": vista.F_DETERMINISTIC, "kahan": vista.F_KAHAN}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_c1_matches_oracle(mode):
+    """The 8-target correctness workload, every accumulation mode."""
+    cfg = synth.config("c1")
+    hs, ds = targets_on_gpu(cfg)
+    g = synth.make_grid(cfg)
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, ds, flags=MODES[mode])
+    err = compare(o, out, st=st)
+    print(mode, err)
+
+
+def test_debug_indices_bit_exact():
+    """Cell (iu, iv), first rest channel and overlap count per (row, channel)."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    for i in range(2):
+        h = synth.make_target(cfg, i, chan_jitter=0.3)
+        gi = vista.debug_indices(g, h.to("cuda"))
+        oi = oracle.indices(g, h)
+        assert np.array_equal(gi["iu"].astype(np.int64), oi["iu"])
+        assert np.array_equal(gi["iv"].astype(np.int64), oi["iv"])
+        assert np.array_equal(gi["j0"], oi["j0"])
+        assert np.array_equal(gi["nj"], oi["nj"])
+
+
+def test_boundary_samples_bit_exact():
+    """Samples placed exactly on cell edges and one ulp either side of them."""
+    cfg = synth.config("small")
+    g = dict(synth.make_grid(cfg))
+    h = synth.make_target(cfg, 0)
+    a = h.chan_freq / 299792458.0
+    uvw = h.uvw.numpy().copy()
+    k = h.nchan // 2
+    # u_lambda exactly (i + 1/2) du at channel k, and nudged by +-1 ulp in metres
+    for r in range(min(uvw.shape[0], 300)):
+        half = ((r % 40) - 20 + 0.5) * g["du"] / a[k]
+        uvw[r, 0] = np.nextafter(half, np.inf * ((r // 40) % 3 - 1)) if (r // 40) % 3 != 1 else half
+        uvw[r, 1] = -half
+    h.uvw = torch.from_numpy(uvw)
+    gi = vista.debug_indices(g, h.to("cuda"))
+    oi = oracle.indices(g, h)
+    assert np.array_equal(gi["iu"].astype(np.int64), oi["iu"])
+    assert np.array_equal(gi["iv"].astype(np.int64), oi["iv"])
+    o = oracle.stack(g, [h])
+    out, st = gpu_stack(g, [h.to("cuda")])
+    compare(o, out, st=st)
+
+
+def test_zero_offset_rotation_is_identity():
+    h = synth.make_target("small", 1, offset_lm=(0.0, 0.0))
+    d = h.to("cuda")
+    rot = vista.debug_rotate(synth.make_grid("small"), d)
+    assert torch.equal(rot, d.vis)
+
+
+@pytest.mark.parametrize("lm", [(10e-6, -4e-6), (0.01, -0.007)])
+def test_point_source_rotates_to_real_constant(lm):
+    cfg = synth.config("small", gauss_frac=0.0)
+    h = synth.make_target(cfg, 2, noiseless=True, offset_lm=lm, no_flags=True)
+    rot = vista.debug_rotate(synth.make_grid(cfg), h.to("cuda")).cpu().numpy().astype(np.complex128)
+    ref = oracle.rotate(h)
+    big = np.abs(ref) > 1e-3 * cfg.peak
+    err = (np.abs(rot - ref)[big] / np.abs(ref[big]))
+    assert err.max() < 2e-6, err.max()
+
+
+def test_phase_fp32_ablation_loses_cycles():
+    """With the phase argument formed in FP32, large offsets on long baselines decorrelate
+    the rotated point source; the FP64 argument does not."""
+    cfg = synth.config("c3", n_int=6, gauss_frac=0.0)
+    h = synth.make_target(cfg, 0, noiseless=True, offset_lm=(2.9e-4, -2.9e-4), no_flags=True)
+    g = synth.make_grid(cfg)
+    ref = oracle.rotate(h)
+    d = h.to("cuda")
+    big = np.abs(ref) > 1e-2 * cfg.peak
+    e64 = np.abs(vista.debug_rotate(g, d).cpu().numpy() - ref)[big] / np.abs(ref[big])
+    e32 = np.abs(vista.debug_rotate(g, d, flags=vista.F_PHASE_FP32).cpu().numpy() - ref)[big] / np.abs(ref[big])
+    assert e64.max() < 2e-6
+    assert e32.max() > 1e-3
+
+
+@pytest.mark.parametrize("variant", ["descending", "jitter_width", "perchan_badw", "nearest", "odd_small_grid",
+                                     "npol1", "npol4", "no_flags"])
+@pytest.mark.parametrize("mode", ["atomic", "kahan"])
+def test_edge_layouts(variant, mode):
+    cfg = synth.config("small")
+    kw = {}
+    g = synth.make_grid(cfg)
+    if variant == "descending":
+        kw = dict(descending=True)
+    elif variant == "jitter_width":
+        kw = dict(chan_jitter=0.4, with_width=True)
+    elif variant == "perchan_badw":
+        kw = dict(weight_per_chan=True, bad_weight_frac=0.1)
+    elif variant == "nearest":
+        g = synth.make_grid(cfg, vista.F_SPECTRAL_NEAREST)
+    elif variant == "odd_small_grid":
+        g = dict(g, nu=37, nv=29, du=g["du"] * 1.7, nchan=61, freq_lo=g["freq_lo"] + 40 * g["dfreq"])
+    elif variant == "npol1":
+        cfg = synth.config("small", npol=1)
+    elif variant == "npol4":
+        cfg = synth.config("small", npol=4)
+    elif variant == "no_flags":
+        kw = dict(no_flags=True)
+    hs, ds = targets_on_gpu(cfg, **kw)
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, ds, flags=g.get("flags", 0) | MODES[mode])
+    compare(o, out, st=st)
+
+
+def test_empty_and_single_channel_targets():
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    h0 = synth.make_target(cfg, 0)
+    h1 = synth.make_target(cfg, 1, nchan=1, with_width=True)
+    h2 = synth.make_target(cfg, 2, n_int=1)
+    empty = synth.make_target(cfg, 3)
+    empty.uvw = empty.uvw[:0]
+    empty.vis = empty.vis[:0]
+    empty.weight = empty.weight[:0]
+    empty.flag = empty.flag[:0]
+    hs = [h0, empty, h1, h2]
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs])
+    compare(o, out, st=st)
+
+
+def test_no_targets_gives_zero_grid():
+    g = synth.make_grid("small")
+    out, st = gpu_stack(g, [])
+    assert not out["count"].any() and not out["sum_w"].any()
+    assert st["n_samples"] == 0
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 64), (16, 8, 32), (16, 16, 16), (8, 4, 128), (4, 4, 256)])
+def test_every_tile_shape_matches(shape):
+    """The autotuner's candidates change only speed: counts identical, sums in tolerance."""
+    cfg = synth.config("small")
+    hs, ds = targets_on_gpu(cfg)
+    g = synth.make_grid(cfg)
+    o = oracle.stack(g, hs)
+    tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=4)
+    out, st = gpu_stack(g, ds, tuning=tu)
+    compare(o, out, st=st)
+    out, st = gpu_stack(g, ds, flags=vista.F_KAHAN, tuning=tu)
+    compare(o, out, st=st)
+
+
+def test_deterministic_mode_is_bit_identical():
+    cfg = synth.config("small")
+    _, ds = targets_on_gpu(cfg)
+    g = synth.make_grid(cfg)
+    ref, _ = gpu_stack(g, ds, flags=vista.F_DETERMINISTIC)
+    for _ in range(4):
+        out, _ = gpu_stack(g, ds, flags=vista.F_DETERMINISTIC)
+        for k in ("sum_wvis", "sum_w", "count"):
+            assert np.array_equal(out[k].view(np.uint8), ref[k].view(np.uint8))
+
+
+def test_kahan_fp64_outputs():
+    cfg = synth.config("small")
+    hs, ds = targets_on_gpu(cfg)
+    g = synth.make_grid(cfg)
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, ds, flags=vista.F_KAHAN, fp64=True)
+    nz = o["N"] > 0
+    e = np.abs(out["sum_wvis64"] - o["S"])[nz] / o["A"][nz]
+    assert e.max() < 1e-6
+    ew = np.abs(out["sum_w64"] - o["W"])[nz] / o["W"][nz]
+    assert ew.max() < 1e-6
+
+
+def test_host_memory_targets_and_outputs():
+    cfg = synth.config("small")
+    hs = synth.make_targets(cfg)
+    g = synth.make_grid(cfg)
+    o = oracle.stack(g, hs)
+    s = vista.Stack(g)
+    for h in hs:
+        s.add(h)                       # pageable host tensors: copied at add time
+    out = vista.alloc_outputs(g, device="cpu")
+    st = s.finalize(out)
+    s.close()
+    compare(o, {k: v.numpy() for k, v in out.items()}, st=st)
+
+
+def test_batch_equals_plain():
+    """Several stacks with different grids and target counts in one launch."""
+    grids, hs_all = [], []
+    for i, name in enumerate(["small", "tiny", "c1"]):
+        cfg = synth.config(name)
+        grids.append(synth.make_grid(cfg))
+        hs_all.append(synth.make_targets(cfg, n=min(cfg.n_targets, 3 + i)))
+    b = vista.Batch(grids)
+    dev = [[h.to("cuda") for h in hs] for hs in hs_all]
+    for s, ds in enumerate(dev):
+        for d in ds:
+            b.add(s, d)
+    b.run()
+    for s, g in enumerate(grids):
+        out = vista.alloc_outputs(g)
+        st = b.finalize(s, out)
+        o = oracle.stack(g, hs_all[s])
+        compare(o, {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+    b.close()
