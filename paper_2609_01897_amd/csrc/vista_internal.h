@@ -12,15 +12,17 @@ constexpr double kC = 299792458.0;  // speed of light [m/s]
 // One input channel of one target, after host planning.
 //   a    = nu_k / c, so u_lambda = u_m * a (the rest-frame scaling of Eq. 1 cancels:
 //          (u_m / (1+z)) * (nu_k (1+z) / c));
-//   j0   = first rest channel of the overlap set J_k (Eq. 4), nj = |J_k| (0: outside);
-//   foff = offset of the nj overlap fractions f_kj in the target's fraction array.
+//   jn   = j0 | nj << 24: j0 the first rest channel of the overlap set J_k (Eq. 4), nj =
+//          |J_k| (0: outside the band; J_k is the contiguous range [j0, j0 + nj));
+//   f0   = the first overlap fraction f_kj (Eq. 4).  The second is in the target's f1
+//          array, all nj of them at foff[k] in its fval array (read only when nj > 2).
 struct DevChan {
     double a;
-    int32_t j0;
-    int32_t nj;
-    int32_t foff;
-    int32_t pad;
+    uint32_t jn;
+    float f0;
 };
+constexpr uint32_t kJMask = 0xffffffu;
+constexpr int kMaxNj = 255;
 
 // One target as the kernels see it.  Row g of the launch's row space is row
 // g - row_base of the target whose [row_base, row_base + nrow) holds it.
@@ -30,16 +32,19 @@ struct DevTarget {
     const float* weight;      // [nrow][npol] or [nrow][nchan][npol]
     const uint8_t* flag;      // [nrow][nchan][npol] or nullptr
     const DevChan* chan;      // [nchan]
+    const float* f1;          // [nchan] second overlap fraction
+    const int32_t* foff;      // [nchan] offset of channel k's fractions in fval
     const float* fval;        // overlap fractions
-    const int32_t* blk;       // [nblk][2]: k range [lo, hi) of the channels that reach
-                              // rest-channel block b (block size = the launch's jsub)
+    const int32_t* blk;       // [nblocks][2]: k range [lo, hi) of the channels that reach
+                              // rest-channel block b (block size = the launch's jc)
+    const int32_t* sblk;      // the same for sub-blocks of size jsub (ordered mode)
     const int32_t* inband;    // [nchan+1] prefix count of channels with nj > 0
     int64_t row_base;
     int64_t nrow;
     int32_t nchan, npol, weight_per_chan, stack;
     int32_t kin_lo, kin_hi;   // hull of the channels with nj > 0
     int32_t nphase;           // lanes this many channels apart never share a rest channel
-    int32_t pad;
+    int32_t nblocks;          // entries of blk
     double l, m, nm1;         // direction cosines, n - 1
 };
 
@@ -50,6 +55,7 @@ struct DevStack {
     int32_t nblocks;          // rest-channel blocks of size jc
     int32_t target_begin, target_end;
     int64_t tile_base;        // first global tile id of this stack
+    int64_t unit_base;        // first global (tile, block) unit id: unit_base + tile*nblocks + b
     double inv_du, inv_dv;
     float2* out_vis;          // [nchan][nv][nu] or nullptr
     float* out_w;
@@ -69,6 +75,7 @@ struct LaunchDesc {
     const DevStack* stacks;
     const int64_t* target_row_base;   // [ntargets+1]
     const int64_t* stack_tile_base;   // [nstacks+1]
+    const int64_t* stack_unit_base;   // [nstacks+1]
     int32_t ntargets, nstacks;
     int32_t tu, tv, jc, jsub;         // tile, block, ordered sub-block
     int64_t nrows;                    // rows in the launch
@@ -84,27 +91,38 @@ constexpr int kModeOrdered = 1;
 
 // Kernel launchers (vista_kernels.hip).  All enqueue on `stream` and return the first
 // HIP error.
-// Binning pass over every row of the launch: emit == 0 counts the (row, tile) records
-// of each row into seg_count and adds the outside-uv samples to the stacks' stats;
-// emit == 1 writes the records at seg_off.
-hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint64_t* seg_count,
-                        const uint64_t* seg_off, uint32_t* keys, uint64_t* vals, int emit,
+// Binning pass over every row of the launch.  emit == 0 counts the records of each row
+// into seg_count and adds the outside-uv samples to the stacks' stats; emit == 1 writes
+// them at seg_off: key = global (tile, block) unit, value = row << 32 | k_lo << 16 | k_hi,
+// one record per run of channels of one row inside one uv tile and one rest-channel
+// block.
+hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint32_t* seg_count,
+                        const uint32_t* seg_off, uint32_t* keys, uint64_t* vals, int emit,
                         hipStream_t stream);
-hipError_t launch_exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, void* tmp,
-                                     size_t* tmp_bytes, hipStream_t stream);
-hipError_t launch_sort_pairs(const uint32_t* kin, uint32_t* kout, const uint64_t* vin, uint64_t* vout,
-                             int64_t n, int end_bit, void* tmp, size_t* tmp_bytes, hipStream_t stream);
-hipError_t launch_tile_offsets(const uint32_t* sorted_keys, int64_t nrec, int64_t ntiles,
-                               uint32_t* tile_off, uint64_t* tile_cost, const uint64_t* vals,
-                               hipStream_t stream);
-// The accumulation over `nunits` (global tile, rest-channel block) units; the grid is
-// `grid` workgroups of `waves` wavefronts that pull units from *counter (zeroed first).
-hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint2* units,
-                             int64_t nunits, uint32_t* counter, const uint32_t* tile_off,
-                             const uint64_t* recs, int grid, int waves, hipStream_t stream);
+// unit_off[u] = first record of unit u in the sorted keys (u = 0..nunits).
+hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
+                               int64_t nunits, uint32_t* unit_off, hipStream_t stream);
+// The accumulation over the work list `order` (global unit ids); `grid` workgroups of
+// `waves` wavefronts pull list entries from *counter (zeroed first).
+// npol == 2 when every target of the launch has two polarisations (specialised path).
+hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint32_t* order,
+                             int64_t nunits, uint32_t* counter, const uint32_t* unit_off,
+                             const uint64_t* recs, int grid, int waves, int npol, hipStream_t stream);
 int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int npol);
 size_t accum_lds_bytes(int tu, int tv, int jc, int mode, int kahan);
 bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kahan);
+
+// Scan and sort (vista_sort.hip).  Counts are read from device memory when n_dev is not
+// null; `cap` sizes the grid.  No memset, no synchronisation: graph-capturable.
+size_t scan_temp_elems(int64_t cap);
+hipError_t exclusive_scan_u32_to_u32(const uint32_t* in, const int64_t* n_dev, int64_t cap, uint32_t* out,
+                                     uint64_t* sums, hipStream_t s);
+hipError_t exclusive_scan_u64(const uint64_t* in, const int64_t* n_dev, int64_t cap, uint64_t* out,
+                              uint64_t* sums, hipStream_t s);
+size_t radix_sort_temp_bytes(int64_t cap);
+// Stable sort of (keys, vals) by the low `bits` bits of the keys, in place.
+hipError_t radix_sort_pairs(uint32_t* keys, uint64_t* vals, const int64_t* n_dev, int64_t cap, int bits,
+                            void* temp, hipStream_t s);
 hipError_t launch_debug_indices(const DevTarget* t, const DevStack* s, int32_t* iu, int32_t* iv,
                                 int32_t* j0, int32_t* nj, int64_t nrow, int32_t nchan,
                                 hipStream_t stream);

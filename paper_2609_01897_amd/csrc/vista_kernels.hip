@@ -1,21 +1,23 @@
 // gfx950 kernels of the ViSta stacking hot path.
 //
-//   track_count / track_emit  -- binning: each row's channels, walked in frequency
-//       order, trace a radial line in uv (u_lambda = u_m nu/c); the cells along it are
-//       monotone, so the channels that fall in one uv tile form one contiguous range.
-//       Each (row, tile) range becomes one record, keyed by the tile.
-//   sort / tile_offsets       -- stable grouping of the records by tile.
-//   accum                     -- one workgroup owns one (uv tile, rest-channel block) of
-//       the grid state in LDS at a time, streams the tile's records (contiguous channel
-//       runs of one row), applies the Eq. 2 phase shift with the phase argument formed
-//       and range-reduced in FP64, splits every sample over the rest channels with the
-//       Eq. 3-4 fractions, accumulates in LDS, and writes its cells once.
+//   track (count / emit) -- binning: each row's channels, walked in frequency order,
+//       trace a radial line in uv (u_lambda = u_m nu/c); the cells along it are monotone,
+//       so the channels that fall in one uv tile form one contiguous run.  Each run is
+//       cut at the rest-channel block boundaries; every piece becomes one record keyed by
+//       its (tile, block) unit.
+//   sort (vista_sort.hip) / unit offsets -- stable grouping of the records by unit.
+//   accum -- one workgroup owns one (uv tile, rest-channel block) unit of the grid state
+//       in LDS, streams the unit's records (contiguous channel runs of one row), applies
+//       the Eq. 2 phase shift with the phase argument formed and range-reduced in FP64,
+//       splits every sample over the rest channels with the Eq. 3-4 fractions,
+//       accumulates in LDS, and writes its cells once.
 //
 // Cell and channel indices follow the FP64 operation sequence of the definition exactly
 // (this file is compiled with -ffp-contract=off, no fast-math): u = u_m * a_k,
 // iu = rint(u * (1/du)) + nu/2.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+
+#include <type_traits>
 
 #include "vista_internal.h"
 
@@ -109,8 +111,8 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 // ----------------------------------------------------------------------------- binning
 
 __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp,
-                                               uint64_t* __restrict__ seg_count,
-                                               const uint64_t* __restrict__ seg_off,
+                                               uint32_t* __restrict__ seg_count,
+                                               const uint32_t* __restrict__ seg_off,
                                                uint32_t* __restrict__ keys,
                                                uint64_t* __restrict__ vals, int emit) {
     const LaunchDesc& L = *Lp;
@@ -123,24 +125,29 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
         const DevStack& S = L.stacks[T.stack];
         stack_id = T.stack;
         int64_t r = g - T.row_base;
-        uint64_t n = 0;
+        uint32_t n = 0;
         if (T.kin_lo < T.kin_hi) {
             double U = T.uvw[3 * r], V = T.uvw[3 * r + 1];
             Track tr = in_grid(T.chan, T.kin_lo, T.kin_hi, U, V, S.inv_du, S.inv_dv, S.nu, S.nv);
             int32_t inb_all = T.inband[T.kin_hi] - T.inband[T.kin_lo];
             int32_t inb_in = T.inband[tr.gb] - T.inband[tr.ga];
             outside = (unsigned long long)(inb_all - inb_in) * (unsigned long long)T.npol;
-            uint64_t base = emit ? seg_off[g] : 0;
+            uint32_t base = emit ? seg_off[g] : 0;
             int32_t k = tr.ga;
             while (k < tr.gb) {
                 int32_t tu, tv;
                 int32_t k1 = tile_run_end(T.chan, k, tr.gb, U, V, S.inv_du, S.inv_dv, S.nu, S.nv, L.tu,
                                           L.tv, tr, &tu, &tv);
-                if (emit) {
-                    keys[base + n] = (uint32_t)(S.tile_base + (int64_t)tv * S.tiles_u + tu);
-                    vals[base + n] = ((uint64_t)g << 32) | ((uint64_t)k << 16) | (uint64_t)k1;
+                int64_t unit0 = S.unit_base + ((int64_t)tv * S.tiles_u + tu) * S.nblocks;
+                for (int32_t b = 0; b < T.nblocks; ++b) {
+                    int32_t lo = max(k, T.blk[2 * b]), hi = min(k1, T.blk[2 * b + 1]);
+                    if (lo >= hi) continue;
+                    if (emit) {
+                        keys[base + n] = (uint32_t)(unit0 + b);
+                        vals[base + n] = ((uint64_t)g << 32) | ((uint64_t)lo << 16) | (uint64_t)hi;
+                    }
+                    ++n;
                 }
-                ++n;
                 k = k1;
             }
         }
@@ -157,18 +164,15 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
     }
 }
 
-__global__ void k_tile_offsets(const uint32_t* __restrict__ keys, int64_t nrec, int64_t ntiles,
-                               uint32_t* __restrict__ off, uint64_t* __restrict__ cost,
-                               const uint64_t* __restrict__ vals) {
+// unit_off[u] = index of the first record of unit u (records sorted by unit).
+__global__ void k_unit_offsets(const uint32_t* __restrict__ keys, const int64_t* __restrict__ nrec_dev,
+                               int64_t nrec_cap, int64_t nunits, uint32_t* __restrict__ off) {
+    int64_t nrec = nrec_dev ? *nrec_dev : nrec_cap;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > nrec) return;
     int64_t prev = (i == 0) ? -1 : (int64_t)keys[i - 1];
-    int64_t cur = (i == nrec) ? ntiles : (int64_t)keys[i];
-    for (int64_t t = prev + 1; t <= cur && t <= ntiles; ++t) off[t] = (uint32_t)i;
-    if (i < nrec && cost) {
-        uint64_t v = vals[i];
-        atomicAdd((unsigned long long*)&cost[cur], (unsigned long long)((v & 0xffff) - ((v >> 16) & 0xffff)));
-    }
+    int64_t cur = (i == nrec) ? nunits : (int64_t)keys[i];
+    for (int64_t t = prev + 1; t <= cur && t <= nunits; ++t) off[t] = (uint32_t)i;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -183,242 +187,493 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 
 // ------------------------------------------------------------------------ accumulation
 
-// Phase of one channel: the Eq. 2 turns t = (u l + v m + w (n-1)) = trow * a, reduced
-// to [-1/2, 1/2] in FP64, then sin/cos of 2 pi r in FP32.
+// (The host compilation pass only parses device code; address spaces exist on the device.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define VISTA_GLOBAL __attribute__((address_space(1)))
+#define VISTA_CONST __attribute__((address_space(4)))
+#else
+#define VISTA_GLOBAL
+#define VISTA_CONST
+#endif
+
+// Pointers read from descriptors are generic; casting them to the global address space
+// lets the compiler use global (not flat) memory instructions.
+template <class T>
+__device__ __forceinline__ const VISTA_GLOBAL T* gptr(const T* p) {
+    return (const VISTA_GLOBAL T*)p;
+}
+// Read-only data addressed uniformly across the wave (descriptors, a row's uvw and
+// weights): the constant address space lets the compiler use scalar loads.
+template <class T>
+__device__ __forceinline__ const VISTA_CONST T* cptr(const T* p) {
+    return (const VISTA_CONST T*)p;
+}
+
+__device__ __forceinline__ int32_t sgpr(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int j) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// sin and cos of 2 pi x for x in [-1/2, 1/2] (an already range-reduced phase in turns).
+// x is split into quarter turns q and a remainder f in [-1/2, 1/2] (both exact), the
+// sine and cosine of pi f / 2 come from polynomials in f fitted by least squares on
+// Chebyshev nodes of [-1/2, 1/2] (max error about 8e-8 in FP32), and the quadrant is
+// applied by swapping and negating.
+__device__ __forceinline__ void sincos_turns(float x, float* sn, float* cs) {
+    float y = 4.0f * x;
+    float q = rintf(y);
+    float f = y - q;
+    float f2 = f * f;
+    float s = f * fmaf(f2, fmaf(f2, fmaf(f2, -4.583587870001793e-3f, 7.96719342470169e-2f), -6.459624171257019e-1f),
+                       1.570796251296997f);
+    float c = fmaf(f2, fmaf(f2, fmaf(f2, fmaf(f2, 9.021605364978313e-4f, -2.085929550230503e-2f),
+                                     2.536690831184387e-1f), -1.2337005138397217f), 1.0f);
+    int qi = (int)q & 3;
+    float a = (qi & 1) ? c : s;
+    float b = (qi & 1) ? s : c;
+    *sn = (qi & 2) ? -a : a;
+    *cs = ((qi + 1) & 2) ? -b : b;
+}
+
+// Phase of one channel: the Eq. 2 turns t = (u l + v m + w (n-1)) = trow * a_k formed and
+// reduced to [-1/2, 1/2] in FP64; sin/cos of 2 pi r in FP32.
 __device__ __forceinline__ void phasor(double trow, double a, float* c, float* s) {
     double t = trow * a;
     double r = t - rint(t);
-    float x = (float)r;
-    sincospif(2.0f * x, s, c);
+    sincos_turns((float)r, s, c);
 }
 
+// Ablation: turns formed from FP32 coordinates and reduced in FP32, so large arguments
+// lose their fractional part to FP32 rounding.
 __device__ __forceinline__ void phasor_fp32(float u, float v, float w, float l, float m, float nm1,
                                             float* c, float* s) {
     float t = u * l + v * m + w * nm1;
-    sincosf(6.2831853071795864769f * t, s, c);
+    sincos_turns(t - rintf(t), s, c);
 }
 
-struct Sample {
-    float pr, pi, q;    // sum_p w_p V'_p (rotated), sum_p w_p
-    uint32_t n;         // used polarisations
-    uint32_t nflag, nbad;
-    int32_t lu, lv;     // cell within the tile
-    int32_t j0, nj, foff;
-};
-
-// Load, rotate and merge the polarisations of channel k of row r.
-__device__ __forceinline__ void load_sample(const DevTarget& T, int64_t r, int32_t k, double U, double V,
-                                            double Wm, double trow, double inv_du, double inv_dv,
-                                            int32_t nu, int32_t nv, int32_t tu0, int32_t tv0,
-                                            const float* wrow, int phase_fp32, Sample& sm) {
-    DevChan ce = T.chan[k];
-    sm.j0 = ce.j0;
-    sm.nj = ce.nj;
-    sm.foff = ce.foff;
-    double ru = cell_coord(U, ce.a, inv_du), rv = cell_coord(V, ce.a, inv_dv);
-    sm.lu = (int32_t)ru + nu / 2 - tu0;
-    sm.lv = (int32_t)rv + nv / 2 - tv0;
-    const int npol = T.npol;
-    size_t e = ((size_t)r * T.nchan + k) * npol;
-    float vr[4], vi[4], wt[4];
-    uint32_t fl = 0;
-    if (npol == 2) {
-        float4 x = *(const float4*)(T.vis + e);
-        vr[0] = x.x; vi[0] = x.y; vr[1] = x.z; vi[1] = x.w;
-        if (T.flag) fl = *(const uint16_t*)(T.flag + e);
-    } else if (npol == 1) {
-        float2 x = T.vis[e];
-        vr[0] = x.x; vi[0] = x.y;
-        if (T.flag) fl = T.flag[e];
-    } else {
-        float4 x = *(const float4*)(T.vis + e);
-        float4 y = *(const float4*)(T.vis + e + 2);
-        vr[0] = x.x; vi[0] = x.y; vr[1] = x.z; vi[1] = x.w;
-        vr[2] = y.x; vi[2] = y.y; vr[3] = y.z; vi[3] = y.w;
-        if (T.flag) fl = *(const uint32_t*)(T.flag + e);
-    }
-    if (T.weight_per_chan) {
-        for (int p = 0; p < npol; ++p) wt[p] = T.weight[e + p];
-    } else {
-        for (int p = 0; p < npol; ++p) wt[p] = wrow[p];
-    }
-    float ar = 0.f, ai = 0.f, q = 0.f;
-    uint32_t n = 0, nflag = 0, nbad = 0;
-    for (int p = 0; p < npol; ++p) {
-        bool flagged = ((fl >> (8 * p)) & 0xffu) != 0u;
-        float w = wt[p];
-        bool good = (w > 0.0f) && (w < __builtin_inff());
-        if (flagged) { ++nflag; continue; }
-        if (!good) { ++nbad; continue; }
-        ar = fmaf(w, vr[p], ar);
-        ai = fmaf(w, vi[p], ai);
-        q += w;
-        ++n;
-    }
-    float c, s;
-    if (phase_fp32) {
-        float a32 = (float)ce.a;
-        phasor_fp32((float)U * a32, (float)V * a32, (float)Wm * a32, (float)T.l, (float)T.m, (float)T.nm1,
-                    &c, &s);
-    } else {
-        phasor(trow, ce.a, &c, &s);
-    }
-    sm.pr = ar * c - ai * s;
-    sm.pi = fmaf(ar, s, ai * c);
-    sm.q = q;
-    sm.n = n;
-    sm.nflag = nflag;
-    sm.nbad = nbad;
-}
-
+// LDS grid state of one unit: per cell sum(w f V') re/im, sum(w f) and the count.  The
+// sums are FP64 (LDS has native FP64 atomic adds, far faster than its FP32 ones on
+// gfx950), or, for the compensated mode, FP32 values with FP32 compensations.
 template <int TU, int TV, int JC, int MODE, bool KAHAN>
 struct AccumShape {
     static constexpr int JP = JC + 1;                 // padded channel stride
     static constexpr int NC = TU * TV * JP;           // LDS cells
-    static constexpr int NARR = KAHAN ? 7 : 4;
-    static constexpr size_t LDS = (size_t)NC * NARR * 4;
+    static constexpr size_t LDS = (size_t)NC * 28;
 };
 
-template <int TU, int TV, int JC, int MODE, bool KAHAN>
-__global__ void __launch_bounds__(512) k_accum(const LaunchDesc* __restrict__ Lp,
-                                               const uint2* __restrict__ units, int64_t nunits,
-                                               uint32_t* __restrict__ counter,
-                                               const uint32_t* __restrict__ tile_off,
-                                               const uint64_t* __restrict__ recs) {
+// Element i of a buffer-load result as float.  Elements are first copied to integers:
+// bit-casting a vector element expression directly has been seen to read element 0.
+template <class V>
+__device__ __forceinline__ float fel(const V& v, int i) {
+    const uint32_t x = (uint32_t)v[i];
+    return __builtin_bit_cast(float, x);
+}
+
+// Raw buffer resource over [base, base + bytes): per-lane 32-bit offsets, uniform base in
+// scalar registers, and reads past the end return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Wave-uniform description of one work item: up to 64 consecutive channels [k0, k1) of one
+// row of one target.  Kept small: three of these live in scalar registers at once.
+struct Item {
+    int32_t ti;                    // target
+    int32_t k0, k1;                // channels of this item
+    int32_t r;                     // row within the target
+    double U, V, trow;             // row u, v [m] and Eq. 2 turns per unit a_k
+    float w[2];                    // row weights of the first two polarisations
+};
+
+__device__ __forceinline__ uint32_t ufl(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t ufl(uint64_t x) {
+    return ((uint64_t)ufl((uint32_t)(x >> 32)) << 32) | ufl((uint32_t)x);
+}
+__device__ __forceinline__ double ufl(double x) { return __builtin_bit_cast(double, ufl(__builtin_bit_cast(uint64_t, x))); }
+__device__ __forceinline__ float ufl(float x) { return __builtin_bit_cast(float, ufl(__builtin_bit_cast(uint32_t, x))); }
+
+// The item with every field read from the first lane: the values are wave-uniform, so
+// they stay in scalar registers and buffer resources built from them need no loops.
+__device__ __forceinline__ Item uniform(const Item& a) {
+    Item u;
+    u.ti = (int32_t)ufl((uint32_t)a.ti);
+    u.k0 = (int32_t)ufl((uint32_t)a.k0);
+    u.k1 = (int32_t)ufl((uint32_t)a.k1);
+    u.r = (int32_t)ufl((uint32_t)a.r);
+    u.U = ufl(a.U); u.V = ufl(a.V); u.trow = ufl(a.trow);
+    u.w[0] = ufl(a.w[0]); u.w[1] = ufl(a.w[1]);
+    return u;
+}
+
+// Per-lane data of an item, loaded one item ahead of its use.
+template <int NPOL>
+struct LaneLoad {
+    double a;
+    uint32_t jn;
+    float f0, f1;
+    float vr[NPOL > 0 ? NPOL : 4], vi[NPOL > 0 ? NPOL : 4];
+    uint32_t fl;
+    float wc[NPOL > 0 ? 1 : 4];    // per-channel weights (generic path only)
+};
+
+template <int NPOL>
+__device__ __forceinline__ void issue_loads(const VISTA_CONST DevTarget* tgts, const Item& itv, int lane,
+                                            LaneLoad<NPOL>& ld) {
+    const Item it = uniform(itv);
+    const VISTA_CONST DevTarget& T = tgts[it.ti];
+    const int npol = NPOL > 0 ? NPOL : T.npol;
+    const uint32_t nch = ufl((uint32_t)T.nchan);
+    const __amdgpu_buffer_rsrc_t ch = buf((const void*)ufl((uint64_t)T.chan), nch * (uint32_t)sizeof(DevChan));
+    const __amdgpu_buffer_rsrc_t f1 = buf((const void*)ufl((uint64_t)T.f1), nch * 4u);
+    // the row's visibilities, flags and per-channel weights
+    const uint32_t rowe = nch * (uint32_t)npol;                   // samples per row
+    const size_t re0 = (size_t)it.r * rowe;
+    const __amdgpu_buffer_rsrc_t visr = buf((const char*)ufl((uint64_t)T.vis) + re0 * 8, rowe * 8u);
+    const uint64_t fbase = ufl((uint64_t)T.flag);
+    const __amdgpu_buffer_rsrc_t flagr = buf(fbase ? (const void*)((const char*)fbase + re0) : (const void*)T.vis,
+                                             fbase ? rowe : 0u);
+    const int has_flag = fbase != 0;
+    const __amdgpu_buffer_rsrc_t wchr = buf((const char*)ufl((uint64_t)T.weight) + re0 * 4,
+                                            T.weight_per_chan ? rowe * 4u : 0u);
+    // whole offsets in the lane offset: the hardware range check covers exactly that part
+    const int kl = it.k0 + lane;
+    auto c = __builtin_amdgcn_raw_buffer_load_b128(ch, kl * 16, 0, 0);
+    const uint32_t c0 = (uint32_t)c[0], c1 = (uint32_t)c[1], c2 = (uint32_t)c[2];
+    ld.a = __builtin_bit_cast(double, ((uint64_t)c1 << 32) | c0);
+    ld.jn = c2;
+    ld.f0 = fel(c, 3);
+    const uint32_t f1w = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(f1, kl * 4, 0, 0);
+    ld.f1 = __builtin_bit_cast(float, f1w);
+    if (NPOL == 0) {
+        // polarisation slots beyond npol take part in the merge with weight 0: keep them 0
+        for (int p = 0; p < 4; ++p) { ld.vr[p] = 0.f; ld.vi[p] = 0.f; }
+    }
+    if (npol == 2) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(visr, kl * 16, 0, 0);
+        ld.vr[0] = fel(v, 0); ld.vi[0] = fel(v, 1);
+        ld.vr[1] = fel(v, 2); ld.vi[1] = fel(v, 3);
+        ld.fl = has_flag ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(flagr, kl * 2, 0, 0) : 0u;
+    } else if (npol == 1) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(visr, kl * 8, 0, 0);
+        ld.vr[0] = fel(v, 0); ld.vi[0] = fel(v, 1);
+        ld.fl = has_flag ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(flagr, kl, 0, 0) : 0u;
+    } else {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(visr, kl * 32, 0, 0);
+        auto u = __builtin_amdgcn_raw_buffer_load_b128(visr, kl * 32 + 16, 0, 0);
+        ld.vr[0] = fel(v, 0); ld.vi[0] = fel(v, 1);
+        ld.vr[1] = fel(v, 2); ld.vi[1] = fel(v, 3);
+        if (NPOL != 2 && NPOL != 1) {
+            ld.vr[2] = fel(u, 0); ld.vi[2] = fel(u, 1);
+            ld.vr[3] = fel(u, 2); ld.vi[3] = fel(u, 3);
+        }
+        ld.fl = has_flag ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(flagr, kl * 4, 0, 0) : 0u;
+    }
+    if (NPOL == 0 && T.weight_per_chan) {
+        for (int p = 0; p < 4; ++p)
+            if (p < npol) {
+                const uint32_t x = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(wchr, (kl * npol + p) * 4, 0, 0);
+                ld.wc[p] = __builtin_bit_cast(float, x);
+            } else {
+                ld.wc[p] = 0.f;
+            }
+    }
+}
+
+// Accumulation of one (uv tile, rest-channel block) unit per workgroup iteration.
+//   MODE == kModeAtomic : waves take the unit's records round-robin and add into the
+//                         shared LDS cells with LDS float atomics.
+//   MODE == kModeOrdered: every wave walks all records in order but only adds into its
+//                         own slice of rest channels, so each cell has one writer; lanes
+//                         that could share a cell add in separate phases.  The order of
+//                         every addition is fixed: results are bit-identical from run to
+//                         run, and KAHAN compensates each addition.
+// NPOL == 2 is the path specialised for two polarisations and row weights; NPOL == 0
+// handles any polarisation count and per-channel weights.
+template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
+__global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict__ Lp,
+                                                   const uint32_t* __restrict__ order, int64_t nunits,
+                                                   uint32_t* __restrict__ counter,
+                                                   const uint32_t* __restrict__ unit_off,
+                                                   const uint64_t* __restrict__ recs) {
     using Sh = AccumShape<TU, TV, JC, MODE, KAHAN>;
     constexpr int JP = Sh::JP;
     constexpr int NC = Sh::NC;
-    __shared__ float s_re[NC], s_im[NC], s_w[NC];
+    using Acc = typename std::conditional<KAHAN, float, double>::type;
+    __shared__ Acc s_re[NC], s_im[NC], s_w[NC];
     __shared__ uint32_t s_n[NC];
     __shared__ float c_re[KAHAN ? NC : 1], c_im[KAHAN ? NC : 1], c_w[KAHAN ? NC : 1];
     __shared__ uint32_t s_unit;
 
     const LaunchDesc& L = *Lp;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    const int wave = sgpr(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    const VISTA_GLOBAL uint64_t* grecs = gptr(recs);
+    const VISTA_CONST DevTarget* tgts = cptr(L.targets);
+    const VISTA_CONST int64_t* trb = cptr(L.target_row_base);
+    const int phase_fp32 = L.phase_fp32;
 
     for (;;) {
         if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
         __syncthreads();
-        uint32_t ui = s_unit;
-        if (ui >= nunits) break;
-        uint2 un = units[ui];
-        int64_t gtile = un.x;
-        int32_t b = (int32_t)un.y;
-        int32_t si = (int32_t)find_le(L.stack_tile_base, L.nstacks, gtile);
+        const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
+        if (li >= nunits) break;
+        const int64_t unit = (uint32_t)sgpr((int32_t)gptr(order)[li]);
+        const int32_t si = sgpr((int32_t)find_le(L.stack_unit_base, L.nstacks, unit));
         const DevStack& S = L.stacks[si];
-        int64_t tile = gtile - S.tile_base;
-        int32_t tu0 = (int32_t)(tile % S.tiles_u) * TU;
-        int32_t tv0 = (int32_t)(tile / S.tiles_u) * TV;
-        int32_t jb0 = b * JC;
-        int32_t jb1 = min(jb0 + JC, S.nchan);
+        const int64_t local = unit - S.unit_base;
+        const int64_t tile = local / S.nblocks;
+        const int32_t b = (int32_t)(local - tile * S.nblocks);
+        const int32_t tu0 = (int32_t)(tile % S.tiles_u) * TU;
+        const int32_t tv0 = (int32_t)(tile / S.tiles_u) * TV;
+        const int32_t jb0 = b * JC;
+        const int32_t jb1 = min(jb0 + JC, S.nchan);
+        const int32_t cu = S.nu / 2 - tu0, cv = S.nv / 2 - tv0;
+        const double inv_du = S.inv_du, inv_dv = S.inv_dv;
 
         for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-            s_re[i] = 0.f; s_im[i] = 0.f; s_w[i] = 0.f; s_n[i] = 0u;
+            s_re[i] = 0; s_im[i] = 0; s_w[i] = 0; s_n[i] = 0u;
             if (KAHAN) { c_re[i] = 0.f; c_im[i] = 0.f; c_w[i] = 0.f; }
         }
         __syncthreads();
 
-        uint32_t rb = tile_off[gtile], re = tile_off[gtile + 1];
-        // channel sub-range this wave adds into: the whole block (atomic mode) or the
-        // wave's own slice of it (ordered mode: cells are never shared between waves)
-        int32_t js0, js1, bi;
+        const uint32_t rb = (uint32_t)sgpr((int32_t)gptr(unit_off)[unit]);
+        const uint32_t re = (uint32_t)sgpr((int32_t)gptr(unit_off)[unit + 1]);
+        int32_t js0, js1, sbi;
         uint32_t r_first, r_step;
         if (MODE == kModeOrdered) {
-            int32_t jsub = L.jsub;
+            const int32_t jsub = L.jsub;
             js0 = jb0 + wave * jsub;
             js1 = min(js0 + jsub, jb1);
-            bi = jb0 / jsub + wave;
+            sbi = jb0 / jsub + wave;
             r_first = rb;
             r_step = 1;
         } else {
             js0 = jb0;
             js1 = jb1;
-            bi = b;
+            sbi = b;
             r_first = rb + wave;
             r_step = nw;
         }
-        unsigned long long st_flag = 0, st_bad = 0, st_used = 0, st_contrib = 0;
-        if (js0 < js1) {
-            for (uint32_t ri = r_first; ri < re; ri += r_step) {
-                uint64_t rec = recs[ri];
-                int64_t g = (int64_t)(rec >> 32);
+        uint32_t st_flag = 0, st_bad = 0, st_used = 0;
+        unsigned long long st_contrib = 0;
+
+        // ---- the wave's work items: its records, cut into 64-channel pieces.  Records
+        // come 64 at a time, one per lane, together with their rows' context (target,
+        // row, u, v, Eq. 2 turns per unit a_k, weights), so no record waits on memory.
+        const uint32_t nrec_w = (js0 < js1 && re > r_first) ? (re - r_first + r_step - 1) / r_step : 0;
+        uint32_t ri = 0;                  // next record of this wave
+        uint64_t rec_l = 0;               // this lane's record of the current batch
+        int32_t ti_l = 0, r_l = 0;
+        double U_l = 0.0, V_l = 0.0, T_l = 0.0;
+        float w0_l = 0.f, w1_l = 0.f;
+        int32_t kc = 0, kend = 0;         // rest of the current record
+        Item row;
+
+        auto load_batch = [&]() __attribute__((always_inline)) {
+            const uint32_t my = r_first + (ri + lane) * r_step;
+            const bool valid = my < re;
+            rec_l = valid ? grecs[my] : 0ull;
+            const int64_t g = (int64_t)(rec_l >> 32);
+            const VISTA_GLOBAL int64_t* rbase = gptr(L.target_row_base);
+            int32_t lo = 0, hi = L.ntargets;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (rbase[mid] <= g) lo = mid; else hi = mid;
+            }
+            ti_l = lo;
+            const VISTA_GLOBAL DevTarget* Tl = gptr(L.targets) + lo;
+            const int64_t r = valid ? g - rbase[lo] : 0;
+            r_l = (int32_t)r;
+            if (valid) {
+                const VISTA_GLOBAL double* uvw = gptr(Tl->uvw) + 3 * r;
+                U_l = uvw[0];
+                V_l = uvw[1];
+                const double Wm = uvw[2];
+                T_l = phase_fp32 ? Wm : U_l * Tl->l + V_l * Tl->m + Wm * Tl->nm1;
+                const int np = Tl->npol;
+                const VISTA_GLOBAL float* wp = gptr(Tl->weight) + (size_t)r * np;
+                const bool rw = !Tl->weight_per_chan;
+                w0_l = rw ? wp[0] : 0.f;
+                w1_l = (rw && np > 1) ? wp[1] : 0.f;
+            }
+        };
+
+        // advance to the next item; false when the wave has no more work
+        auto next_item = [&](Item& nx) __attribute__((always_inline)) -> bool {
+            while (kc >= kend) {
+                if (ri >= nrec_w) return false;
+                const int jl = (int)(ri & (kWave - 1));
+                if (jl == 0) load_batch();
+                ++ri;
+                const uint64_t rec = readlane_u64(rec_l, jl);
                 int32_t kin = (int32_t)((rec >> 16) & 0xffff), kout = (int32_t)(rec & 0xffff);
-                int32_t ti = (int32_t)find_le(L.target_row_base, L.ntargets, g);
-                const DevTarget& T = L.targets[ti];
-                int32_t ka = max(kin, T.blk[2 * bi]), kb = min(kout, T.blk[2 * bi + 1]);
-                if (ka >= kb) continue;
-                int64_t r = g - T.row_base;
-                double U = T.uvw[3 * r], V = T.uvw[3 * r + 1], Wm = T.uvw[3 * r + 2];
-                double trow = U * T.l + V * T.m + Wm * T.nm1;
-                float wrow[4] = {0.f, 0.f, 0.f, 0.f};
-                if (!T.weight_per_chan)
-                    for (int p = 0; p < T.npol; ++p) wrow[p] = T.weight[(size_t)r * T.npol + p];
-                const int nph = (MODE == kModeOrdered) ? T.nphase : 1;
-                for (int32_t k0 = ka; k0 < kb; k0 += kWave) {
-                    int32_t k = k0 + lane;
-                    bool act = k < kb;
-                    Sample sm;
-                    sm.nj = 0;
-                    sm.n = 0;
-                    if (act) {
-                        load_sample(T, r, k, U, V, Wm, trow, S.inv_du, S.inv_dv, S.nu, S.nv, tu0, tv0, wrow,
-                                    L.phase_fp32, sm);
-                        // a record's channels all lie in this tile; anything else is a bug
-                        if (sm.lu < 0 || sm.lu >= TU || sm.lv < 0 || sm.lv >= TV) { sm.nj = 0; sm.n = 0; }
-                        // per-sample classification is counted in the block of j0
-                        if (sm.nj > 0 && sm.j0 >= js0 && sm.j0 < js1) {
-                            st_flag += sm.nflag;
-                            st_bad += sm.nbad;
-                            st_used += sm.n;
-                        }
+                const int32_t ti = __builtin_amdgcn_readlane(ti_l, jl);
+                if (MODE == kModeOrdered) {
+                    const VISTA_CONST DevTarget& T = tgts[ti];
+                    kin = max(kin, cptr(T.sblk)[2 * sbi]);
+                    kout = min(kout, cptr(T.sblk)[2 * sbi + 1]);
+                }
+                if (kin >= kout) continue;
+                kc = kin;
+                kend = kout;
+                row.ti = ti;
+                row.r = __builtin_amdgcn_readlane(r_l, jl);
+                row.U = __builtin_bit_cast(double, readlane_u64(__builtin_bit_cast(uint64_t, U_l), jl));
+                row.V = __builtin_bit_cast(double, readlane_u64(__builtin_bit_cast(uint64_t, V_l), jl));
+                row.trow = __builtin_bit_cast(double, readlane_u64(__builtin_bit_cast(uint64_t, T_l), jl));
+                row.w[0] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, w0_l), jl));
+                row.w[1] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, w1_l), jl));
+            }
+            nx = row;
+            nx.k0 = kc;
+            nx.k1 = min(kc + kWave, kend);
+            kc += kWave;
+            return true;
+        };
+
+        // ---- one item: cell, polarisation merge, rotation, rest-channel split
+        auto process = [&](const Item& itv, const LaneLoad<NPOL>& ld) __attribute__((always_inline)) {
+            const Item it = uniform(itv);
+            const VISTA_CONST DevTarget& T = tgts[it.ti];
+            const int npol = NPOL > 0 ? NPOL : T.npol;
+            const uint32_t nj = ld.jn >> 24;
+            const int32_t j0 = (int32_t)(ld.jn & kJMask);
+            const bool act = (it.k0 + lane < it.k1) && nj > 0;     // idle lanes add nothing
+            // cell within the tile (exact FP64 sequence of the definition)
+            const double ru = cell_coord(it.U, ld.a, inv_du);
+            const double rv = cell_coord(it.V, ld.a, inv_dv);
+            const int32_t lu = (int32_t)ru + cu, lv = (int32_t)rv + cv;
+            const bool in_tile = act && (uint32_t)lu < (uint32_t)TU && (uint32_t)lv < (uint32_t)TV;
+            // polarisations: drop flagged and bad-weight samples, merge the rest
+            float ar = 0.f, ai = 0.f, q = 0.f;
+            uint32_t n = 0, nflag = 0, nbad = 0;
+#pragma unroll
+            for (int p = 0; p < (NPOL > 0 ? NPOL : 4); ++p) {
+                const bool live = p < npol;
+                float w;
+                if (NPOL == 0 && T.weight_per_chan) w = ld.wc[NPOL > 0 ? 0 : p];
+                else if (p < 2) w = it.w[p];
+                else w = live ? cptr(T.weight)[(size_t)it.r * npol + (p < npol ? p : 0)] : 0.f;
+                const bool flagged = live && ((ld.fl >> (8 * p)) & 0xffu) != 0u;
+                const bool good = live && (w > 0.0f) && (w < __builtin_inff());
+                nflag += flagged ? 1u : 0u;
+                nbad += (live && !flagged && !good) ? 1u : 0u;
+                const bool use = !flagged && good;
+                const float wu = use ? w : 0.0f;
+                n += use ? 1u : 0u;
+                ar = fmaf(wu, ld.vr[p], ar);
+                ai = fmaf(wu, ld.vi[p], ai);
+                q += wu;
+            }
+            float c, s;
+            if (phase_fp32) {
+                const float a32 = (float)ld.a;
+                phasor_fp32((float)it.U * a32, (float)it.V * a32, (float)it.trow * a32, (float)T.l, (float)T.m,
+                            (float)T.nm1, &c, &s);
+            } else {
+                phasor(it.trow, ld.a, &c, &s);
+            }
+            const float pr = ar * c - ai * s;
+            const float pi = fmaf(ar, s, ai * c);
+            // classification is counted once, in the block holding j0
+            if (in_tile && j0 >= js0 && j0 < js1) {
+                st_flag += nflag;
+                st_bad += nbad;
+                st_used += n;
+            }
+            const bool add = in_tile && n > 0;
+            const int cell = (lv * TU + lu) * JP - jb0;
+            const int nph = (MODE == kModeOrdered) ? T.nphase : 1;
+            for (int ph = 0; ph < nph; ++ph) {
+                const bool mine = add && (MODE != kModeOrdered || (lane % nph) == ph);
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                    const int32_t j = j0 + qq;
+                    if (!(mine && qq < (int)nj && j >= js0 && j < js1)) continue;
+                    const float f = qq == 0 ? ld.f0 : ld.f1;
+                    const int cc = cell + j;
+                    const float xr = f * pr, xi = f * pi, xw = f * q;
+                    st_contrib += n;
+                    if (MODE == kModeAtomic) {
+                        atomicAdd(&s_re[cc], (double)f * (double)pr);   // exact products
+                        atomicAdd(&s_im[cc], (double)f * (double)pi);
+                        atomicAdd(&s_w[cc], (double)f * (double)q);
+                        atomicAdd(&s_n[cc], n);
+                    } else if (!KAHAN) {
+                        s_re[cc] += (double)f * (double)pr;
+                        s_im[cc] += (double)f * (double)pi;
+                        s_w[cc] += (double)f * (double)q;
+                        s_n[cc] += n;
+                    } else {
+                        float y, t;
+                        y = xr - c_re[cc]; t = s_re[cc] + y; c_re[cc] = (t - s_re[cc]) - y; s_re[cc] = t;
+                        y = xi - c_im[cc]; t = s_im[cc] + y; c_im[cc] = (t - s_im[cc]) - y; s_im[cc] = t;
+                        y = xw - c_w[cc]; t = s_w[cc] + y; c_w[cc] = (t - s_w[cc]) - y; s_w[cc] = t;
+                        s_n[cc] += n;
                     }
-                    int32_t cell = (sm.lv * TU + sm.lu) * JP;
-                    for (int ph = 0; ph < nph; ++ph) {
-                        bool mine = act && sm.n > 0 && (MODE != kModeOrdered || ((k - k0) % nph) == ph);
-                        if (mine) {
-                            for (int q = 0; q < sm.nj; ++q) {
-                                int32_t j = sm.j0 + q;
-                                if (j < js0 || j >= js1) continue;
-                                float f = T.fval[sm.foff + q];
-                                int c = cell + (j - jb0);
-                                float xr = f * sm.pr, xi = f * sm.pi, xw = f * sm.q;
-                                st_contrib += sm.n;
-                                if (MODE == kModeAtomic) {
-                                    atomicAdd(&s_re[c], xr);
-                                    atomicAdd(&s_im[c], xi);
-                                    atomicAdd(&s_w[c], xw);
-                                    atomicAdd(&s_n[c], sm.n);
-                                } else if (!KAHAN) {
-                                    s_re[c] += xr;
-                                    s_im[c] += xi;
-                                    s_w[c] += xw;
-                                    s_n[c] += sm.n;
-                                } else {
-                                    float y, t;
-                                    y = xr - c_re[c]; t = s_re[c] + y; c_re[c] = (t - s_re[c]) - y; s_re[c] = t;
-                                    y = xi - c_im[c]; t = s_im[c] + y; c_im[c] = (t - s_im[c]) - y; s_im[c] = t;
-                                    y = xw - c_w[c]; t = s_w[c] + y; c_w[c] = (t - s_w[c]) - y; s_w[c] = t;
-                                    s_n[c] += sm.n;
-                                }
-                            }
+                }
+                // more than two rest channels (rest grid finer than the channel): rare
+                if (mine && nj > 2) {
+                    const int32_t fo = gptr(T.foff)[it.k0 + lane];
+                    for (int qq = 2; qq < (int)nj; ++qq) {
+                        const int32_t j = j0 + qq;
+                        if (j < js0 || j >= js1) continue;
+                        const float f = gptr(T.fval)[fo + qq];
+                        const int cc = cell + j;
+                        const float xr = f * pr, xi = f * pi, xw = f * q;
+                        st_contrib += n;
+                        if (MODE == kModeAtomic) {
+                            atomicAdd(&s_re[cc], (double)f * (double)pr);
+                            atomicAdd(&s_im[cc], (double)f * (double)pi);
+                            atomicAdd(&s_w[cc], (double)f * (double)q);
+                            atomicAdd(&s_n[cc], n);
+                        } else if (!KAHAN) {
+                            s_re[cc] += (double)f * (double)pr;
+                            s_im[cc] += (double)f * (double)pi;
+                            s_w[cc] += (double)f * (double)q;
+                            s_n[cc] += n;
+                        } else {
+                            float y, t;
+                            y = xr - c_re[cc]; t = s_re[cc] + y; c_re[cc] = (t - s_re[cc]) - y; s_re[cc] = t;
+                            y = xi - c_im[cc]; t = s_im[cc] + y; c_im[cc] = (t - s_im[cc]) - y; s_im[cc] = t;
+                            y = xw - c_w[cc]; t = s_w[cc] + y; c_w[cc] = (t - s_w[cc]) - y; s_w[cc] = t;
+                            s_n[cc] += n;
                         }
                     }
                 }
             }
+        };
+
+        // ---- items processed with the loads of the next item already in flight
+        Item it0, it1;
+        LaneLoad<NPOL> ld0, ld1;
+        bool have0 = next_item(it0);
+        if (have0) issue_loads<NPOL>(tgts, it0, lane, ld0);
+        while (have0) {
+            const bool have1 = next_item(it1);
+            if (have1) issue_loads<NPOL>(tgts, it1, lane, ld1);
+            process(it0, ld0);
+            if (!have1) break;
+            have0 = next_item(it0);
+            if (have0) issue_loads<NPOL>(tgts, it0, lane, ld0);
+            process(it1, ld1);
         }
+
         // classification and contribution counts: one atomic per wave and unit
-        st_flag = wave_sum_u64(st_flag);
-        st_bad = wave_sum_u64(st_bad);
-        st_used = wave_sum_u64(st_used);
-        st_contrib = wave_sum_u64(st_contrib);
+        unsigned long long t_flag = wave_sum_u64(st_flag);
+        unsigned long long t_bad = wave_sum_u64(st_bad);
+        unsigned long long t_used = wave_sum_u64(st_used);
+        unsigned long long t_contrib = wave_sum_u64(st_contrib);
         if (lane == 0) {
-            if (st_flag) atomicAdd(&S.stats[1], st_flag);
-            if (st_bad) atomicAdd(&S.stats[2], st_bad);
-            if (st_used) atomicAdd(&S.stats[5], st_used);
-            if (st_contrib) atomicAdd(&S.stats[6], st_contrib);
-            if (st_contrib > 0xffffffffull) atomicOr(&S.stats[7], 1ull);
+            if (t_flag) atomicAdd(&S.stats[1], t_flag);
+            if (t_bad) atomicAdd(&S.stats[2], t_bad);
+            if (t_used) atomicAdd(&S.stats[5], t_used);
+            if (t_contrib) atomicAdd(&S.stats[6], t_contrib);
+            if (t_contrib > 0xffffffffull) atomicOr(&S.stats[7], 1ull);
         }
         __syncthreads();
 
@@ -438,7 +693,7 @@ __global__ void __launch_bounds__(512) k_accum(const LaunchDesc* __restrict__ Lp
                 dim = (double)s_im[c] - (double)c_im[c];
                 dw = (double)s_w[c] - (double)c_w[c];
             } else {
-                dre = s_re[c]; dim = s_im[c]; dw = s_w[c];
+                dre = (double)s_re[c]; dim = (double)s_im[c]; dw = (double)s_w[c];
             }
             uint32_t n = s_n[c];
             if (L.carry) {
@@ -498,8 +753,9 @@ __global__ void k_debug_indices(const DevTarget* __restrict__ Tp, const DevStack
     double rv = cell_coord(T.uvw[3 * r + 1], ce.a, S.inv_dv);
     iu[e] = fabs(ru) < 2.0e9 ? (int32_t)ru + S.nu / 2 : INT32_MIN;
     iv[e] = fabs(rv) < 2.0e9 ? (int32_t)rv + S.nv / 2 : INT32_MIN;
-    j0[e] = ce.nj ? ce.j0 : -1;
-    nj[e] = ce.nj;
+    int32_t n = (int32_t)(ce.jn >> 24);
+    j0[e] = n ? (int32_t)(ce.jn & kJMask) : -1;
+    nj[e] = n;
 }
 
 __global__ void k_debug_rotate(const DevTarget* __restrict__ Tp, float2* out, int64_t nrow, int32_t nchan,
@@ -529,32 +785,20 @@ __global__ void k_debug_rotate(const DevTarget* __restrict__ Tp, float2* out, in
 
 // ---------------------------------------------------------------------------- launchers
 
-hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint64_t* seg_count,
-                        const uint64_t* seg_off, uint32_t* keys, uint64_t* vals, int emit,
-                        hipStream_t stream) {
+hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint32_t* seg_count, const uint32_t* seg_off,
+                        uint32_t* keys, uint64_t* vals, int emit, hipStream_t stream) {
     if (L.nrows <= 0) return hipSuccess;
     int64_t blocks = (L.nrows + 255) / 256;
-    hipLaunchKernelGGL(k_track, dim3((unsigned)blocks), dim3(256), 0, stream, dL, seg_count, seg_off, keys,
-                       vals, emit);
+    hipLaunchKernelGGL(k_track, dim3((unsigned)blocks), dim3(256), 0, stream, dL, seg_count, seg_off, keys, vals,
+                       emit);
     return hipGetLastError();
 }
 
-hipError_t launch_exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, void* tmp,
-                                     size_t* tmp_bytes, hipStream_t stream) {
-    return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, stream);
-}
-
-hipError_t launch_sort_pairs(const uint32_t* kin, uint32_t* kout, const uint64_t* vin, uint64_t* vout,
-                             int64_t n, int end_bit, void* tmp, size_t* tmp_bytes, hipStream_t stream) {
-    return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kin, kout, vin, vout, (int)n, 0, end_bit,
-                                              stream);
-}
-
-hipError_t launch_tile_offsets(const uint32_t* sorted_keys, int64_t nrec, int64_t ntiles, uint32_t* tile_off,
-                               uint64_t* tile_cost, const uint64_t* vals, hipStream_t stream) {
-    int64_t n = nrec + 1;
-    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sorted_keys,
-                       nrec, ntiles, tile_off, tile_cost, vals);
+hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
+                               int64_t nunits, uint32_t* unit_off, hipStream_t stream) {
+    int64_t n = nrec_cap + 1;
+    hipLaunchKernelGGL(k_unit_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sorted_keys,
+                       nrec_dev, nrec_cap, nunits, unit_off);
     return hipGetLastError();
 }
 
@@ -573,35 +817,35 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 // Supported shapes (tile_u, tile_v, jblock).  The autotuner chooses among these.
 #define VISTA_SHAPES(X) \
     X(8, 8, 64)          \
+    X(16, 4, 64)         \
     X(16, 8, 32)         \
     X(16, 16, 16)        \
-    X(8, 4, 128)         \
-    X(4, 4, 256)
+    X(8, 4, 128)
 
-template <int TU, int TV, int JC, int MODE, bool KAHAN>
-static hipError_t launch_one(const LaunchDesc* dL, const uint2* units, int64_t nunits, uint32_t* counter,
-                             const uint32_t* tile_off, const uint64_t* recs, int grid, int waves,
+template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
+static hipError_t launch_one(const LaunchDesc* dL, const uint32_t* order, int64_t nunits, uint32_t* counter,
+                             const uint32_t* unit_off, const uint64_t* recs, int grid, int waves,
                              hipStream_t stream) {
-    hipLaunchKernelGGL((k_accum<TU, TV, JC, MODE, KAHAN>), dim3(grid), dim3(waves * kWave), 0, stream, dL,
-                       units, nunits, counter, tile_off, recs);
+    hipLaunchKernelGGL((k_accum<TU, TV, JC, MODE, KAHAN, NPOL>), dim3(grid), dim3(waves * kWave), 0, stream, dL,
+                       order, nunits, counter, unit_off, recs);
     return hipGetLastError();
 }
 
-template <int TU, int TV, int JC, int MODE, bool KAHAN>
+template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
 static int occ_one(int waves) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum<TU, TV, JC, MODE, KAHAN>, waves * kWave, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum<TU, TV, JC, MODE, KAHAN, NPOL>, waves * kWave,
+                                                     0) != hipSuccess)
         return 0;
     return nb;
 }
 
 size_t accum_lds_bytes(int tu, int tv, int jc, int mode, int kahan) {
-    return (size_t)tu * tv * (jc + 1) * (kahan ? 7 : 4) * 4;
+    return (size_t)tu * tv * (jc + 1) * 28;
 }
 
 bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kahan) {
-    if (waves < 1 || waves > 8) return false;
+    if (waves < 1 || waves > 16) return false;
     if (kahan && mode != kModeOrdered) return false;
     if (mode == kModeOrdered && (jc % waves) != 0) return false;
 #define X(a, b, c) if (tu == a && tv == b && jc == c) return accum_lds_bytes(a, b, c, mode, kahan) <= 160 * 1024;
@@ -610,36 +854,43 @@ bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kaha
     return false;
 }
 
-hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint2* units, int64_t nunits,
-                             uint32_t* counter, const uint32_t* tile_off, const uint64_t* recs, int grid,
-                             int waves, hipStream_t stream) {
-    if (!accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan)) return hipErrorInvalidValue;
-#define X(a, b, c)                                                                                         \
-    if (L.tu == a && L.tv == b && L.jc == c) {                                                             \
-        if (L.mode == kModeAtomic)                                                                         \
-            return launch_one<a, b, c, kModeAtomic, false>(dL, units, nunits, counter, tile_off, recs, grid, \
-                                                           waves, stream);                                 \
-        if (L.kahan)                                                                                       \
-            return launch_one<a, b, c, kModeOrdered, true>(dL, units, nunits, counter, tile_off, recs, grid, \
-                                                           waves, stream);                                 \
-        return launch_one<a, b, c, kModeOrdered, false>(dL, units, nunits, counter, tile_off, recs, grid,   \
-                                                        waves, stream);                                    \
+// npol: 2 for launches whose targets all have two polarisations (the specialised path),
+// anything else selects the generic path.
+#define VISTA_DISPATCH(a, b, c, CALL)                                                    \
+    if (L.tu == a && L.tv == b && L.jc == c) {                                           \
+        if (L.mode == kModeAtomic) {                                                     \
+            if (npol == 2) return CALL(a, b, c, kModeAtomic, false, 2);                  \
+            return CALL(a, b, c, kModeAtomic, false, 0);                                 \
+        }                                                                                \
+        if (L.kahan) {                                                                   \
+            if (npol == 2) return CALL(a, b, c, kModeOrdered, true, 2);                  \
+            return CALL(a, b, c, kModeOrdered, true, 0);                                 \
+        }                                                                                \
+        if (npol == 2) return CALL(a, b, c, kModeOrdered, false, 2);                     \
+        return CALL(a, b, c, kModeOrdered, false, 0);                                    \
     }
+
+hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint32_t* order, int64_t nunits,
+                             uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, int grid,
+                             int waves, int npol, hipStream_t stream) {
+    if (!accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan)) return hipErrorInvalidValue;
+#define CALL(a, b, c, m, k, p) launch_one<a, b, c, m, k, p>(dL, order, nunits, counter, unit_off, recs, grid, waves, stream)
+#define X(a, b, c) VISTA_DISPATCH(a, b, c, CALL)
     VISTA_SHAPES(X)
 #undef X
+#undef CALL
     return hipErrorInvalidValue;
 }
 
-int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int /*npol*/) {
+int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int npol) {
     if (!accum_shape_supported(tu, tv, jc, waves, mode, kahan)) return 0;
-#define X(a, b, c)                                                                   \
-    if (tu == a && tv == b && jc == c) {                                             \
-        if (mode == kModeAtomic) return occ_one<a, b, c, kModeAtomic, false>(waves); \
-        if (kahan) return occ_one<a, b, c, kModeOrdered, true>(waves);               \
-        return occ_one<a, b, c, kModeOrdered, false>(waves);                         \
-    }
+    LaunchDesc L;
+    L.tu = tu; L.tv = tv; L.jc = jc; L.mode = mode; L.kahan = kahan;
+#define CALL(a, b, c, m, k, p) occ_one<a, b, c, m, k, p>(waves)
+#define X(a, b, c) VISTA_DISPATCH(a, b, c, CALL)
     VISTA_SHAPES(X)
 #undef X
+#undef CALL
     return 0;
 }
 

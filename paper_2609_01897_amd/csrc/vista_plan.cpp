@@ -36,7 +36,7 @@ bool check_grid(const vista_grid_desc* g, std::string* why) {
         *why = fmt("grid nu, nv must be in 1..65535 (got %g, %g)", g->nu, g->nv);
         return false;
     }
-    if (g->nchan < 1) { *why = "grid nchan must be >= 1"; return false; }
+    if (g->nchan < 1 || g->nchan >= (int32_t)kJMask) { *why = "grid nchan must be in 1..16777214"; return false; }
     if (!(g->du > 0 && isfinite(g->du) && g->dv > 0 && isfinite(g->dv))) {
         *why = fmt("grid du, dv must be finite and > 0 (got %g, %g)", g->du, g->dv);
         return false;
@@ -113,19 +113,20 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
     const double lm2 = t->l * t->l + t->m * t->m;
     p.nm1 = -lm2 / (1.0 + sqrt(1.0 - lm2));
     p.chan.resize(n);
+    p.f1.assign(n, 0.f);
+    p.foff.assign(n, 0);
+    p.j0.assign(n, -1);
+    p.nj.assign(n, 0);
     p.inband.assign(n + 1, 0);
     for (int32_t k = 0; k < n; ++k) {
-        DevChan& c = p.chan[k];
-        c.a = t->chan_freq[k] / kC;
-        c.j0 = -1;
-        c.nj = 0;
-        c.foff = (int32_t)p.fval.size();
-        c.pad = 0;
+        struct { int32_t j0, nj; float f0, f1; } c = {-1, 0, 0.f, 0.f};
+        p.foff[k] = (int32_t)p.fval.size();
         if (g->flags & VISTA_F_SPECTRAL_NEAREST) {
             double x = floor((t->chan_freq[k] * opz - g->freq_lo) / g->dfreq);
             if (x >= 0.0 && x < (double)g->nchan) {
                 c.j0 = (int32_t)x;
                 c.nj = 1;
+                c.f0 = 1.0f;
                 p.fval.push_back(1.0f);
             }
         } else {
@@ -145,18 +146,27 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
                 double f = ov / Wr;
                 if (f > kSliver) {
                     if (c.nj == 0) c.j0 = j;
+                    if (c.nj == 0) c.f0 = (float)f;
+                    if (c.nj == 1) c.f1 = (float)f;
                     c.nj++;
                     p.fval.push_back((float)f);
                 }
             }
         }
         p.inband[k + 1] = p.inband[k] + (c.nj > 0 ? 1 : 0);
+        p.j0[k] = c.j0;
+        p.nj[k] = c.nj;
+        p.f1[k] = c.f1;
+        DevChan& d = p.chan[k];
+        d.a = t->chan_freq[k] / kC;
+        d.jn = c.nj > 0 ? ((uint32_t)c.j0 | ((uint32_t)std::min(c.nj, kMaxNj) << 24)) : kJMask;
+        d.f0 = c.f0;
     }
     p.n_inband = p.inband[n];
     p.kin_lo = n;
     p.kin_hi = 0;
     for (int32_t k = 0; k < n; ++k) {
-        if (p.chan[k].nj > 0) {
+        if (p.nj[k] > 0) {
             p.kin_lo = std::min(p.kin_lo, k);
             p.kin_hi = std::max(p.kin_hi, k + 1);
         }
@@ -166,8 +176,8 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
     // share rest channel j are at most (last - first channel reaching j) apart.
     std::vector<int32_t> kmin(g->nchan, INT32_MAX), kmax(g->nchan, -1);
     for (int32_t k = 0; k < n; ++k) {
-        for (int32_t q = 0; q < p.chan[k].nj; ++q) {
-            int32_t j = p.chan[k].j0 + q;
+        for (int32_t q = 0; q < p.nj[k]; ++q) {
+            int32_t j = p.j0[k] + q;
             kmin[j] = std::min(kmin[j], k);
             kmax[j] = std::max(kmax[j], k);
         }
@@ -180,14 +190,23 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
     return p;
 }
 
+bool check_plan(const ChannelPlan& p, std::string* why) {
+    for (size_t k = 0; k < p.nj.size(); ++k) {
+        if (p.nj[k] > kMaxNj) {
+            *why = "a channel overlaps more than 255 rest channels (rest grid too fine for the data)";
+            return false;
+        }
+    }
+    return true;
+}
+
 std::vector<int32_t> block_ranges(const ChannelPlan& p, int32_t nchan_grid, int32_t jsub) {
     int32_t nb = (nchan_grid + jsub - 1) / jsub;
     std::vector<int32_t> out(2 * (size_t)nb, 0);
     std::vector<int32_t> lo(nb, INT32_MAX), hi(nb, INT32_MIN);
     for (int32_t k = 0; k < (int32_t)p.chan.size(); ++k) {
-        const DevChan& c = p.chan[k];
-        for (int32_t q = 0; q < c.nj; ++q) {
-            int32_t b = (c.j0 + q) / jsub;
+        for (int32_t q = 0; q < p.nj[k]; ++q) {
+            int32_t b = (p.j0[k] + q) / jsub;
             lo[b] = std::min(lo[b], k);
             hi[b] = std::max(hi[b], k + 1);
         }

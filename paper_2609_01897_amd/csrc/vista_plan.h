@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vista.h"
+#include "vista.h"
 #include "vista_internal.h"
 
 namespace vista {
@@ -14,7 +14,10 @@ namespace vista {
 // Per-target rest-frame plan (Sec. 3.1 and Eq. 3-4), computed in FP64 on the host.
 struct ChannelPlan {
     std::vector<DevChan> chan;     // [nchan]
-    std::vector<float> fval;       // overlap fractions, CSR by DevChan::foff / nj
+    std::vector<float> f1;         // [nchan] second overlap fraction (0 if nj < 2)
+    std::vector<int32_t> foff;     // [nchan] offset of the channel's fractions in fval
+    std::vector<float> fval;       // overlap fractions of every channel, in order
+    std::vector<int32_t> j0, nj;   // [nchan] unpacked J_k ranges (host use)
     std::vector<int32_t> inband;   // [nchan+1] prefix count of channels with nj > 0
     int32_t kin_lo = 0, kin_hi = 0;  // hull of channels with nj > 0
     int32_t nphase = 1;            // channel distance with disjoint rest-channel sets
@@ -25,6 +28,9 @@ struct ChannelPlan {
 // Validation; on failure returns false and fills *why.
 bool check_grid(const vista_grid_desc* g, std::string* why);
 bool check_target(const vista_grid_desc* g, const vista_target* t, std::string* why);
+// Channel-table limits of the packed device format (J_k sizes up to kMaxNj); false with
+// *why when the target's overlap sets do not fit.
+bool check_plan(const ChannelPlan& p, std::string* why);
 
 // Build the plan of target t on grid g.
 ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t);

@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vista.h"
+#include "vista.h"
 #include "vista_internal.h"
 #include "vista_plan.h"
 
@@ -165,13 +165,13 @@ static void copy_target(HostTarget& h, const vista_grid_desc* g, const vista_tar
 }
 
 struct Tuning {
-    int tu = 8, tv = 8, jc = 64, waves = 8, wg_per_cu = 0;
+    int tu = 16, tv = 4, jc = 64, waves = 16, wg_per_cu = 0;
 };
 
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
     if (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) {
-        t.tu = 8; t.tv = 4; t.jc = 128; t.waves = 8;
+        t.tu = 8; t.tv = 4; t.jc = 128; t.waves = 8;   // ordered: 16-channel slices per wave
     }
     return t;
 }
@@ -285,9 +285,10 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
         if (n) memcpy(arena.data() + off, p, n);
         return off;
     };
-    struct Offs { size_t chan, fval, blk, inband; };
+    struct Offs { size_t chan, f1, foff, fval, blk, sblk, inband; };
     std::vector<Offs> offs;
-    int64_t rows = 0, tiles = 0;
+    int64_t rows = 0, tiles = 0, nunits = 0;
+    std::vector<int64_t> unit_base;
     for (size_t s = 0; s < jobs.size(); ++s) {
         const vista_grid_desc* g = jobs[s].g;
         DevStack& S = dss[s];
@@ -300,8 +301,11 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
         S.inv_dv = 1.0 / g->dv;
         S.target_begin = (int32_t)dts.size();
         S.tile_base = tiles;
+        S.unit_base = nunits;
         tile_base.push_back(tiles);
+        unit_base.push_back(nunits);
         tiles += (int64_t)S.tiles_u * S.tiles_v;
+        nunits += (int64_t)S.tiles_u * S.tiles_v * S.nblocks;
         for (HostTarget* h : jobs[s].targets) {
             if (h->t.nrow == 0) continue;
             DevTarget T;
@@ -315,12 +319,21 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
             T.kin_lo = h->plan.kin_lo;
             T.kin_hi = h->plan.kin_hi;
             T.nphase = h->plan.nphase;
+            T.nblocks = S.nblocks;
             T.l = h->t.l; T.m = h->t.m; T.nm1 = h->plan.nm1;
             Offs o;
             o.chan = put(h->plan.chan.data(), h->plan.chan.size() * sizeof(DevChan));
+            o.f1 = put(h->plan.f1.data(), h->plan.f1.size() * sizeof(float));
+            o.foff = put(h->plan.foff.data(), h->plan.foff.size() * sizeof(int32_t));
             o.fval = put(h->plan.fval.data(), h->plan.fval.size() * sizeof(float));
-            std::vector<int32_t> blk = block_ranges(h->plan, g->nchan, jsub);
+            std::vector<int32_t> blk = block_ranges(h->plan, g->nchan, tu.jc);
             o.blk = put(blk.data(), blk.size() * sizeof(int32_t));
+            if (jsub != tu.jc) {
+                std::vector<int32_t> sblk = block_ranges(h->plan, g->nchan, jsub);
+                o.sblk = put(sblk.data(), sblk.size() * sizeof(int32_t));
+            } else {
+                o.sblk = o.blk;
+            }
             o.inband = put(h->plan.inband.data(), h->plan.inband.size() * sizeof(int32_t));
             offs.push_back(o);
             row_base.push_back(rows);
@@ -331,8 +344,9 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     }
     row_base.push_back(rows);
     tile_base.push_back(tiles);
+    unit_base.push_back(nunits);
     if (rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
-    if (tiles >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many tiles in one launch"};
+    if (nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
 
     VISTA_HIP(hipEventRecord(ev.e[0], stream));
 
@@ -367,8 +381,11 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     VISTA_HIP(hipMemcpyAsync(d_arena, arena.data(), arena.size(), hipMemcpyHostToDevice, stream));
     for (size_t i = 0; i < dts.size(); ++i) {
         dts[i].chan = (const DevChan*)(d_arena + offs[i].chan);
+        dts[i].f1 = (const float*)(d_arena + offs[i].f1);
+        dts[i].foff = (const int32_t*)(d_arena + offs[i].foff);
         dts[i].fval = (const float*)(d_arena + offs[i].fval);
         dts[i].blk = (const int32_t*)(d_arena + offs[i].blk);
+        dts[i].sblk = (const int32_t*)(d_arena + offs[i].sblk);
         dts[i].inband = (const int32_t*)(d_arena + offs[i].inband);
     }
     unsigned long long* d_stats = mem.alloc_n<unsigned long long>(8 * jobs.size());
@@ -386,11 +403,13 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     DevStack* d_s = mem.alloc_n<DevStack>(dss.size());
     int64_t* d_rb = mem.alloc_n<int64_t>(row_base.size());
     int64_t* d_tb = mem.alloc_n<int64_t>(tile_base.size());
+    int64_t* d_ub = mem.alloc_n<int64_t>(unit_base.size());
     if (!dts.empty())
         VISTA_HIP(hipMemcpyAsync(d_t, dts.data(), dts.size() * sizeof(DevTarget), hipMemcpyHostToDevice, stream));
     VISTA_HIP(hipMemcpyAsync(d_s, dss.data(), dss.size() * sizeof(DevStack), hipMemcpyHostToDevice, stream));
     VISTA_HIP(hipMemcpyAsync(d_rb, row_base.data(), row_base.size() * 8, hipMemcpyHostToDevice, stream));
     VISTA_HIP(hipMemcpyAsync(d_tb, tile_base.data(), tile_base.size() * 8, hipMemcpyHostToDevice, stream));
+    VISTA_HIP(hipMemcpyAsync(d_ub, unit_base.data(), unit_base.size() * 8, hipMemcpyHostToDevice, stream));
 
     LaunchDesc L;
     memset(&L, 0, sizeof(L));
@@ -398,6 +417,7 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     L.stacks = d_s;
     L.target_row_base = d_rb;
     L.stack_tile_base = d_tb;
+    L.stack_unit_base = d_ub;
     L.ntargets = (int32_t)dts.size();
     L.nstacks = (int32_t)dss.size();
     L.tu = tu.tu; L.tv = tu.tv; L.jc = tu.jc; L.jsub = jsub;
@@ -408,73 +428,61 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     LaunchDesc* d_L = mem.alloc_n<LaunchDesc>(1);
     VISTA_HIP(hipMemcpyAsync(d_L, &L, sizeof(L), hipMemcpyHostToDevice, stream));
 
-    // ---- binning: (row, tile) records grouped by tile
+    // ---- binning: records of (row, tile run, block), grouped by (tile, block) unit
     int64_t nrec = 0;
-    uint32_t* tile_off = mem.alloc_n<uint32_t>(tiles + 1);
-    uint64_t* tile_cost = mem.alloc_n<uint64_t>(tiles + 1);
-    check_launch(launch_fill_u64((unsigned long long*)tile_cost, 0ull, tiles + 1, stream), "fill");
-    uint32_t* keys_s = nullptr;
-    uint64_t* vals_s = nullptr;
+    uint32_t* unit_off = mem.alloc_n<uint32_t>(nunits + 1);
+    uint64_t* vals = nullptr;
     if (rows > 0) {
-        uint64_t* cnt = mem.alloc_n<uint64_t>(rows);
-        uint64_t* off = mem.alloc_n<uint64_t>(rows);
+        uint32_t* cnt = mem.alloc_n<uint32_t>(rows);
+        uint32_t* off = mem.alloc_n<uint32_t>(rows + 1);
+        uint64_t* sums = mem.alloc_n<uint64_t>(scan_temp_elems(rows));
         check_launch(launch_track(L, d_L, cnt, nullptr, nullptr, nullptr, 0, stream), "track count");
-        size_t tb = 0;
-        VISTA_HIP(launch_exclusive_scan_u64(cnt, off, rows, nullptr, &tb, stream));
-        void* tmp = mem.alloc(tb);
-        VISTA_HIP(launch_exclusive_scan_u64(cnt, off, rows, tmp, &tb, stream));
-        uint64_t last[2];
-        VISTA_HIP(hipMemcpyAsync(&last[0], off + rows - 1, 8, hipMemcpyDeviceToHost, stream));
-        VISTA_HIP(hipMemcpyAsync(&last[1], cnt + rows - 1, 8, hipMemcpyDeviceToHost, stream));
+        check_launch(exclusive_scan_u32_to_u32(cnt, nullptr, rows, off, sums, stream), "scan");
+        int64_t nb = (int64_t)scan_temp_elems(rows) - 1;
+        uint64_t total = 0;
+        VISTA_HIP(hipMemcpyAsync(&total, sums + nb, 8, hipMemcpyDeviceToHost, stream));
         VISTA_HIP(hipStreamSynchronize(stream));
-        nrec = (int64_t)(last[0] + last[1]);
-        if (nrec >= 0x7fffffffLL) throw HipFail{hipErrorInvalidValue, "too many track records in one launch"};
+        if (total >= 0xffffffffull) throw HipFail{hipErrorInvalidValue, "too many track records in one launch"};
+        nrec = (int64_t)total;
         if (nrec > 0) {
             uint32_t* keys = mem.alloc_n<uint32_t>(nrec);
-            uint64_t* vals = mem.alloc_n<uint64_t>(nrec);
-            keys_s = mem.alloc_n<uint32_t>(nrec);
-            vals_s = mem.alloc_n<uint64_t>(nrec);
+            vals = mem.alloc_n<uint64_t>(nrec);
+            void* stmp = mem.alloc(radix_sort_temp_bytes(nrec));
             check_launch(launch_track(L, d_L, nullptr, off, keys, vals, 1, stream), "track emit");
-            int end_bit = 1;
-            while (end_bit < 32 && (int64_t(1) << end_bit) < tiles) ++end_bit;
-            size_t sb = 0;
-            VISTA_HIP(launch_sort_pairs(keys, keys_s, vals, vals_s, nrec, end_bit, nullptr, &sb, stream));
-            void* stmp = mem.alloc(sb);
-            VISTA_HIP(launch_sort_pairs(keys, keys_s, vals, vals_s, nrec, end_bit, stmp, &sb, stream));
+            int bits = 1;
+            while (bits < 32 && (int64_t(1) << bits) < nunits) ++bits;
+            check_launch(radix_sort_pairs(keys, vals, nullptr, nrec, bits, stmp, stream), "sort");
+            check_launch(launch_unit_offsets(keys, nullptr, nrec, nunits, unit_off, stream), "unit offsets");
         }
     }
-    if (nrec > 0) {
-        check_launch(launch_tile_offsets(keys_s, nrec, tiles, tile_off, tile_cost, vals_s, stream), "tile offsets");
-    } else {
-        check_launch(launch_fill_u32(tile_off, 0u, tiles + 1, stream), "fill");
-    }
+    if (nrec == 0) check_launch(launch_fill_u32(unit_off, 0u, nunits + 1, stream), "fill");
 
-    // ---- work list: every (tile, block) of every stack, heaviest tiles first
-    std::vector<uint64_t> cost(tiles + 1);
-    VISTA_HIP(hipMemcpyAsync(cost.data(), tile_cost, (tiles + 1) * 8, hipMemcpyDeviceToHost, stream));
+    // ---- work list: every (tile, block) unit of every stack, heaviest first (units
+    // without records still write their zero cells)
+    std::vector<uint32_t> uoff(nunits + 1);
+    VISTA_HIP(hipMemcpyAsync(uoff.data(), unit_off, (nunits + 1) * 4, hipMemcpyDeviceToHost, stream));
     VISTA_HIP(hipStreamSynchronize(stream));
-    std::vector<uint32_t> order(tiles);
+    std::vector<uint32_t> order(nunits);
     std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
-    std::vector<uint2> units;
-    for (uint32_t gt : order) {
-        size_t s = std::upper_bound(tile_base.begin(), tile_base.end() - 1, (int64_t)gt) - tile_base.begin() - 1;
-        for (int32_t b = 0; b < dss[s].nblocks; ++b) units.push_back(make_uint2(gt, (uint32_t)b));
-    }
-    uint2* d_units = mem.alloc_n<uint2>(std::max<size_t>(1, units.size()));
-    if (!units.empty())
-        VISTA_HIP(hipMemcpyAsync(d_units, units.data(), units.size() * sizeof(uint2), hipMemcpyHostToDevice, stream));
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return uoff[a + 1] - uoff[a] > uoff[b + 1] - uoff[b]; });
+    uint32_t* d_order = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nunits));
+    if (nunits > 0)
+        VISTA_HIP(hipMemcpyAsync(d_order, order.data(), nunits * 4, hipMemcpyHostToDevice, stream));
     uint32_t* counter = mem.alloc_n<uint32_t>(1);
     check_launch(launch_fill_u32(counter, 0u, 1, stream), "fill");
-    uint64_t* dummy = nullptr;
-    if (!vals_s) { dummy = mem.alloc_n<uint64_t>(1); vals_s = dummy; }
+    if (!vals) vals = mem.alloc_n<uint64_t>(1);
 
     VISTA_HIP(hipEventRecord(ev.e[1], stream));
-    int per_cu = tu.wg_per_cu > 0 ? tu.wg_per_cu : accum_max_blocks_per_cu(tu.tu, tu.tv, tu.jc, tu.waves, mode, kahan, 2);
+    int npol_all = 2;
+    for (auto& T : dts)
+        if (T.npol != 2 || T.weight_per_chan) npol_all = 0;   // the specialised path: 2 pols, row weights
+    int per_cu = tu.wg_per_cu > 0 ? tu.wg_per_cu
+                                  : accum_max_blocks_per_cu(tu.tu, tu.tv, tu.jc, tu.waves, mode, kahan, npol_all);
     if (per_cu < 1) per_cu = 1;
-    int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, (int64_t)units.size()));
-    check_launch(launch_accum_impl(L, d_L, d_units, (int64_t)units.size(), counter, tile_off, vals_s, (int)grid,
-                                   tu.waves, stream),
+    int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, nunits));
+    check_launch(launch_accum_impl(L, d_L, d_order, nunits, counter, unit_off, vals, (int)grid, tu.waves, npol_all,
+                                   stream),
                  "accumulate");
     VISTA_HIP(hipEventRecord(ev.e[2], stream));
 
@@ -502,7 +510,7 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
         tim->finalize_ms = ev.ms(2, 3);
         tim->total_ms = ev.ms(0, 3);
         tim->n_records = nrec;
-        tim->n_units = (int64_t)units.size();
+        tim->n_units = nunits;
         tim->n_accum_launches = 1;
         tim->n_waves = 1;
     }
@@ -604,6 +612,8 @@ int vista_stack_add_target(vista_stack* s, const vista_target* t) {
     return guarded(nullptr, [&]() -> int {
         auto h = std::make_unique<HostTarget>();
         copy_target(*h, &s->g, t);
+        std::string w;
+        if (!check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
         s->targets.push_back(std::move(h));
         return VISTA_OK;
     });
@@ -785,6 +795,8 @@ int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t)
     return guarded(nullptr, [&]() -> int {
         auto h = std::make_unique<HostTarget>();
         copy_target(*h, &b->g[stack], t);
+        std::string w;
+        if (!check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
         b->targets[stack].push_back(std::move(h));
         return VISTA_OK;
     });
