@@ -819,8 +819,11 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     X(8, 8, 64)          \
     X(16, 4, 64)         \
     X(16, 8, 32)         \
-    X(16, 16, 16)        \
-    X(8, 4, 128)
+    X(8, 4, 128)         \
+    X(16, 2, 128)        \
+    X(4, 4, 256)         \
+    X(8, 2, 256)         \
+    X(4, 2, 512)
 
 template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
 static hipError_t launch_one(const LaunchDesc* dL, const uint32_t* order, int64_t nunits, uint32_t* counter,

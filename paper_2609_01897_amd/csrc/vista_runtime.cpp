@@ -165,7 +165,7 @@ static void copy_target(HostTarget& h, const vista_grid_desc* g, const vista_tar
 }
 
 struct Tuning {
-    int tu = 16, tv = 4, jc = 64, waves = 16, wg_per_cu = 0;
+    int tu = 4, tv = 4, jc = 256, waves = 16, wg_per_cu = 0;
 };
 
 static Tuning default_tuning(uint32_t flags) {

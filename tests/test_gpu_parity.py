@@ -158,7 +158,8 @@ def test_no_targets_gives_zero_grid():
     assert st["n_samples"] == 0
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 64), (16, 4, 64), (16, 8, 32), (16, 16, 16), (8, 4, 128)])
+@pytest.mark.parametrize("shape", [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128), (4, 4, 256),
+                                   (8, 2, 256), (4, 2, 512)])
 def test_every_tile_shape_matches(shape):
     """The autotuner's candidates change only speed: counts identical, sums in tolerance."""
     cfg = synth.config("small")
