@@ -78,6 +78,25 @@ def cpu_baseline(targets_dev, grid, n_targets):
                 % (n_targets, len(targets_dev), ns, dt))
 
 
+def copy_probe(nbytes, steps):
+    """Time the plain copy kernel; its counter readings scale those of the stacking kernel."""
+    import torch
+    from paper_2609_01897_amd import vista
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    vista.debug_copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        vista.debug_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": steps + 1,
+                      "ms_per_launch": ms, "GB/s": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,9 +105,12 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--targets", type=int, default=0, help="use only this many targets (0 = all)")
     ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32")
-    ap.add_argument("--cpu-targets", type=int, default=4, help="targets in the oracle's timed sample")
+    ap.add_argument("--cpu-targets", type=int, default=8, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the library's plain copy kernel on MIB MiB, --steps times (calibrates "
+                         "hardware byte counters), and print its bytes and time")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes "
@@ -101,6 +123,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     vista.lib()
+    if args.copy_probe:
+        copy_probe(args.copy_probe << 20, args.steps)
+        return
     cfg = synth.config(args.config)
     ntg = args.targets or cfg.n_targets
     grid = synth.make_grid(cfg)

@@ -207,6 +207,12 @@ int vista_debug_indices(const vista_grid_desc* g, const vista_target* t, void* h
  * Flags and weights are ignored.  The target must be VISTA_MEM_DEVICE. */
 int vista_debug_rotate(const vista_grid_desc* g, const vista_target* t, void* hip_stream, void* out);
 
+/* A plain device-to-device copy of nbytes (a multiple of 16; both pointers 16-byte
+ * aligned, regions not overlapping) by one streaming kernel, stream-ordered on hip_stream
+ * and not waited for.  It is no part of the method: it reads and writes each byte once,
+ * so hardware byte counters read on it calibrate those read on the stacking kernels. */
+int vista_debug_copy(void* dst, const void* src, size_t nbytes, void* hip_stream);
+
 /* Autotune the launch shape for the stack's targets: times the candidate shapes on the
  * real data and keeps the fastest whose counts equal the default shape's.  The result
  * is applied to the stack and returned in *best (may be NULL).  Only before finalize;

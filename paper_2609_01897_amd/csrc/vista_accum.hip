@@ -1,0 +1,562 @@
+// Packed accumulation of the atomic mode (Eq. 2 rotation, Eq. 3-4 rest-frame rebinning).
+//
+// The binning pass leaves the records of every (uv tile, rest-channel block) unit
+// contiguous; a record is a run [k_lo, k_hi) of channels of one row.  Concatenated, the
+// unit's records form one stream of (row, channel) samples, and pre[] gives each record's
+// start in it.  A workgroup owns one unit at a time: its cells live in LDS (FP64 sums and a
+// u32 count per cell), so every cell of the grid is written exactly once, from one place.
+// The unit's stream is split into equal sample ranges, one per wavefront, and a wavefront
+// walks its range in chunks of 64 consecutive samples, one per lane, whatever records they
+// come from: no lane idles at record ends.  Each lane finds its record in a window of 64
+// records held one per lane (the starts falling inside the chunk are few and are tested
+// one by one), takes the record's context from that lane with ds_bpermute, and loads its
+// own channel-table entry, visibilities and flags.  The loads of the next chunk are in
+// flight while the current one is processed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "vista_device.h"
+
+namespace vista {
+
+namespace {
+
+__device__ __forceinline__ uint32_t bperm(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ uint64_t bperm64(uint64_t v, int src) {
+    return ((uint64_t)bperm((uint32_t)(v >> 32), src) << 32) | bperm((uint32_t)v, src);
+}
+__device__ __forceinline__ double bpermd(double v, int src) {
+    return __builtin_bit_cast(double, bperm64(__builtin_bit_cast(uint64_t, v), src));
+}
+__device__ __forceinline__ float bpermf(float v, int src) {
+    return __builtin_bit_cast(float, bperm(__builtin_bit_cast(uint32_t, v), src));
+}
+__device__ __forceinline__ uint64_t ufl64(uint64_t x) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+
+// A record's context with its addresses rebased to the window's stream positions: the
+// sample at position p (relative to the window origin) of the record has its visibilities
+// at vis + p * (npol * 8), its flags at flag + p * npol, its channel-table entry at index
+// chan + p and (per-channel weights) its weights at wadj + p * wstride; positions from
+// `end` on are the record's padding.
+template <int NPOL>
+struct RecCtx {
+    double U, V, T;
+    float w0, w1;              // NPOL == 2: the row weights
+    uint64_t vis, flag;
+    uint64_t wadj;             // NPOL == 0: weight base
+    uint32_t info;             // NPOL == 0: npol | wstride << 8 (wstride 0: row weights)
+    int32_t chan;
+    uint32_t end;
+};
+
+template <int NPOL>
+__device__ __forceinline__ RecCtx<NPOL> gather(const RecCtx<NPOL>& w, int src) {
+    RecCtx<NPOL> c;
+    c.U = bpermd(w.U, src);
+    c.V = bpermd(w.V, src);
+    c.T = bpermd(w.T, src);
+    if (NPOL == 2) {
+        c.w0 = bpermf(w.w0, src);
+        c.w1 = bpermf(w.w1, src);
+    } else {
+        c.wadj = bperm64(w.wadj, src);
+        c.info = bperm(w.info, src);
+    }
+    c.vis = bperm64(w.vis, src);
+    c.flag = bperm64(w.flag, src);
+    c.chan = (int32_t)bperm((uint32_t)w.chan, src);
+    c.end = bperm(w.end, src);
+    return c;
+}
+
+// What one sample loaded.
+template <int NPOL>
+struct Loaded {
+    double a;                  // nu_k / c
+    uint32_t jn;               // j0 | nj << 24 (nj = 0: nothing to add)
+    float f0, f1;              // overlap fractions of j0 and j0 + 1
+    float vr[NPOL == 2 ? 2 : 4], vi[NPOL == 2 ? 2 : 4];
+    uint32_t fl;               // flag bytes, polarisation p in byte p
+    float wc[NPOL == 2 ? 1 : 4];
+};
+
+// One lane's pair of samples of a chunk: positions pos and pos + 1 of one record.
+template <int NPOL>
+struct Pair {
+    RecCtx<NPOL> c;
+    uint32_t pos;              // stream position relative to the window origin
+    bool act;                  // inside the wavefront's range
+    Loaded<NPOL> s[2];
+};
+
+template <class T>
+__device__ __forceinline__ T gload(uint64_t addr) {
+    return *(const VISTA_GLOBAL T*)addr;
+}
+
+template <int NPOL>
+__device__ __forceinline__ void load_sample(const VISTA_GLOBAL DevChan* chan_all, const VISTA_GLOBAL float* f1_all,
+                                            const RecCtx<NPOL>& c, uint32_t p, bool valid, Loaded<NPOL>& x) {
+    const int32_t ci = c.chan + (int32_t)p;
+    const uint4 ch = *(const VISTA_GLOBAL uint4*)(chan_all + ci);
+    x.a = __builtin_bit_cast(double, ((uint64_t)ch.y << 32) | ch.x);
+    x.jn = valid ? ch.z : 0u;
+    x.f0 = __builtin_bit_cast(float, ch.w);
+    x.f1 = f1_all[ci];
+    if (NPOL == 2) {
+        const float4 v = gload<float4>(c.vis + (uint64_t)p * 16u);
+        x.vr[0] = v.x; x.vi[0] = v.y; x.vr[1] = v.z; x.vi[1] = v.w;
+        x.fl = gload<uint16_t>(c.flag + (uint64_t)p * 2u);
+    } else {
+        const uint32_t np = c.info & 0xffu, ws = c.info >> 8;
+        for (int q = 0; q < 4; ++q) { x.vr[q] = 0.f; x.vi[q] = 0.f; x.wc[q] = 0.f; }
+        if (np == 1) {
+            const float2 v = gload<float2>(c.vis + (uint64_t)p * 8u);
+            x.vr[0] = v.x; x.vi[0] = v.y;
+            x.fl = gload<uint8_t>(c.flag + p);
+        } else if (np == 2) {
+            const float4 v = gload<float4>(c.vis + (uint64_t)p * 16u);
+            x.vr[0] = v.x; x.vi[0] = v.y; x.vr[1] = v.z; x.vi[1] = v.w;
+            x.fl = gload<uint16_t>(c.flag + (uint64_t)p * 2u);
+        } else {
+            const float4 v = gload<float4>(c.vis + (uint64_t)p * 32u);
+            const float4 u = gload<float4>(c.vis + (uint64_t)p * 32u + 16u);
+            x.vr[0] = v.x; x.vi[0] = v.y; x.vr[1] = v.z; x.vi[1] = v.w;
+            x.vr[2] = u.x; x.vi[2] = u.y; x.vr[3] = u.z; x.vi[3] = u.w;
+            x.fl = gload<uint32_t>(c.flag + (uint64_t)p * 4u);
+        }
+        const uint64_t wb = c.wadj + (uint64_t)p * ws;
+        for (int q = 0; q < 4; ++q)
+            if (q < (int)np) x.wc[q] = gload<float>(wb + 4u * q);
+    }
+}
+
+// Both samples of a lane's pair; the second one of a record with an odd channel count is
+// padding: it re-reads the first (always in bounds) and adds nothing.
+template <int NPOL>
+__device__ __forceinline__ void issue(const VISTA_GLOBAL DevChan* chan_all, const VISTA_GLOBAL float* f1_all,
+                                      Pair<NPOL>& x) {
+    if (!x.act) {                 // lanes past the range read nothing
+        for (int i = 0; i < 2; ++i) {
+            Loaded<NPOL>& y = x.s[i];
+            y.a = 0.0; y.jn = 0u; y.f0 = 0.f; y.f1 = 0.f; y.fl = 0u;
+            for (int q = 0; q < (NPOL == 2 ? 2 : 4); ++q) { y.vr[q] = 0.f; y.vi[q] = 0.f; }
+            for (int q = 0; q < (NPOL == 2 ? 1 : 4); ++q) y.wc[q] = 0.f;
+        }
+        return;
+    }
+    const bool two = x.pos + 1u < x.c.end;
+    load_sample<NPOL>(chan_all, f1_all, x.c, x.pos, true, x.s[0]);
+    load_sample<NPOL>(chan_all, f1_all, x.c, two ? x.pos + 1u : x.pos, two, x.s[1]);
+}
+
+// Per-wavefront classification and contribution counts, kept over many units and added to
+// the stack's statistics when the stack changes, every 64 units and at the end.
+struct WaveStats {
+    uint32_t flag = 0, bad = 0, used = 0, contrib = 0;
+    int32_t stack = -1;
+    uint32_t units = 0;
+    __device__ void flush(const LaunchDesc& L, int lane) {
+        const unsigned long long t_flag = wave_sum_u64(flag);
+        const unsigned long long t_bad = wave_sum_u64(bad);
+        const unsigned long long t_used = wave_sum_u64(used);
+        const unsigned long long t_contrib = wave_sum_u64(contrib);
+        if (lane == 0 && stack >= 0) {
+            unsigned long long* st = cptr(L.stacks)[stack].stats;
+            if (t_flag) atomicAdd(&st[1], t_flag);
+            if (t_bad) atomicAdd(&st[2], t_bad);
+            if (t_used) atomicAdd(&st[5], t_used);
+            if (t_contrib) atomicAdd(&st[6], t_contrib);
+        }
+        flag = bad = used = contrib = 0;
+        units = 0;
+    }
+};
+
+template <int TU, int TV, int JC, int NPOL>
+__global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __restrict__ Lp,
+                                                          const uint64_t* __restrict__ order, int64_t nunits,
+                                                          uint32_t* __restrict__ counter,
+                                                          const uint32_t* __restrict__ unit_off,
+                                                          const uint64_t* __restrict__ recs,
+                                                          const uint64_t* __restrict__ pre) {
+    constexpr int JP = JC + 1;            // padded channel stride of a cell
+    constexpr int NC = TU * TV * JP;
+    constexpr uint32_t kChunk = 2 * kWave;
+    __shared__ double s_re[NC], s_im[NC], s_w[NC];
+    __shared__ uint32_t s_n[NC];
+    __shared__ uint32_t s_unit;
+    __shared__ unsigned long long s_contrib;
+
+    const LaunchDesc& L = *Lp;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = sgpr(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
+    const VISTA_GLOBAL uint64_t* grecs = gptr(recs);
+    const VISTA_GLOBAL uint64_t* gpre = gptr(pre);
+    const VISTA_CONST uint64_t* cpre = cptr(pre);
+    const VISTA_GLOBAL RowCtx* rctx = gptr((const RowCtx*)L.rowctx);
+    const VISTA_GLOBAL DevChan* chan_all = gptr(L.chan_all);
+    const VISTA_GLOBAL float* f1_all = gptr(L.f1_all);
+    const int phase_fp32 = L.phase_fp32;
+    WaveStats ws;
+
+    // LDS starts zeroed; afterwards each unit's flush zeroes the cells it wrote
+    for (int i = threadIdx.x; i < NC; i += blockDim.x) {
+        s_re[i] = 0.0; s_im[i] = 0.0; s_w[i] = 0.0; s_n[i] = 0u;
+    }
+    // the next unit is claimed while the current one is processed
+    if (threadIdx.x == 0) {
+        s_unit = atomicAdd(counter, 1u);
+        s_contrib = 0ull;
+    }
+    __syncthreads();
+    for (;;) {
+        const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
+        if (li >= nunits) break;
+        const int64_t unit = (int64_t)ufl64(cptr(order)[li]);
+        const int32_t si = sgpr((int32_t)find_le_uniform(L.stack_unit_base, L.nstacks, unit));
+        const VISTA_CONST DevStack& S = cptr(L.stacks)[si];
+        const int64_t local = unit - S.unit_base;
+        const int64_t tile = local / S.nblocks;
+        const int32_t b = (int32_t)(local - tile * S.nblocks);
+        const int32_t tu0 = (int32_t)(tile % S.tiles_u) * TU;
+        const int32_t tv0 = (int32_t)(tile / S.tiles_u) * TV;
+        const int32_t jb0 = b * JC;
+        const int32_t jb1 = min(jb0 + JC, S.nchan);
+        const int32_t cu = S.nu / 2 - tu0, cv = S.nv / 2 - tv0;
+        const uint32_t ntu = (uint32_t)min(TU, S.nu - tu0), ntv = (uint32_t)min(TV, S.nv - tv0);   // in-grid part
+        const double inv_du = S.inv_du, inv_dv = S.inv_dv;
+        if (si != ws.stack || ws.units >= 64) {
+            ws.flush(L, lane);
+            ws.stack = si;
+        }
+        ++ws.units;
+        __syncthreads();                  // every thread has read s_unit
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+
+        const uint32_t rb = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit]);
+        const uint32_t re = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit + 1]);
+        uint32_t u_contrib = 0;
+        uint64_t sw0 = 0, sw1 = 0;
+        if (rb < re) {
+            // the unit's stream, in pairs, split evenly over the wavefronts
+            const uint64_t p0 = ufl64(cpre[rb]), p1 = ufl64(cpre[re]);
+            const uint64_t pairs = (p1 - p0) >> 1;
+            sw0 = p0 + 2 * (pairs * (uint64_t)wave / (uint64_t)nw);
+            sw1 = p0 + 2 * (pairs * (uint64_t)(wave + 1) / (uint64_t)nw);
+        }
+        if (sw0 < sw1) {
+            // ---- the record holding sample sw0: largest i in [rb, re) with pre[i] <= sw0
+            uint32_t lo = rb, hi = re;
+            while (hi - lo > (uint32_t)kWave) {
+                const uint32_t step = (hi - lo + kWave - 1) / kWave;
+                const uint32_t idx = lo + (uint32_t)lane * step;
+                const bool v = idx < hi;
+                const uint64_t p = v ? gpre[idx] : ~0ull;
+                const uint64_t m = __ballot(v && p <= sw0);        // lane 0 always set
+                lo = lo + (uint32_t)(63 - __clzll(m)) * step;
+                hi = min(lo + step, hi);
+            }
+            uint32_t first;
+            {
+                const uint32_t idx = lo + (uint32_t)lane;
+                const bool v = idx < hi;
+                const uint64_t p = v ? gpre[idx] : ~0ull;
+                const uint64_t m = __ballot(v && p <= sw0);
+                first = lo + (uint32_t)(63 - __clzll(m));
+            }
+
+            // ---- window of up to 64 records, one per lane
+            uint32_t wb = 0, nwin = 0, cur = 0;
+            uint64_t pw = 0, wend = 0;
+            uint32_t wrel = 0;             // this lane's record start, relative to pw
+            RecCtx<NPOL> w;
+            auto load_window = [&](uint32_t nb) __attribute__((always_inline)) {
+                wb = nb;
+                nwin = min((uint32_t)kWave, re - nb);
+                pw = ufl64(cpre[nb]);
+                wend = ufl64(cpre[nb + nwin]);
+                const bool v = (uint32_t)lane < nwin;
+                const uint64_t rec = v ? grecs[nb + lane] : 0ull;
+                const uint64_t pg = v ? gpre[nb + lane] : 0ull;
+                wrel = v ? (uint32_t)(pg - pw) : 0xffffffffu;
+                const uint32_t g = (uint32_t)(rec >> 32);
+                const uint32_t kin = (uint32_t)((rec >> 16) & 0xffffu), kout = (uint32_t)(rec & 0xffffu);
+                const int64_t d = (int64_t)kin - (int64_t)wrel;         // channel - position
+                const VISTA_GLOBAL RowCtx& rc = rctx[g];
+                w.U = rc.U;
+                w.V = rc.V;
+                w.T = rc.T;
+                const uint64_t vrow = rc.vis, frow = rc.flag;
+                w.chan = rc.chan0 + (int32_t)d;
+                w.end = wrel + (kout - kin);
+                if (NPOL == 2) {
+                    w.w0 = rc.w0;
+                    w.w1 = rc.w1;
+                    w.vis = vrow + (uint64_t)(d * 16);
+                    w.flag = frow + (uint64_t)(d * 2);
+                } else {
+                    const uint32_t info = rc.info;
+                    const int64_t np = info & 0xffu;
+                    const bool wpc = (info >> 8) & 1u;
+                    w.vis = vrow + (uint64_t)(d * np * 8);
+                    w.flag = frow + (uint64_t)(d * np);
+                    w.wadj = rc.wrow + (wpc ? (uint64_t)(d * np * 4) : 0ull);
+                    w.info = (uint32_t)np | ((wpc ? (uint32_t)np * 4u : 0u) << 8);
+                }
+            };
+            // lanes of the chunk starting at s (two samples each): records and contexts
+            auto map = [&](uint64_t s, Pair<NPOL>& x) __attribute__((always_inline)) {
+                const uint64_t need = min(s + (uint64_t)kChunk, sw1);
+                if (need > wend) {
+                    load_window(wb + cur);     // restart the window at the record holding s
+                    cur = 0;
+                }
+                const uint32_t srel = (uint32_t)(s - pw);
+                const uint32_t pos = srel + 2u * (uint32_t)lane;
+                // records starting in (s, s + 128]: the last one at or before a lane's pair wins
+                const uint64_t B = __ballot(lane > (int)cur && wrel <= srel + kChunk);
+                int rec = (int)cur;
+                uint64_t m = B;
+                while (m) {
+                    const int i = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane((int)wrel, i);
+                    rec = pos >= pi ? i : rec;
+                }
+                cur += (uint32_t)__popcll(B);
+                x.c = gather<NPOL>(w, rec);
+                x.pos = pos;
+                x.act = s + 2u * (uint64_t)lane < sw1;
+            };
+
+            auto process = [&](const RecCtx<NPOL>& rc, const Loaded<NPOL>& x, int32_t ci) __attribute__((always_inline)) {
+                const uint32_t nj = x.jn >> 24;
+                const int32_t j0 = (int32_t)(x.jn & kJMask);
+                // cell within the tile (exact FP64 sequence of the definition)
+                const double ru = cell_coord(rc.U, x.a, inv_du);
+                const double rv = cell_coord(rc.V, x.a, inv_dv);
+                const int32_t lu = (int32_t)ru + cu, lv = (int32_t)rv + cv;
+                const bool in_tile = nj > 0 && (uint32_t)lu < ntu && (uint32_t)lv < ntv;
+                // polarisations: drop flagged and bad-weight samples, merge the rest
+                float ar = 0.f, ai = 0.f, q = 0.f;
+                uint32_t n = 0, nflag = 0, nbad = 0;
+                const int np = NPOL == 2 ? 2 : (int)(rc.info & 0xffu);
+#pragma unroll
+                for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p) {
+                    const bool live = NPOL == 2 || p < np;
+                    const float wgt = NPOL == 2 ? (p == 0 ? rc.w0 : rc.w1) : x.wc[p];
+                    const bool flagged = live && ((x.fl >> (8 * p)) & 0xffu) != 0u;
+                    const bool good = live && (wgt > 0.0f) && (wgt < __builtin_inff());
+                    nflag += flagged ? 1u : 0u;
+                    nbad += (live && !flagged && !good) ? 1u : 0u;
+                    const bool use = !flagged && good;
+                    const float wu = use ? wgt : 0.0f;
+                    n += use ? 1u : 0u;
+                    ar = fmaf(wu, x.vr[p], ar);
+                    ai = fmaf(wu, x.vi[p], ai);
+                    q += wu;
+                }
+                float c, s;
+                if (phase_fp32) {
+                    const float t = (float)rc.T * (float)x.a;
+                    sincos_turns(t - rintf(t), &s, &c);
+                } else {
+                    phasor(rc.T, x.a, &c, &s);
+                }
+                const float pr = ar * c - ai * s;
+                const float pi = fmaf(ar, s, ai * c);
+                // classification is counted once, in the block holding j0
+                if (in_tile && j0 >= jb0 && j0 < jb1) {
+                    ws.flag += nflag;
+                    ws.bad += nbad;
+                    ws.used += n;
+                }
+                if (!(in_tile && n > 0)) return;
+                const int cell = (lv * TU + lu) * JP - jb0;
+                const double dr = (double)pr, di = (double)pi, dq = (double)q;
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                    const int32_t j = j0 + qq;
+                    if (qq < (int)nj && j >= jb0 && j < jb1) {
+                        const double f = (double)(qq == 0 ? x.f0 : x.f1);
+                        const int cc = cell + j;
+                        atomicAdd(&s_re[cc], f * dr);          // exact products of FP32 values
+                        atomicAdd(&s_im[cc], f * di);
+                        atomicAdd(&s_w[cc], f * dq);
+                        atomicAdd(&s_n[cc], n);
+                        u_contrib += n;
+                    }
+                }
+                // more than two rest channels (rest grid finer than the channel): rare
+                if (nj > 2) {
+                    const int32_t fo = gptr(L.foff_all)[ci];
+                    for (int qq = 2; qq < (int)nj; ++qq) {
+                        const int32_t j = j0 + qq;
+                        if (j < jb0 || j >= jb1) continue;
+                        const double f = (double)gptr(L.fval_all)[fo + qq];
+                        const int cc = cell + j;
+                        atomicAdd(&s_re[cc], f * dr);
+                        atomicAdd(&s_im[cc], f * di);
+                        atomicAdd(&s_w[cc], f * dq);
+                        atomicAdd(&s_n[cc], n);
+                        u_contrib += n;
+                    }
+                }
+            };
+            auto process_pair = [&](const Pair<NPOL>& x) __attribute__((always_inline)) {
+                const int32_t ci = x.c.chan + (int32_t)x.pos;
+                process(x.c, x.s[0], ci);
+                process(x.c, x.s[1], ci + 1);
+            };
+
+            // ---- chunks, the next one's loads in flight while one is processed
+            load_window(first);
+            cur = 0;
+            Pair<NPOL> x0, x1;
+            uint64_t s = sw0;
+            map(s, x0);
+            issue<NPOL>(chan_all, f1_all, x0);
+            for (;;) {
+                const bool more1 = s + kChunk < sw1;
+                if (more1) {
+                    map(s + kChunk, x1);
+                    issue<NPOL>(chan_all, f1_all, x1);
+                }
+                process_pair(x0);
+                if (!more1) break;
+                s += kChunk;
+                const bool more0 = s + kChunk < sw1;
+                if (more0) {
+                    map(s + kChunk, x0);
+                    issue<NPOL>(chan_all, f1_all, x0);
+                }
+                process_pair(x1);
+                if (!more0) break;
+                s += kChunk;
+            }
+        }
+        ws.contrib += u_contrib;
+
+        // a cell count can wrap only if the unit's contributions reach 2^32
+        const unsigned long long t_contrib = wave_sum_u64(u_contrib);
+        if (lane == 0 && t_contrib) atomicAdd(&s_contrib, t_contrib);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_contrib > 0xffffffffull) atomicOr(&S.stats[7], 1ull);
+            s_contrib = 0ull;
+            s_unit = next;
+        }
+        flush_unit<TU, TV, JP, double, false, true>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, nullptr,
+                                                    nullptr, nullptr);
+        __syncthreads();
+    }
+    ws.flush(L, lane);
+}
+
+// ---------------------------------------------------------------- record prefix, order
+
+__global__ void k_record_lens(const uint64_t* __restrict__ recs, int64_t n, uint32_t* __restrict__ lens) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t r = recs[i];
+        const uint32_t len = (uint32_t)(r & 0xffffu) - (uint32_t)((r >> 16) & 0xffffu);
+        lens[i] = (len + 1u) & ~1u;        // records take whole pairs of stream positions
+    }
+}
+
+// key: descending sample count (saturated), value: unit id
+__global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_t* __restrict__ pre, int64_t nunits,
+                            uint32_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < nunits) {
+        const uint64_t ns = pre[unit_off[u + 1]] - pre[unit_off[u]];
+        keys[u] = 0xffffffffu - (uint32_t)min(ns, (uint64_t)0xffffffffu);
+        vals[u] = (uint64_t)u;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_record_prefix(const uint64_t* recs, int64_t nrec, uint32_t* lens, uint64_t* pre, uint64_t* sums,
+                                hipStream_t stream) {
+    if (nrec > 0)
+        hipLaunchKernelGGL(k_record_lens, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, stream, recs, nrec,
+                           lens);
+    return exclusive_scan_u32_to_u64(lens, nullptr, nrec, pre, sums, stream);
+}
+
+hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, int64_t nunits, uint32_t* keys,
+                             uint64_t* vals, void* sort_temp, hipStream_t stream) {
+    if (nunits <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unit_keys, dim3((unsigned)((nunits + 255) / 256)), dim3(256), 0, stream, unit_off, pre,
+                       nunits, keys, vals);
+    return radix_sort_pairs(keys, vals, nullptr, nunits, 32, sort_temp, stream);
+}
+
+#define VISTA_PACKED_SHAPES(X) \
+    X(8, 8, 64)                \
+    X(16, 4, 64)               \
+    X(16, 8, 32)               \
+    X(8, 4, 128)               \
+    X(16, 2, 128)              \
+    X(4, 4, 256)               \
+    X(8, 2, 256)               \
+    X(4, 2, 512)               \
+    X(4, 4, 128)               \
+    X(8, 4, 64)                \
+    X(8, 2, 128)               \
+    X(4, 2, 256)
+
+bool accum_packed_shape_supported(int tu, int tv, int jc, int waves) {
+    if (waves < 1 || waves > 16) return false;
+#define X(a, b, c) \
+    if (tu == a && tv == b && jc == c) return (size_t)a * b * (c + 1) * 28 + 4 <= 160 * 1024;
+    VISTA_PACKED_SHAPES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, int64_t nunits,
+                               uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre,
+                               int grid, int waves, int npol, hipStream_t stream) {
+    if (waves < 1 || waves > 16) return hipErrorInvalidValue;
+#define X(a, b, c)                                                                                              \
+    if (L.tu == a && L.tv == b && L.jc == c) {                                                                  \
+        if (npol == 2)                                                                                          \
+            hipLaunchKernelGGL((k_accum_packed<a, b, c, 2>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
+                               order, nunits, counter, unit_off, recs, pre);                                    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_accum_packed<a, b, c, 0>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
+                               order, nunits, counter, unit_off, recs, pre);                                    \
+        return hipGetLastError();                                                                               \
+    }
+    VISTA_PACKED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol) {
+    int nb = 0;
+#define X(a, b, c)                                                                                               \
+    if (tu == a && tv == b && jc == c) {                                                                         \
+        hipError_t e = npol == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_packed<a, b, c, 2>, \
+                                                                               waves * kWave, 0)                 \
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_packed<a, b, c, 0>, \
+                                                                               waves * kWave, 0);                \
+        return e == hipSuccess ? nb : 0;                                                                         \
+    }
+    VISTA_PACKED_SHAPES(X)
+#undef X
+    return 0;
+}
+
+}  // namespace vista

@@ -45,8 +45,24 @@ struct DevTarget {
     int32_t kin_lo, kin_hi;   // hull of the channels with nj > 0
     int32_t nphase;           // lanes this many channels apart never share a rest channel
     int32_t nblocks;          // entries of blk
+    int32_t chan0;            // index of channel 0 in the launch-wide channel tables
     double l, m, nm1;         // direction cosines, n - 1
 };
+
+// Context of row g of a launch, written once by the binning pass and read by the packed
+// accumulation for every record of the row.
+struct RowCtx {
+    double U, V;              // uvw[r][0], uvw[r][1] [m]
+    double T;                 // U l + V m + W (n - 1) [m]: channel k's Eq. 2 phase is T a_k
+                              // turns (under the FP32-phase ablation: formed in FP32)
+    float w0, w1;             // row weights of polarisations 0 and 1 (npol == 2, row weights)
+    uint64_t vis;             // address of vis[r][0][0]
+    uint64_t flag;            // address of flag[r][0][0]; a zero row when there are no flags
+    uint64_t wrow;            // address of the row's first weight
+    int32_t chan0;            // launch-wide index of the target's channel 0
+    uint32_t info;            // npol | weight_per_chan << 8
+};
+static_assert(sizeof(RowCtx) == 64, "RowCtx is one 64-byte record");
 
 // One stack (grid) of a launch.
 struct DevStack {
@@ -84,6 +100,13 @@ struct LaunchDesc {
     int32_t carry;                    // 0: write outputs; 1: merge into carried state
     int32_t last_wave;                // with carry: also write outputs
     int32_t kahan;
+    // launch-wide channel tables (targets' tables are slices at their chan0) and row contexts
+    const DevChan* chan_all;
+    const float* f1_all;
+    const int32_t* foff_all;          // offsets into fval_all
+    const float* fval_all;
+    RowCtx* rowctx;                   // [nrows]
+    const uint8_t* zero_flags;        // a zero row for targets without flags
 };
 
 constexpr int kModeAtomic = 0;
@@ -102,6 +125,21 @@ hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint32_t* seg
 // unit_off[u] = first record of unit u in the sorted keys (u = 0..nunits).
 hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
                                int64_t nunits, uint32_t* unit_off, hipStream_t stream);
+// Per-record prefix of the records' channel counts: pre[i] = sum of (k_hi - k_lo) over the
+// sorted records before i (pre[nrec] = total); lens is nrec u32 of scratch.
+hipError_t launch_record_prefix(const uint64_t* recs, int64_t nrec, uint32_t* lens, uint64_t* pre, uint64_t* sums,
+                                hipStream_t stream);
+// Work list of the packed accumulation: units sorted by descending channel-sample count
+// (keys/vals: nunits entries each, sorted in place; vals end as the unit ids).
+hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, int64_t nunits, uint32_t* keys,
+                             uint64_t* vals, void* sort_temp, hipStream_t stream);
+// The packed accumulation (atomic mode): `grid` workgroups of `waves` wavefronts pull units
+// from *counter (zeroed first) in the order of `order` (u64 unit ids).
+hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, int64_t nunits,
+                               uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre,
+                               int grid, int waves, int npol, hipStream_t stream);
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol);
+bool accum_packed_shape_supported(int tu, int tv, int jc, int waves);
 // The accumulation over the work list `order` (global unit ids); `grid` workgroups of
 // `waves` wavefronts pull list entries from *counter (zeroed first).
 // npol == 2 when every target of the launch has two polarisations (specialised path).
@@ -119,6 +157,8 @@ hipError_t exclusive_scan_u32_to_u32(const uint32_t* in, const int64_t* n_dev, i
                                      uint64_t* sums, hipStream_t s);
 hipError_t exclusive_scan_u64(const uint64_t* in, const int64_t* n_dev, int64_t cap, uint64_t* out,
                               uint64_t* sums, hipStream_t s);
+hipError_t exclusive_scan_u32_to_u64(const uint32_t* in, const int64_t* n_dev, int64_t cap, uint64_t* out,
+                                     uint64_t* sums, hipStream_t s);
 size_t radix_sort_temp_bytes(int64_t cap);
 // Stable sort of (keys, vals) by the low `bits` bits of the keys, in place.
 hipError_t radix_sort_pairs(uint32_t* keys, uint64_t* vals, const int64_t* n_dev, int64_t cap, int bits,
@@ -126,6 +166,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint64_t* vals, const int64_t* n_dev
 hipError_t launch_debug_indices(const DevTarget* t, const DevStack* s, int32_t* iu, int32_t* iv,
                                 int32_t* j0, int32_t* nj, int64_t nrow, int32_t nchan,
                                 hipStream_t stream);
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t stream);
 hipError_t launch_debug_rotate(const DevTarget* t, float2* out, int64_t nrow, int32_t nchan, int32_t npol,
                                int phase_fp32, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);

@@ -17,32 +17,17 @@
 // iu = rint(u * (1/du)) + nu/2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
-#include "vista_internal.h"
+#include "vista_device.h"
 
 namespace vista {
 
 namespace {
 
-constexpr int kWave = 64;
 
-__device__ __forceinline__ int64_t find_le(const int64_t* base, int32_t n, int64_t x) {
-    // largest i in [0, n) with base[i] <= x (base non-decreasing, base[0] <= x)
-    int32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
-        if (base[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
-}
 
-// rint((c * a) * inv): the nearest-cell coordinate of the definition (two roundings,
-// then round half to even).
-__device__ __forceinline__ double cell_coord(double c, double a, double inv) {
-    double x = c * a;
-    return rint(x * inv);
-}
 
 // First k in [lo, hi) with s * rint((c * a_k) * inv) >= A, or hi.  The key is
 // non-decreasing in k for the given orientation s.
@@ -103,10 +88,6 @@ __device__ int32_t tile_run_end(const DevChan* ch, int32_t k, int32_t gb, double
     return min(nu_k, nv_k);
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
-}
 
 // ----------------------------------------------------------------------------- binning
 
@@ -126,6 +107,26 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
         stack_id = T.stack;
         int64_t r = g - T.row_base;
         uint32_t n = 0;
+        if (!emit && L.rowctx) {
+            // the row's context for the packed accumulation
+            const double U = T.uvw[3 * r], V = T.uvw[3 * r + 1], W = T.uvw[3 * r + 2];
+            RowCtx c;
+            c.U = U;
+            c.V = V;
+            if (L.phase_fp32)
+                c.T = (double)((float)U * (float)T.l + (float)V * (float)T.m + (float)W * (float)T.nm1);
+            else
+                c.T = U * T.l + V * T.m + W * T.nm1;
+            const size_t rs = (size_t)T.nchan * T.npol;     // samples per row
+            c.w0 = T.weight_per_chan ? 0.f : T.weight[r * T.npol];
+            c.w1 = (T.weight_per_chan || T.npol < 2) ? 0.f : T.weight[r * T.npol + 1];
+            c.vis = (uint64_t)(T.vis + r * rs);
+            c.flag = T.flag ? (uint64_t)(T.flag + r * rs) : (uint64_t)L.zero_flags;
+            c.wrow = (uint64_t)(T.weight + (T.weight_per_chan ? r * rs : r * T.npol));
+            c.chan0 = T.chan0;
+            c.info = (uint32_t)T.npol | ((uint32_t)(T.weight_per_chan != 0) << 8);
+            L.rowctx[g] = c;
+        }
         if (T.kin_lo < T.kin_hi) {
             double U = T.uvw[3 * r], V = T.uvw[3 * r + 1];
             Track tr = in_grid(T.chan, T.kin_lo, T.kin_hi, U, V, S.inv_du, S.inv_dv, S.nu, S.nv);
@@ -185,74 +186,14 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     if (i < n) p[i] = v;
 }
 
+// Plain 16-byte-vector copy: reads and writes every byte once (byte-counter calibration).
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------------ accumulation
 
-// (The host compilation pass only parses device code; address spaces exist on the device.)
-#if defined(__HIP_DEVICE_COMPILE__)
-#define VISTA_GLOBAL __attribute__((address_space(1)))
-#define VISTA_CONST __attribute__((address_space(4)))
-#else
-#define VISTA_GLOBAL
-#define VISTA_CONST
-#endif
-
-// Pointers read from descriptors are generic; casting them to the global address space
-// lets the compiler use global (not flat) memory instructions.
-template <class T>
-__device__ __forceinline__ const VISTA_GLOBAL T* gptr(const T* p) {
-    return (const VISTA_GLOBAL T*)p;
-}
-// Read-only data addressed uniformly across the wave (descriptors, a row's uvw and
-// weights): the constant address space lets the compiler use scalar loads.
-template <class T>
-__device__ __forceinline__ const VISTA_CONST T* cptr(const T* p) {
-    return (const VISTA_CONST T*)p;
-}
-
-__device__ __forceinline__ int32_t sgpr(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int j) {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// sin and cos of 2 pi x for x in [-1/2, 1/2] (an already range-reduced phase in turns).
-// x is split into quarter turns q and a remainder f in [-1/2, 1/2] (both exact), the
-// sine and cosine of pi f / 2 come from polynomials in f fitted by least squares on
-// Chebyshev nodes of [-1/2, 1/2] (max error about 8e-8 in FP32), and the quadrant is
-// applied by swapping and negating.
-__device__ __forceinline__ void sincos_turns(float x, float* sn, float* cs) {
-    float y = 4.0f * x;
-    float q = rintf(y);
-    float f = y - q;
-    float f2 = f * f;
-    float s = f * fmaf(f2, fmaf(f2, fmaf(f2, -4.583587870001793e-3f, 7.96719342470169e-2f), -6.459624171257019e-1f),
-                       1.570796251296997f);
-    float c = fmaf(f2, fmaf(f2, fmaf(f2, fmaf(f2, 9.021605364978313e-4f, -2.085929550230503e-2f),
-                                     2.536690831184387e-1f), -1.2337005138397217f), 1.0f);
-    int qi = (int)q & 3;
-    float a = (qi & 1) ? c : s;
-    float b = (qi & 1) ? s : c;
-    *sn = (qi & 2) ? -a : a;
-    *cs = ((qi + 1) & 2) ? -b : b;
-}
-
-// Phase of one channel: the Eq. 2 turns t = (u l + v m + w (n-1)) = trow * a_k formed and
-// reduced to [-1/2, 1/2] in FP64; sin/cos of 2 pi r in FP32.
-__device__ __forceinline__ void phasor(double trow, double a, float* c, float* s) {
-    double t = trow * a;
-    double r = t - rint(t);
-    sincos_turns((float)r, s, c);
-}
-
-// Ablation: turns formed from FP32 coordinates and reduced in FP32, so large arguments
-// lose their fractional part to FP32 rounding.
-__device__ __forceinline__ void phasor_fp32(float u, float v, float w, float l, float m, float nm1,
-                                            float* c, float* s) {
-    float t = u * l + v * m + w * nm1;
-    sincos_turns(t - rintf(t), s, c);
-}
 
 // LDS grid state of one unit: per cell sum(w f V') re/im, sum(w f) and the count.  The
 // sums are FP64 (LDS has native FP64 atomic adds, far faster than its FP32 ones on
@@ -422,8 +363,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict_
         const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
         if (li >= nunits) break;
         const int64_t unit = (uint32_t)sgpr((int32_t)gptr(order)[li]);
-        const int32_t si = sgpr((int32_t)find_le(L.stack_unit_base, L.nstacks, unit));
-        const DevStack& S = L.stacks[si];
+        const int32_t si = sgpr((int32_t)find_le_uniform(L.stack_unit_base, L.nstacks, unit));
+        const VISTA_CONST DevStack& S = cptr(L.stacks)[si];
         const int64_t local = unit - S.unit_base;
         const int64_t tile = local / S.nblocks;
         const int32_t b = (int32_t)(local - tile * S.nblocks);
@@ -677,62 +618,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict_
         }
         __syncthreads();
 
-        // write the (tile, block) cells: iu fastest, so stores are contiguous runs of TU
-        const int ncv = (jb1 - jb0) * TV * TU;
-        for (int i = threadIdx.x; i < ncv; i += blockDim.x) {
-            int lu = i % TU;
-            int lv = (i / TU) % TV;
-            int jl = i / (TU * TV);
-            int iu = tu0 + lu, iv = tv0 + lv;
-            if (iu >= S.nu || iv >= S.nv) continue;
-            int c = (lv * TU + lu) * JP + jl;
-            size_t o = ((size_t)(jb0 + jl) * S.nv + iv) * S.nu + iu;
-            double dre, dim, dw;
-            if (KAHAN) {
-                dre = (double)s_re[c] - (double)c_re[c];
-                dim = (double)s_im[c] - (double)c_im[c];
-                dw = (double)s_w[c] - (double)c_w[c];
-            } else {
-                dre = (double)s_re[c]; dim = (double)s_im[c]; dw = (double)s_w[c];
-            }
-            uint32_t n = s_n[c];
-            if (L.carry) {
-                // merge into the state carried across waves (this unit owns the cells)
-                size_t plane = (size_t)S.nchan * S.nv * S.nu;
-                float* sp = S.st_s;
-                float* cp = S.st_c;
-                double vals3[3] = {dre, dim, dw};
-                for (int q = 0; q < 3; ++q) {
-                    float x = (float)vals3[q];
-                    float sv = sp[q * plane + o];
-                    if (L.kahan) {
-                        float cc = cp[q * plane + o];
-                        float xl = (float)(vals3[q] - (double)x);   // keep the part lost to FP32
-                        float y = x - cc;
-                        float t = sv + y;
-                        cc = (t - sv) - y;
-                        sv = t;
-                        y = xl - cc; t = sv + y; cc = (t - sv) - y; sv = t;
-                        cp[q * plane + o] = cc;
-                        vals3[q] = (double)sv - (double)cc;
-                    } else {
-                        sv = sv + x;
-                        vals3[q] = sv;
-                    }
-                    sp[q * plane + o] = sv;
-                }
-                uint64_t nn = (uint64_t)S.st_n[o] + n;
-                if (nn > 0xffffffffull) atomicOr(&S.stats[7], 1ull);
-                S.st_n[o] = (uint32_t)nn;
-                if (!L.last_wave) continue;
-                dre = vals3[0]; dim = vals3[1]; dw = vals3[2]; n = (uint32_t)nn;
-            }
-            if (S.out_vis) S.out_vis[o] = make_float2((float)dre, (float)dim);
-            if (S.out_w) S.out_w[o] = (float)dw;
-            if (S.out_cnt) S.out_cnt[o] = n;
-            if (S.out_vis64) S.out_vis64[o] = make_double2(dre, dim);
-            if (S.out_w64) S.out_w64[o] = dw;
-        }
+        flush_unit<TU, TV, JP, Acc, KAHAN>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, c_re, c_im, c_w);
         __syncthreads();
     }
 }
@@ -799,6 +685,13 @@ hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_
     int64_t n = nrec_cap + 1;
     hipLaunchKernelGGL(k_unit_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sorted_keys,
                        nrec_dev, nrec_cap, nunits, unit_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t stream) {
+    if (n16 <= 0) return hipSuccess;
+    int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint4*)src, (uint4*)dst, n16);
     return hipGetLastError();
 }
 

@@ -168,6 +168,14 @@ struct Tuning {
     int tu = 4, tv = 4, jc = 256, waves = 16, wg_per_cu = 0;
 };
 
+// Launch shapes the kernels are built for: the packed kernel's (plain mode) or the
+// ordered kernel's (deterministic and compensated modes).
+static bool shape_ok(const Tuning& t, uint32_t flags) {
+    if (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN))
+        return accum_shape_supported(t.tu, t.tv, t.jc, t.waves, kModeOrdered, (flags & VISTA_F_KAHAN) ? 1 : 0);
+    return accum_packed_shape_supported(t.tu, t.tv, t.jc, t.waves);
+}
+
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
     if (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) {
@@ -270,7 +278,7 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     Events ev;
     const int mode = (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
     const int kahan = (flags & VISTA_F_KAHAN) ? 1 : 0;
-    if (!accum_shape_supported(tu.tu, tu.tv, tu.jc, tu.waves, mode, kahan))
+    if (!shape_ok(tu, flags))
         throw HipFail{hipErrorInvalidValue, "unsupported launch shape (tile/jblock/waves)"};
     const int jsub = mode == kModeOrdered ? tu.jc / tu.waves : tu.jc;
 
@@ -285,7 +293,12 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
         if (n) memcpy(arena.data() + off, p, n);
         return off;
     };
-    struct Offs { size_t chan, f1, foff, fval, blk, sblk, inband; };
+    struct Offs { size_t blk, sblk, inband; };
+    // launch-wide channel tables: target i's entries start at its chan0
+    std::vector<DevChan> chan_all;
+    std::vector<float> f1_all, fval_all;
+    std::vector<int32_t> foff_all;
+    int64_t zero_flag_bytes = 0;
     std::vector<Offs> offs;
     int64_t rows = 0, tiles = 0, nunits = 0;
     std::vector<int64_t> unit_base;
@@ -321,11 +334,15 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
             T.nphase = h->plan.nphase;
             T.nblocks = S.nblocks;
             T.l = h->t.l; T.m = h->t.m; T.nm1 = h->plan.nm1;
+            T.chan0 = (int32_t)chan_all.size();
+            chan_all.insert(chan_all.end(), h->plan.chan.begin(), h->plan.chan.end());
+            f1_all.insert(f1_all.end(), h->plan.f1.begin(), h->plan.f1.end());
+            for (int32_t f : h->plan.foff) foff_all.push_back(f + (int32_t)fval_all.size());
+            fval_all.insert(fval_all.end(), h->plan.fval.begin(), h->plan.fval.end());
+            if (!h->t.flag) zero_flag_bytes = std::max<int64_t>(zero_flag_bytes, (int64_t)h->t.nchan * h->t.npol);
+            if (chan_all.size() >= 0x7fffffffu || fval_all.size() >= 0x7fffffffu)
+                throw HipFail{hipErrorInvalidValue, "too many channels in one launch"};
             Offs o;
-            o.chan = put(h->plan.chan.data(), h->plan.chan.size() * sizeof(DevChan));
-            o.f1 = put(h->plan.f1.data(), h->plan.f1.size() * sizeof(float));
-            o.foff = put(h->plan.foff.data(), h->plan.foff.size() * sizeof(int32_t));
-            o.fval = put(h->plan.fval.data(), h->plan.fval.size() * sizeof(float));
             std::vector<int32_t> blk = block_ranges(h->plan, g->nchan, tu.jc);
             o.blk = put(blk.data(), blk.size() * sizeof(int32_t));
             if (jsub != tu.jc) {
@@ -377,13 +394,21 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
             }
         }
     }
-    unsigned char* d_arena = mem.alloc_n<unsigned char>(arena.size());
+    const size_t o_chan = put(chan_all.data(), chan_all.size() * sizeof(DevChan));
+    const size_t o_f1 = put(f1_all.data(), f1_all.size() * sizeof(float));
+    const size_t o_foff = put(foff_all.data(), foff_all.size() * sizeof(int32_t));
+    const size_t o_fval = put(fval_all.data(), fval_all.size() * sizeof(float));
+    unsigned char* d_arena = mem.alloc_n<unsigned char>(std::max<size_t>(arena.size(), 1));
     VISTA_HIP(hipMemcpyAsync(d_arena, arena.data(), arena.size(), hipMemcpyHostToDevice, stream));
+    const DevChan* d_chan = (const DevChan*)(d_arena + o_chan);
+    const float* d_f1 = (const float*)(d_arena + o_f1);
+    const int32_t* d_foff = (const int32_t*)(d_arena + o_foff);
+    const float* d_fval = (const float*)(d_arena + o_fval);
     for (size_t i = 0; i < dts.size(); ++i) {
-        dts[i].chan = (const DevChan*)(d_arena + offs[i].chan);
-        dts[i].f1 = (const float*)(d_arena + offs[i].f1);
-        dts[i].foff = (const int32_t*)(d_arena + offs[i].foff);
-        dts[i].fval = (const float*)(d_arena + offs[i].fval);
+        dts[i].chan = d_chan + dts[i].chan0;
+        dts[i].f1 = d_f1 + dts[i].chan0;
+        dts[i].foff = d_foff + dts[i].chan0;
+        dts[i].fval = d_fval;
         dts[i].blk = (const int32_t*)(d_arena + offs[i].blk);
         dts[i].sblk = (const int32_t*)(d_arena + offs[i].sblk);
         dts[i].inband = (const int32_t*)(d_arena + offs[i].inband);
@@ -425,6 +450,20 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     L.mode = mode;
     L.kahan = kahan;
     L.phase_fp32 = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
+    L.chan_all = d_chan;
+    L.f1_all = d_f1;
+    L.foff_all = d_foff;
+    L.fval_all = d_fval;
+    const bool packed = mode == kModeAtomic;
+    if (packed && rows > 0) {
+        L.rowctx = mem.alloc_n<RowCtx>(rows);
+        if (zero_flag_bytes > 0) {
+            int64_t words = (zero_flag_bytes + 3) / 4;
+            uint32_t* z = mem.alloc_n<uint32_t>(words);
+            check_launch(launch_fill_u32(z, 0u, words, stream), "fill");
+            L.zero_flags = (const uint8_t*)z;
+        }
+    }
     LaunchDesc* d_L = mem.alloc_n<LaunchDesc>(1);
     VISTA_HIP(hipMemcpyAsync(d_L, &L, sizeof(L), hipMemcpyHostToDevice, stream));
 
@@ -457,6 +496,35 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     }
     if (nrec == 0) check_launch(launch_fill_u32(unit_off, 0u, nunits + 1, stream), "fill");
 
+    if (packed) {
+        // ---- record starts in the units' sample streams, and the work list: every unit of
+        // every stack (units without records still write their zero cells), most samples
+        // first, all on the device
+        uint64_t* pre = mem.alloc_n<uint64_t>(nrec + 1);
+        {
+            uint32_t* lens = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nrec));
+            uint64_t* sums = mem.alloc_n<uint64_t>(scan_temp_elems(nrec));
+            check_launch(launch_record_prefix(vals, nrec, lens, pre, sums, stream), "record prefix");
+        }
+        uint32_t* okeys = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nunits));
+        uint64_t* order = mem.alloc_n<uint64_t>(std::max<int64_t>(1, nunits));
+        void* otmp = mem.alloc(radix_sort_temp_bytes(std::max<int64_t>(1, nunits)));
+        check_launch(launch_unit_order(unit_off, pre, nunits, okeys, order, otmp, stream), "unit order");
+        uint32_t* counter = mem.alloc_n<uint32_t>(1);
+        check_launch(launch_fill_u32(counter, 0u, 1, stream), "fill");
+        if (!vals) vals = mem.alloc_n<uint64_t>(1);
+        VISTA_HIP(hipEventRecord(ev.e[1], stream));
+        int npol_all = 2;
+        for (auto& T : dts)
+            if (T.npol != 2 || T.weight_per_chan) npol_all = 0;   // the specialised path: 2 pols, row weights
+        int per_cu = tu.wg_per_cu > 0 ? tu.wg_per_cu
+                                      : accum_packed_max_blocks_per_cu(tu.tu, tu.tv, tu.jc, tu.waves, npol_all);
+        if (per_cu < 1) per_cu = 1;
+        int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, nunits));
+        check_launch(launch_accum_packed(L, d_L, order, nunits, counter, unit_off, vals, pre, (int)grid, tu.waves,
+                                         npol_all, stream),
+                     "accumulate");
+    } else {
     // ---- work list: every (tile, block) unit of every stack, heaviest first (units
     // without records still write their zero cells)
     std::vector<uint32_t> uoff(nunits + 1);
@@ -484,6 +552,7 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     check_launch(launch_accum_impl(L, d_L, d_order, nunits, counter, unit_off, vals, (int)grid, tu.waves, npol_all,
                                    stream),
                  "accumulate");
+    }
     VISTA_HIP(hipEventRecord(ev.e[2], stream));
 
     std::vector<unsigned long long> st(8 * jobs.size());
@@ -623,8 +692,7 @@ int vista_stack_set_tuning(vista_stack* s, const vista_tuning* tu) {
     if (!s) return fail(VISTA_E_ARG, "stack is NULL");
     if (s->state != 0) return fail(VISTA_E_STATE, "stack is not open");
     Tuning t = merge_tuning(default_tuning(s->g.flags), tu);
-    int mode = (s->g.flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
-    if (!accum_shape_supported(t.tu, t.tv, t.jc, t.waves, mode, (s->g.flags & VISTA_F_KAHAN) ? 1 : 0))
+    if (!shape_ok(t, s->g.flags))
         return fail(VISTA_E_ARG, "unsupported tuning (tile_u, tile_v, jblock, waves)");
     s->tune = t;
     s->tune_set = tu != nullptr;
@@ -761,6 +829,18 @@ int vista_debug_rotate(const vista_grid_desc* g, const vista_target* t, void* hi
     });
 }
 
+int vista_debug_copy(void* dst, const void* src, size_t nbytes, void* hip_stream) {
+    if (!dst || !src) return fail(VISTA_E_ARG, "NULL pointer");
+    if ((nbytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(VISTA_E_ARG, "vista_debug_copy needs 16-byte aligned pointers and size");
+    const uintptr_t d = (uintptr_t)dst, s = (uintptr_t)src;
+    if (d < s + nbytes && s < d + nbytes) return fail(VISTA_E_ARG, "regions overlap");
+    return guarded(nullptr, [&]() -> int {
+        check_launch(launch_copy16(dst, src, (int64_t)(nbytes / 16), (hipStream_t)hip_stream), "copy");
+        return VISTA_OK;
+    });
+}
+
 // ---------------------------------------------------------------------------- batch
 
 int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_stream, vista_batch** out) {
@@ -806,8 +886,7 @@ int vista_batch_set_tuning(vista_batch* b, const vista_tuning* tu) {
     if (!b) return fail(VISTA_E_ARG, "batch is NULL");
     if (b->state != 0) return fail(VISTA_E_STATE, "batch already ran");
     Tuning t = merge_tuning(default_tuning(b->g[0].flags), tu);
-    int mode = (b->g[0].flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
-    if (!accum_shape_supported(t.tu, t.tv, t.jc, t.waves, mode, (b->g[0].flags & VISTA_F_KAHAN) ? 1 : 0))
+    if (!shape_ok(t, b->g[0].flags))
         return fail(VISTA_E_ARG, "unsupported tuning (tile_u, tile_v, jblock, waves)");
     b->tune = t;
     b->tune_set = tu != nullptr;

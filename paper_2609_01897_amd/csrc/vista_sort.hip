@@ -187,6 +187,11 @@ hipError_t exclusive_scan_u64(const uint64_t* in, const int64_t* n_dev, int64_t 
     return scan_impl<uint64_t, uint64_t>(in, n_dev, cap, out, sums, s);
 }
 
+hipError_t exclusive_scan_u32_to_u64(const uint32_t* in, const int64_t* n_dev, int64_t cap, uint64_t* out,
+                                     uint64_t* sums, hipStream_t s) {
+    return scan_impl<uint32_t, uint64_t>(in, n_dev, cap, out, sums, s);
+}
+
 hipError_t exclusive_scan_u32_to_u32(const uint32_t* in, const int64_t* n_dev, int64_t cap, uint32_t* out,
                                      uint64_t* sums, hipStream_t s) {
     return scan_impl<uint32_t, uint32_t>(in, n_dev, cap, out, sums, s);

@@ -89,6 +89,7 @@ SYMBOLS = {
     "vista_debug_indices": ([C.POINTER(GridDesc), C.POINTER(TargetDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
     "vista_debug_rotate": ([C.POINTER(GridDesc), C.POINTER(TargetDesc), C.c_void_p, C.c_void_p], C.c_int),
+    "vista_debug_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "vista_last_error": ([], C.c_char_p),
     "vista_version": ([], C.c_char_p),
 }
@@ -315,6 +316,15 @@ def debug_rotate(grid: dict, t, flags: int | None = None, stream=None):
     s = current_stream() if stream is None else stream
     _check(lib().vista_debug_rotate(C.byref(g), C.byref(d), s, _ptr(out)))
     return out
+
+
+def debug_copy(dst, src, stream=None):
+    """dst <- src (same byte size) by the library's plain copy kernel."""
+    n = dst.numel() * dst.element_size()
+    if n != src.numel() * src.element_size():
+        raise ValueError("sizes differ")
+    s = current_stream() if stream is None else stream
+    _check(lib().vista_debug_copy(_ptr(dst), _ptr(src), n, s))
 
 
 def plan_spectral_grid(chan_freqs, chan_widths, zs, central_freq: float, nchan_out: int):
