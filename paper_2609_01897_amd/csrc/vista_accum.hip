@@ -55,26 +55,6 @@ struct RecCtx {
     uint32_t end;
 };
 
-template <int NPOL>
-__device__ __forceinline__ RecCtx<NPOL> gather(const RecCtx<NPOL>& w, int src) {
-    RecCtx<NPOL> c;
-    c.U = bpermd(w.U, src);
-    c.V = bpermd(w.V, src);
-    c.T = bpermd(w.T, src);
-    if (NPOL == 2) {
-        c.w0 = bpermf(w.w0, src);
-        c.w1 = bpermf(w.w1, src);
-    } else {
-        c.wadj = bperm64(w.wadj, src);
-        c.info = bperm(w.info, src);
-    }
-    c.vis = bperm64(w.vis, src);
-    c.flag = bperm64(w.flag, src);
-    c.chan = (int32_t)bperm((uint32_t)w.chan, src);
-    c.end = bperm(w.end, src);
-    return c;
-}
-
 // What one sample loaded.
 template <int NPOL>
 struct Loaded {
@@ -86,12 +66,15 @@ struct Loaded {
     float wc[NPOL == 2 ? 1 : 4];
 };
 
-// One lane's pair of samples of a chunk: positions pos and pos + 1 of one record.
+// One lane's pair of samples of a chunk: positions pos and pos + 1 of one record.  Only the
+// record's window lane is carried while the loads are in flight; the record's coordinates
+// and weights are gathered again when the pair is processed.
 template <int NPOL>
 struct Pair {
-    RecCtx<NPOL> c;
+    int rec;                   // window lane of the record
     uint32_t pos;              // stream position relative to the window origin
-    bool act;                  // inside the wavefront's range
+    bool act;                  // the first sample is inside the wavefront's range
+    bool two;                  // so is the second (not the padding of an odd record)
     Loaded<NPOL> s[2];
 };
 
@@ -100,16 +83,26 @@ __device__ __forceinline__ T gload(uint64_t addr) {
     return *(const VISTA_GLOBAL T*)addr;
 }
 
+// Loads of one sample.  Nothing here looks at the loaded values: the loads of the next
+// chunk stay in flight while the current one is processed.
+// Addresses of a record's samples (see RecCtx), gathered for issuing a chunk's loads.
+template <int NPOL>
+struct Bases {
+    uint64_t vis, flag, wadj;
+    uint32_t info;
+    int32_t chan;
+};
+
 template <int NPOL>
 __device__ __forceinline__ void load_sample(const VISTA_GLOBAL DevChan* chan_all, const VISTA_GLOBAL float* f1_all,
-                                            const RecCtx<NPOL>& c, uint32_t p, bool valid, Loaded<NPOL>& x) {
+                                            const Bases<NPOL>& c, uint32_t p, Loaded<NPOL>& x) {
     const int32_t ci = c.chan + (int32_t)p;
     const uint4 ch = *(const VISTA_GLOBAL uint4*)(chan_all + ci);
     x.a = __builtin_bit_cast(double, ((uint64_t)ch.y << 32) | ch.x);
-    x.jn = valid ? ch.z : 0u;
+    x.jn = ch.z;
     x.f0 = __builtin_bit_cast(float, ch.w);
     x.f1 = f1_all[ci];
-    if (NPOL == 2) {
+    if constexpr (NPOL == 2) {
         const float4 v = gload<float4>(c.vis + (uint64_t)p * 16u);
         x.vr[0] = v.x; x.vi[0] = v.y; x.vr[1] = v.z; x.vi[1] = v.w;
         x.fl = gload<uint16_t>(c.flag + (uint64_t)p * 2u);
@@ -137,47 +130,69 @@ __device__ __forceinline__ void load_sample(const VISTA_GLOBAL DevChan* chan_all
     }
 }
 
-// Both samples of a lane's pair; the second one of a record with an odd channel count is
-// padding: it re-reads the first (always in bounds) and adds nothing.
+// Mark every loaded value of a sample as used, at one point, before any branch: a load
+// whose result some path never reads stays "pending" for the compiler, which then waits
+// for all loads in flight before that register is next written.
 template <int NPOL>
-__device__ __forceinline__ void issue(const VISTA_GLOBAL DevChan* chan_all, const VISTA_GLOBAL float* f1_all,
-                                      Pair<NPOL>& x) {
-    if (!x.act) {                 // lanes past the range read nothing
-        for (int i = 0; i < 2; ++i) {
-            Loaded<NPOL>& y = x.s[i];
-            y.a = 0.0; y.jn = 0u; y.f0 = 0.f; y.f1 = 0.f; y.fl = 0u;
-            for (int q = 0; q < (NPOL == 2 ? 2 : 4); ++q) { y.vr[q] = 0.f; y.vi[q] = 0.f; }
-            for (int q = 0; q < (NPOL == 2 ? 1 : 4); ++q) y.wc[q] = 0.f;
-        }
-        return;
+__device__ __forceinline__ void settle(const Loaded<NPOL>& x) {
+    __asm__ volatile("" ::"v"(x.a), "v"(x.jn), "v"(x.f0), "v"(x.f1), "v"(x.fl));
+#pragma unroll
+    for (int q = 0; q < (NPOL == 2 ? 2 : 4); ++q) __asm__ volatile("" ::"v"(x.vr[q]), "v"(x.vi[q]));
+    if constexpr (NPOL != 2) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) __asm__ volatile("" ::"v"(x.wc[q]));
     }
-    const bool two = x.pos + 1u < x.c.end;
-    load_sample<NPOL>(chan_all, f1_all, x.c, x.pos, true, x.s[0]);
-    load_sample<NPOL>(chan_all, f1_all, x.c, two ? x.pos + 1u : x.pos, two, x.s[1]);
 }
 
-// Per-wavefront classification and contribution counts, kept over many units and added to
-// the stack's statistics when the stack changes, every 64 units and at the end.
+template <int NPOL>
+__device__ __forceinline__ Bases<NPOL> gather_bases(const RecCtx<NPOL>& w, int src) {
+    Bases<NPOL> c;
+    c.vis = bperm64(w.vis, src);
+    c.flag = bperm64(w.flag, src);
+    c.chan = (int32_t)bperm((uint32_t)w.chan, src);
+    if (NPOL != 2) {
+        c.wadj = bperm64(w.wadj, src);
+        c.info = bperm(w.info, src);
+    }
+    return c;
+}
+
+// Both samples of a lane's pair.  Every lane loads from inside its record: a lane past the
+// wavefront's range reads the record's last sample, the padding of an odd record re-reads
+// the first; process() ignores what they read.  Nothing here looks at loaded values.
+template <int NPOL>
+__device__ __forceinline__ void issue(const VISTA_GLOBAL DevChan* chan_all, const VISTA_GLOBAL float* f1_all,
+                                      const RecCtx<NPOL>& w, Pair<NPOL>& x) {
+    const Bases<NPOL> c = gather_bases<NPOL>(w, x.rec);
+    const uint32_t end = bperm(w.end, x.rec);
+    x.two = x.act && x.pos + 1u < end;
+    const uint32_t p0 = x.act ? x.pos : end - 1u;
+    const uint32_t p1 = x.two ? x.pos + 1u : p0;
+    load_sample<NPOL>(chan_all, f1_all, c, p0, x.s[0]);
+    load_sample<NPOL>(chan_all, f1_all, c, p1, x.s[1]);
+}
+
+// Per-wavefront classification and contribution counts (wave-uniform, from ballots), kept
+// over many units and added to the stack's statistics when the stack changes, every 64
+// units and at the end.
 struct WaveStats {
-    uint32_t flag = 0, bad = 0, used = 0, contrib = 0;
+    uint64_t flag = 0, bad = 0, used = 0, contrib = 0;
     int32_t stack = -1;
     uint32_t units = 0;
     __device__ void flush(const LaunchDesc& L, int lane) {
-        const unsigned long long t_flag = wave_sum_u64(flag);
-        const unsigned long long t_bad = wave_sum_u64(bad);
-        const unsigned long long t_used = wave_sum_u64(used);
-        const unsigned long long t_contrib = wave_sum_u64(contrib);
         if (lane == 0 && stack >= 0) {
             unsigned long long* st = cptr(L.stacks)[stack].stats;
-            if (t_flag) atomicAdd(&st[1], t_flag);
-            if (t_bad) atomicAdd(&st[2], t_bad);
-            if (t_used) atomicAdd(&st[5], t_used);
-            if (t_contrib) atomicAdd(&st[6], t_contrib);
+            if (flag) atomicAdd(&st[1], (unsigned long long)flag);
+            if (bad) atomicAdd(&st[2], (unsigned long long)bad);
+            if (used) atomicAdd(&st[5], (unsigned long long)used);
+            if (contrib) atomicAdd(&st[6], (unsigned long long)contrib);
         }
         flag = bad = used = contrib = 0;
         units = 0;
     }
 };
+
+__device__ __forceinline__ uint64_t popc_ballot(bool p) { return (uint64_t)__popcll(__ballot(p)); }
 
 template <int TU, int TV, int JC, int NPOL>
 __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __restrict__ Lp,
@@ -244,7 +259,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 
         const uint32_t rb = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit]);
         const uint32_t re = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit + 1]);
-        uint32_t u_contrib = 0;
+        uint64_t u_contrib = 0;           // wave-uniform (ballots)
+        uint32_t u_contrib_l = 0;         // per lane (rest channels beyond j0 + 1)
         uint64_t sw0 = 0, sw1 = 0;
         if (rb < re) {
             // the unit's stream, in pairs, split evenly over the wavefronts
@@ -312,53 +328,65 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     w.wadj = rc.wrow + (wpc ? (uint64_t)(d * np * 4) : 0ull);
                     w.info = (uint32_t)np | ((wpc ? (uint32_t)np * 4u : 0u) << 8);
                 }
+                // the first chunk needs the window anyway; waiting here also tells the
+                // compiler that no window load is pending in the chunk loop, where it
+                // would otherwise wait for every load in flight before each gather
+                __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
             };
-            // lanes of the chunk starting at s (two samples each): records and contexts
-            auto map = [&](uint64_t s, Pair<NPOL>& x) __attribute__((always_inline)) {
-                const uint64_t need = min(s + (uint64_t)kChunk, sw1);
-                if (need > wend) {
-                    load_window(wb + cur);     // restart the window at the record holding s
-                    cur = 0;
-                }
+            // lanes of the chunk starting at s (two samples each): records and contexts.
+            // live == false: an idle chunk (every lane inactive, the window cursor kept) whose
+            // lanes load from the record at the cursor.
+            auto map = [&](uint64_t s, Pair<NPOL>& x, bool live) __attribute__((always_inline)) {
                 const uint32_t srel = (uint32_t)(s - pw);
                 const uint32_t pos = srel + 2u * (uint32_t)lane;
-                // records starting in (s, s + 128]: the last one at or before a lane's pair wins
-                const uint64_t B = __ballot(lane > (int)cur && wrel <= srel + kChunk);
-                int rec = (int)cur;
-                uint64_t m = B;
-                while (m) {
-                    const int i = __builtin_ctzll(m);
-                    m &= m - 1;
-                    const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane((int)wrel, i);
-                    rec = pos >= pi ? i : rec;
+                // (an idle chunk may find the cursor one past the window: use its last record)
+                int rec = live ? (int)cur : (int)min(cur, nwin - 1u);
+                if (live) {
+                    // records starting in (s, s + 128]: the last one at or before a lane's
+                    // pair wins
+                    const uint64_t B = __ballot(lane > (int)cur && wrel <= srel + kChunk);
+                    uint64_t m = B;
+                    while (m) {
+                        const int i = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane((int)wrel, i);
+                        rec = pos >= pi ? i : rec;
+                    }
+                    cur += (uint32_t)__popcll(B);
                 }
-                cur += (uint32_t)__popcll(B);
-                x.c = gather<NPOL>(w, rec);
+                x.rec = rec;
                 x.pos = pos;
-                x.act = s + 2u * (uint64_t)lane < sw1;
+                x.act = live && s + 2u * (uint64_t)lane < sw1;
             };
 
-            auto process = [&](const RecCtx<NPOL>& rc, const Loaded<NPOL>& x, int32_t ci) __attribute__((always_inline)) {
-                const uint32_t nj = x.jn >> 24;
+            // one sample: g0, g1 tell whether the record's row weights are usable (NPOL == 2)
+            auto process = [&](const RecCtx<NPOL>& rc, const Loaded<NPOL>& x, bool valid, int32_t ci, bool g0,
+                               bool g1) __attribute__((always_inline)) {
+                const uint32_t nj = valid ? x.jn >> 24 : 0u;
                 const int32_t j0 = (int32_t)(x.jn & kJMask);
                 // cell within the tile (exact FP64 sequence of the definition)
                 const double ru = cell_coord(rc.U, x.a, inv_du);
                 const double rv = cell_coord(rc.V, x.a, inv_dv);
                 const int32_t lu = (int32_t)ru + cu, lv = (int32_t)rv + cv;
                 const bool in_tile = nj > 0 && (uint32_t)lu < ntu && (uint32_t)lv < ntv;
+                const bool home = in_tile && j0 >= jb0 && j0 < jb1;    // counted once, in j0's block
                 // polarisations: drop flagged and bad-weight samples, merge the rest
                 float ar = 0.f, ai = 0.f, q = 0.f;
-                uint32_t n = 0, nflag = 0, nbad = 0;
+                uint32_t n = 0;
                 const int np = NPOL == 2 ? 2 : (int)(rc.info & 0xffu);
+                bool use_p[NPOL == 2 ? 2 : 4];
 #pragma unroll
                 for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p) {
                     const bool live = NPOL == 2 || p < np;
                     const float wgt = NPOL == 2 ? (p == 0 ? rc.w0 : rc.w1) : x.wc[p];
                     const bool flagged = live && ((x.fl >> (8 * p)) & 0xffu) != 0u;
-                    const bool good = live && (wgt > 0.0f) && (wgt < __builtin_inff());
-                    nflag += flagged ? 1u : 0u;
-                    nbad += (live && !flagged && !good) ? 1u : 0u;
+                    const bool good = NPOL == 2 ? (p == 0 ? g0 : g1)
+                                                : (live && (wgt > 0.0f) && (wgt < __builtin_inff()));
+                    ws.flag += popc_ballot(home && flagged);
+                    ws.bad += popc_ballot(home && live && !flagged && !good);
                     const bool use = !flagged && good;
+                    use_p[p] = use;
+                    ws.used += popc_ballot(home && use);
                     const float wu = use ? wgt : 0.0f;
                     n += use ? 1u : 0u;
                     ar = fmaf(wu, x.vr[p], ar);
@@ -374,26 +402,25 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 }
                 const float pr = ar * c - ai * s;
                 const float pi = fmaf(ar, s, ai * c);
-                // classification is counted once, in the block holding j0
-                if (in_tile && j0 >= jb0 && j0 < jb1) {
-                    ws.flag += nflag;
-                    ws.bad += nbad;
-                    ws.used += n;
-                }
-                if (!(in_tile && n > 0)) return;
+                // rest channels j0 and j0 + 1 of this unit's block (counted before any lane leaves)
+                const bool live_add = in_tile && n > 0;
+                const bool add0 = live_add && j0 >= jb0 && j0 < jb1;
+                const bool add1 = live_add && nj > 1 && j0 + 1 >= jb0 && j0 + 1 < jb1;
+#pragma unroll
+                for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p)
+                    u_contrib += popc_ballot(add0 && use_p[p]) + popc_ballot(add1 && use_p[p]);
+                if (!live_add) return;
                 const int cell = (lv * TU + lu) * JP - jb0;
                 const double dr = (double)pr, di = (double)pi, dq = (double)q;
 #pragma unroll
                 for (int qq = 0; qq < 2; ++qq) {
-                    const int32_t j = j0 + qq;
-                    if (qq < (int)nj && j >= jb0 && j < jb1) {
+                    if (qq == 0 ? add0 : add1) {
                         const double f = (double)(qq == 0 ? x.f0 : x.f1);
-                        const int cc = cell + j;
+                        const int cc = cell + j0 + qq;
                         atomicAdd(&s_re[cc], f * dr);          // exact products of FP32 values
                         atomicAdd(&s_im[cc], f * di);
                         atomicAdd(&s_w[cc], f * dq);
                         atomicAdd(&s_n[cc], n);
-                        u_contrib += n;
                     }
                 }
                 // more than two rest channels (rest grid finer than the channel): rare
@@ -408,46 +435,73 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                         atomicAdd(&s_im[cc], f * di);
                         atomicAdd(&s_w[cc], f * dq);
                         atomicAdd(&s_n[cc], n);
-                        u_contrib += n;
+                        u_contrib_l += n;
                     }
                 }
             };
             auto process_pair = [&](const Pair<NPOL>& x) __attribute__((always_inline)) {
-                const int32_t ci = x.c.chan + (int32_t)x.pos;
-                process(x.c, x.s[0], ci);
-                process(x.c, x.s[1], ci + 1);
+                settle<NPOL>(x.s[0]);
+                settle<NPOL>(x.s[1]);
+                RecCtx<NPOL> rc;
+                rc.U = bpermd(w.U, x.rec);
+                rc.V = bpermd(w.V, x.rec);
+                rc.T = bpermd(w.T, x.rec);
+                bool g0 = false, g1 = false;
+                if (NPOL == 2) {
+                    rc.w0 = bpermf(w.w0, x.rec);
+                    rc.w1 = bpermf(w.w1, x.rec);
+                    g0 = (rc.w0 > 0.0f) && (rc.w0 < __builtin_inff());
+                    g1 = (rc.w1 > 0.0f) && (rc.w1 < __builtin_inff());
+                } else {
+                    rc.info = bperm(w.info, x.rec);
+                }
+                const int32_t ci = (int32_t)bperm((uint32_t)w.chan, x.rec) + (int32_t)x.pos;
+                process(rc, x.s[0], x.act, ci, g0, g1);
+                process(rc, x.s[1], x.two, ci + 1, g0, g1);
             };
 
-            // ---- chunks, the next one's loads in flight while one is processed
+            // ---- chunks, the next one's loads in flight while one is processed.  A chunk is
+            // mapped only when the window holds all of its records; the window is reloaded
+            // between runs of chunks, so no other load sits among the chunks' loads.
+            // (After a reload at the record holding s, the window reaches at least 128
+            // positions past s: records take whole pairs and s is even.)
+            auto fits = [&](uint64_t t) __attribute__((always_inline)) {
+                return t < sw1 && min(t + (uint64_t)kChunk, sw1) <= wend;
+            };
             load_window(first);
             cur = 0;
-            Pair<NPOL> x0, x1;
             uint64_t s = sw0;
-            map(s, x0);
-            issue<NPOL>(chan_all, f1_all, x0);
+            // the next chunks, or, at the end of a run, idle ones: the loads are issued on
+            // every path, so the wait before processing a chunk is for its own loads only
+            auto next = [&](bool live, uint64_t t, Pair<NPOL>& x) __attribute__((always_inline)) {
+                map(live ? t : wend - 2u, x, live);
+                issue<NPOL>(chan_all, f1_all, w, x);
+            };
             for (;;) {
-                const bool more1 = s + kChunk < sw1;
-                if (more1) {
-                    map(s + kChunk, x1);
-                    issue<NPOL>(chan_all, f1_all, x1);
+                // two chunks in the pipeline: one processed while the next one's loads fly
+                Pair<NPOL> x0, x1;
+                next(true, s, x0);
+                for (;;) {
+                    const bool l1 = fits(s + kChunk);
+                    next(l1, s + kChunk, x1);
+                    process_pair(x0);
+                    s += kChunk;
+                    if (!l1) break;
+                    const bool l0 = fits(s + kChunk);
+                    next(l0, s + kChunk, x0);
+                    process_pair(x1);
+                    s += kChunk;
+                    if (!l0) break;
                 }
-                process_pair(x0);
-                if (!more1) break;
-                s += kChunk;
-                const bool more0 = s + kChunk < sw1;
-                if (more0) {
-                    map(s + kChunk, x0);
-                    issue<NPOL>(chan_all, f1_all, x0);
-                }
-                process_pair(x1);
-                if (!more0) break;
-                s += kChunk;
+                if (s >= sw1) break;
+                load_window(wb + cur);         // the record holding s and the 63 after it
+                cur = 0;
             }
         }
-        ws.contrib += u_contrib;
 
         // a cell count can wrap only if the unit's contributions reach 2^32
-        const unsigned long long t_contrib = wave_sum_u64(u_contrib);
+        const unsigned long long t_contrib = u_contrib + wave_sum_u64(u_contrib_l);
+        ws.contrib += t_contrib;
         if (lane == 0 && t_contrib) atomicAdd(&s_contrib, t_contrib);
         __syncthreads();
         if (threadIdx.x == 0) {

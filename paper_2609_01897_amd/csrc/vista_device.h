@@ -74,25 +74,12 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int j) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// sin and cos of 2 pi x for x in [-1/2, 1/2] (an already range-reduced phase in turns).
-// x is split into quarter turns q and a remainder f in [-1/2, 1/2] (both exact), the
-// sine and cosine of pi f / 2 come from polynomials in f fitted by least squares on
-// Chebyshev nodes of [-1/2, 1/2] (max error about 8e-8 in FP32), and the quadrant is
-// applied by swapping and negating.
+// sin and cos of 2 pi x for x in [-1/2, 1/2] (an already range-reduced phase in turns),
+// from the hardware's FP32 sine and cosine, which take their argument in turns (measured
+// maximum absolute error on this range: 1.3e-7).
 __device__ __forceinline__ void sincos_turns(float x, float* sn, float* cs) {
-    float y = 4.0f * x;
-    float q = rintf(y);
-    float f = y - q;
-    float f2 = f * f;
-    float s = f * fmaf(f2, fmaf(f2, fmaf(f2, -4.583587870001793e-3f, 7.96719342470169e-2f), -6.459624171257019e-1f),
-                       1.570796251296997f);
-    float c = fmaf(f2, fmaf(f2, fmaf(f2, fmaf(f2, 9.021605364978313e-4f, -2.085929550230503e-2f),
-                                     2.536690831184387e-1f), -1.2337005138397217f), 1.0f);
-    int qi = (int)q & 3;
-    float a = (qi & 1) ? c : s;
-    float b = (qi & 1) ? s : c;
-    *sn = (qi & 2) ? -a : a;
-    *cs = ((qi + 1) & 2) ? -b : b;
+    *sn = __builtin_amdgcn_sinf(x);
+    *cs = __builtin_amdgcn_cosf(x);
 }
 
 // Phase of one channel: the Eq. 2 turns t = (u l + v m + w (n-1)) = trow * a_k formed and

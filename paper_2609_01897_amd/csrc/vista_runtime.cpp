@@ -165,7 +165,7 @@ static void copy_target(HostTarget& h, const vista_grid_desc* g, const vista_tar
 }
 
 struct Tuning {
-    int tu = 4, tv = 4, jc = 256, waves = 16, wg_per_cu = 0;
+    int tu = 8, tv = 4, jc = 128, waves = 16, wg_per_cu = 0;
 };
 
 // Launch shapes the kernels are built for: the packed kernel's (plain mode) or the
