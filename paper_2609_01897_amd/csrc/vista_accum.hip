@@ -196,7 +196,7 @@ __device__ __forceinline__ uint64_t popc_ballot(bool p) { return (uint64_t)__pop
 
 template <int TU, int TV, int JC, int NPOL>
 __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __restrict__ Lp,
-                                                          const uint64_t* __restrict__ order, int64_t nunits,
+                                                          const uint64_t* __restrict__ order,
                                                           uint32_t* __restrict__ counter,
                                                           const uint32_t* __restrict__ unit_off,
                                                           const uint64_t* __restrict__ recs,
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
     __syncthreads();
     for (;;) {
         const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
-        if (li >= nunits) break;
+        if (li >= L.nunits) break;
         const int64_t unit = (int64_t)ufl64(cptr(order)[li]);
         const int32_t si = sgpr((int32_t)find_le_uniform(L.stack_unit_base, L.nstacks, unit));
         const VISTA_CONST DevStack& S = cptr(L.stacks)[si];
@@ -518,9 +518,10 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 
 // ---------------------------------------------------------------- record prefix, order
 
-__global__ void k_record_lens(const uint64_t* __restrict__ recs, int64_t n, uint32_t* __restrict__ lens) {
+__global__ void k_record_lens(const uint64_t* __restrict__ recs, const int64_t* __restrict__ n_dev,
+                              uint32_t* __restrict__ lens) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    if (i < *n_dev) {
         const uint64_t r = recs[i];
         const uint32_t len = (uint32_t)(r & 0xffffu) - (uint32_t)((r >> 16) & 0xffffu);
         lens[i] = (len + 1u) & ~1u;        // records take whole pairs of stream positions
@@ -528,10 +529,11 @@ __global__ void k_record_lens(const uint64_t* __restrict__ recs, int64_t n, uint
 }
 
 // key: descending sample count (saturated), value: unit id
-__global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_t* __restrict__ pre, int64_t nunits,
-                            uint32_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+__global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_t* __restrict__ pre,
+                            const int64_t* __restrict__ nunits_dev, uint32_t* __restrict__ keys,
+                            uint64_t* __restrict__ vals) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < nunits) {
+    if (u < *nunits_dev) {
         const uint64_t ns = pre[unit_off[u + 1]] - pre[unit_off[u]];
         keys[u] = 0xffffffffu - (uint32_t)min(ns, (uint64_t)0xffffffffu);
         vals[u] = (uint64_t)u;
@@ -540,20 +542,20 @@ __global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_
 
 }  // namespace
 
-hipError_t launch_record_prefix(const uint64_t* recs, int64_t nrec, uint32_t* lens, uint64_t* pre, uint64_t* sums,
-                                hipStream_t stream) {
-    if (nrec > 0)
-        hipLaunchKernelGGL(k_record_lens, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, stream, recs, nrec,
-                           lens);
-    return exclusive_scan_u32_to_u64(lens, nullptr, nrec, pre, sums, stream);
+hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, int64_t nrec_cap, uint32_t* lens,
+                                uint64_t* pre, uint64_t* sums, hipStream_t stream) {
+    if (nrec_cap > 0)
+        hipLaunchKernelGGL(k_record_lens, dim3((unsigned)((nrec_cap + 255) / 256)), dim3(256), 0, stream, recs,
+                           nrec_dev, lens);
+    return exclusive_scan_u32_to_u64(lens, nrec_dev, nrec_cap, pre, sums, stream);
 }
 
-hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, int64_t nunits, uint32_t* keys,
-                             uint64_t* vals, void* sort_temp, hipStream_t stream) {
-    if (nunits <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unit_keys, dim3((unsigned)((nunits + 255) / 256)), dim3(256), 0, stream, unit_off, pre,
-                       nunits, keys, vals);
-    return radix_sort_pairs(keys, vals, nullptr, nunits, 32, sort_temp, stream);
+hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, const int64_t* nunits_dev,
+                             int64_t nunits_cap, uint32_t* keys, uint64_t* vals, void* sort_temp, hipStream_t stream) {
+    if (nunits_cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unit_keys, dim3((unsigned)((nunits_cap + 255) / 256)), dim3(256), 0, stream, unit_off, pre,
+                       nunits_dev, keys, vals);
+    return radix_sort_pairs(keys, vals, nunits_dev, nunits_cap, 32, sort_temp, stream);
 }
 
 #define VISTA_PACKED_SHAPES(X) \
@@ -579,18 +581,18 @@ bool accum_packed_shape_supported(int tu, int tv, int jc, int waves) {
     return false;
 }
 
-hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, int64_t nunits,
-                               uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre,
-                               int grid, int waves, int npol, hipStream_t stream) {
+hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
+                               const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
+                               int npol, hipStream_t stream) {
     if (waves < 1 || waves > 16) return hipErrorInvalidValue;
 #define X(a, b, c)                                                                                              \
     if (L.tu == a && L.tv == b && L.jc == c) {                                                                  \
         if (npol == 2)                                                                                          \
             hipLaunchKernelGGL((k_accum_packed<a, b, c, 2>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
-                               order, nunits, counter, unit_off, recs, pre);                                    \
+                               order, counter, unit_off, recs, pre);                                    \
         else                                                                                                    \
             hipLaunchKernelGGL((k_accum_packed<a, b, c, 0>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
-                               order, nunits, counter, unit_off, recs, pre);                                    \
+                               order, counter, unit_off, recs, pre);                                    \
         return hipGetLastError();                                                                               \
     }
     VISTA_PACKED_SHAPES(X)

@@ -120,7 +120,7 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
     VISTA_GLOBAL float* const st_c = (VISTA_GLOBAL float*)S.st_c;
     VISTA_GLOBAL uint32_t* const st_n = (VISTA_GLOBAL uint32_t*)S.st_n;
     unsigned long long* const stats = S.stats;
-    const int carry = L.carry, kahan = L.kahan, last = L.last_wave;
+    const int carry = S.carry, kahan = L.kahan, last = S.last;
     const int ncv = (jb1 - jb0) * TV * TU;
     for (int i = threadIdx.x; i < ncv; i += blockDim.x) {
         const int lu = i % TU;

@@ -80,10 +80,12 @@ struct DevStack {
     double* out_w64;
     unsigned long long* stats;  // [8]: samples, flagged, bad weight, outside uv,
                                 //      outside band, used, contrib, overflow flag
-    // carried grid state for multi-wave runs (nullptr for a single pass)
+    // grid state carried across the waves of a streamed batch (nullptr otherwise)
     float* st_s;              // [3][nchan][nv][nu]: re, im, w
     float* st_c;              // [3][nchan][nv][nu]: Kahan compensations
     uint32_t* st_n;           // [nchan][nv][nu]
+    int32_t carry;            // 1: merge this launch's sums into the carried state
+    int32_t last;             // with carry: this is the stack's last wave, write outputs
 };
 
 struct LaunchDesc {
@@ -97,9 +99,8 @@ struct LaunchDesc {
     int64_t nrows;                    // rows in the launch
     int32_t mode;                     // kModeAtomic / kModeOrdered
     int32_t phase_fp32;
-    int32_t carry;                    // 0: write outputs; 1: merge into carried state
-    int32_t last_wave;                // with carry: also write outputs
-    int32_t kahan;
+    int32_t kahan;                    // carried-state merges are compensated
+    int64_t nunits;                   // (tile, block) units of the launch's stacks
     // launch-wide channel tables (targets' tables are slices at their chan0) and row contexts
     const DevChan* chan_all;
     const float* f1_all;
@@ -119,32 +120,33 @@ constexpr int kModeOrdered = 1;
 // them at seg_off: key = global (tile, block) unit, value = row << 32 | k_lo << 16 | k_hi,
 // one record per run of channels of one row inside one uv tile and one rest-channel
 // block.
-hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint32_t* seg_count,
+hipError_t launch_track(int64_t rows_cap, const LaunchDesc* dL, uint32_t* seg_count,
                         const uint32_t* seg_off, uint32_t* keys, uint64_t* vals, int emit,
                         hipStream_t stream);
-// unit_off[u] = first record of unit u in the sorted keys (u = 0..nunits).
+// unit_off[u] = first record of unit u in the sorted keys (u = 0..nunits).  Counts are
+// read from device memory (nrec_dev, nunits_dev); capacities size the grids.
 hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
-                               int64_t nunits, uint32_t* unit_off, hipStream_t stream);
+                               const int64_t* nunits_dev, uint32_t* unit_off, hipStream_t stream);
 // Per-record prefix of the records' channel counts: pre[i] = sum of (k_hi - k_lo) over the
 // sorted records before i (pre[nrec] = total); lens is nrec u32 of scratch.
-hipError_t launch_record_prefix(const uint64_t* recs, int64_t nrec, uint32_t* lens, uint64_t* pre, uint64_t* sums,
-                                hipStream_t stream);
+hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, int64_t nrec_cap, uint32_t* lens,
+                                uint64_t* pre, uint64_t* sums, hipStream_t stream);
 // Work list of the packed accumulation: units sorted by descending channel-sample count
 // (keys/vals: nunits entries each, sorted in place; vals end as the unit ids).
-hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, int64_t nunits, uint32_t* keys,
-                             uint64_t* vals, void* sort_temp, hipStream_t stream);
+hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, const int64_t* nunits_dev,
+                             int64_t nunits_cap, uint32_t* keys, uint64_t* vals, void* sort_temp, hipStream_t stream);
 // The packed accumulation (atomic mode): `grid` workgroups of `waves` wavefronts pull units
-// from *counter (zeroed first) in the order of `order` (u64 unit ids).
-hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, int64_t nunits,
-                               uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre,
-                               int grid, int waves, int npol, hipStream_t stream);
+// from *counter (zeroed first) in the order of `order` (u64 unit ids, L.nunits of them).
+hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
+                               const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
+                               int npol, hipStream_t stream);
 int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol);
 bool accum_packed_shape_supported(int tu, int tv, int jc, int waves);
 // The accumulation over the work list `order` (global unit ids); `grid` workgroups of
 // `waves` wavefronts pull list entries from *counter (zeroed first).
 // npol == 2 when every target of the launch has two polarisations (specialised path).
-hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint32_t* order,
-                             int64_t nunits, uint32_t* counter, const uint32_t* unit_off,
+hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order,
+                             uint32_t* counter, const uint32_t* unit_off,
                              const uint64_t* recs, int grid, int waves, int npol, hipStream_t stream);
 int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int npol);
 size_t accum_lds_bytes(int tu, int tv, int jc, int mode, int kahan);

@@ -167,7 +167,9 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
 
 // unit_off[u] = index of the first record of unit u (records sorted by unit).
 __global__ void k_unit_offsets(const uint32_t* __restrict__ keys, const int64_t* __restrict__ nrec_dev,
-                               int64_t nrec_cap, int64_t nunits, uint32_t* __restrict__ off) {
+                               int64_t nrec_cap, const int64_t* __restrict__ nunits_dev,
+                               uint32_t* __restrict__ off) {
+    const int64_t nunits = *nunits_dev;
     int64_t nrec = nrec_dev ? *nrec_dev : nrec_cap;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > nrec) return;
@@ -335,7 +337,7 @@ __device__ __forceinline__ void issue_loads(const VISTA_CONST DevTarget* tgts, c
 // handles any polarisation count and per-channel weights.
 template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
 __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict__ Lp,
-                                                   const uint32_t* __restrict__ order, int64_t nunits,
+                                                   const uint64_t* __restrict__ order,
                                                    uint32_t* __restrict__ counter,
                                                    const uint32_t* __restrict__ unit_off,
                                                    const uint64_t* __restrict__ recs) {
@@ -361,8 +363,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict_
         if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
         __syncthreads();
         const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
-        if (li >= nunits) break;
-        const int64_t unit = (uint32_t)sgpr((int32_t)gptr(order)[li]);
+        if (li >= L.nunits) break;
+        const int64_t unit = (uint32_t)sgpr((int32_t)(uint32_t)gptr(order)[li]);
         const int32_t si = sgpr((int32_t)find_le_uniform(L.stack_unit_base, L.nstacks, unit));
         const VISTA_CONST DevStack& S = cptr(L.stacks)[si];
         const int64_t local = unit - S.unit_base;
@@ -671,20 +673,20 @@ __global__ void k_debug_rotate(const DevTarget* __restrict__ Tp, float2* out, in
 
 // ---------------------------------------------------------------------------- launchers
 
-hipError_t launch_track(const LaunchDesc& L, const LaunchDesc* dL, uint32_t* seg_count, const uint32_t* seg_off,
+hipError_t launch_track(int64_t rows_cap, const LaunchDesc* dL, uint32_t* seg_count, const uint32_t* seg_off,
                         uint32_t* keys, uint64_t* vals, int emit, hipStream_t stream) {
-    if (L.nrows <= 0) return hipSuccess;
-    int64_t blocks = (L.nrows + 255) / 256;
+    if (rows_cap <= 0) return hipSuccess;
+    int64_t blocks = (rows_cap + 255) / 256;
     hipLaunchKernelGGL(k_track, dim3((unsigned)blocks), dim3(256), 0, stream, dL, seg_count, seg_off, keys, vals,
                        emit);
     return hipGetLastError();
 }
 
 hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
-                               int64_t nunits, uint32_t* unit_off, hipStream_t stream) {
+                               const int64_t* nunits_dev, uint32_t* unit_off, hipStream_t stream) {
     int64_t n = nrec_cap + 1;
     hipLaunchKernelGGL(k_unit_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sorted_keys,
-                       nrec_dev, nrec_cap, nunits, unit_off);
+                       nrec_dev, nrec_cap, nunits_dev, unit_off);
     return hipGetLastError();
 }
 
@@ -719,11 +721,11 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     X(4, 2, 512)
 
 template <int TU, int TV, int JC, int MODE, bool KAHAN, int NPOL>
-static hipError_t launch_one(const LaunchDesc* dL, const uint32_t* order, int64_t nunits, uint32_t* counter,
+static hipError_t launch_one(const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
                              const uint32_t* unit_off, const uint64_t* recs, int grid, int waves,
                              hipStream_t stream) {
     hipLaunchKernelGGL((k_accum<TU, TV, JC, MODE, KAHAN, NPOL>), dim3(grid), dim3(waves * kWave), 0, stream, dL,
-                       order, nunits, counter, unit_off, recs);
+                       order, counter, unit_off, recs);
     return hipGetLastError();
 }
 
@@ -766,11 +768,11 @@ bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kaha
         return CALL(a, b, c, kModeOrdered, false, 0);                                    \
     }
 
-hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint32_t* order, int64_t nunits,
+hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order,
                              uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, int grid,
                              int waves, int npol, hipStream_t stream) {
     if (!accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan)) return hipErrorInvalidValue;
-#define CALL(a, b, c, m, k, p) launch_one<a, b, c, m, k, p>(dL, order, nunits, counter, unit_off, recs, grid, waves, stream)
+#define CALL(a, b, c, m, k, p) launch_one<a, b, c, m, k, p>(dL, order, counter, unit_off, recs, grid, waves, stream)
 #define X(a, b, c) VISTA_DISPATCH(a, b, c, CALL)
     VISTA_SHAPES(X)
 #undef X

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -241,6 +242,12 @@ struct StackJob {
     vista_output out;          // device pointers (or NULL)
     vista_stats stats{};
     bool overflow = false;
+    int32_t index = 0;         // slot of the stack's statistics
+    // carried state of a stack streamed over several waves, and this launch's role
+    float* st_s = nullptr;
+    float* st_c = nullptr;
+    uint32_t* st_n = nullptr;
+    int carry = 0, last = 1;
 };
 
 struct Events {
@@ -271,40 +278,41 @@ static int device_cus() {
     return cus;
 }
 
-// Stack every job in one pass: all output cells of every job are written.
-static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t flags, hipStream_t stream,
-                     vista_timings* tim) {
-    DevMem mem(stream);
-    Events ev;
-    const int mode = (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
-    const int kahan = (flags & VISTA_F_KAHAN) ? 1 : 0;
-    if (!shape_ok(tu, flags))
-        throw HipFail{hipErrorInvalidValue, "unsupported launch shape (tile/jblock/waves)"};
-    const int jsub = mode == kModeOrdered ? tu.jc / tu.waves : tu.jc;
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-    // ---- host side: tables of every target, packed into one device upload
+// Host side of one launch: the descriptors and tables of its stacks and targets, packed
+// for one upload.  Target data pointers (uvw, vis, weight, flag) are set by the caller.
+struct HostLaunch {
     std::vector<DevTarget> dts;
-    std::vector<DevStack> dss(jobs.size());
-    std::vector<int64_t> row_base, tile_base;
+    std::vector<DevStack> dss;
+    std::vector<int64_t> row_base, tile_base, unit_base;
     std::vector<unsigned char> arena;
-    auto put = [&arena](const void* p, size_t n) {
-        size_t off = (arena.size() + 255) & ~(size_t)255;
-        arena.resize(off + n);
-        if (n) memcpy(arena.data() + off, p, n);
+    struct Offs { size_t blk, sblk, inband; };
+    std::vector<Offs> offs;
+    std::vector<const HostTarget*> hts;        // the HostTarget of each DevTarget
+    std::vector<int32_t> stats_index;          // per stack
+    size_t o_chan = 0, o_f1 = 0, o_foff = 0, o_fval = 0;
+    int64_t rows = 0, nunits = 0, zero_flag_bytes = 0;
+    int npol_all = 2;
+};
+
+static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& tu, int jsub) {
+    HostLaunch h;
+    auto put = [&h](const void* p, size_t n) {
+        size_t off = align256(h.arena.size());
+        h.arena.resize(off + n);
+        if (n) memcpy(h.arena.data() + off, p, n);
         return off;
     };
-    struct Offs { size_t blk, sblk, inband; };
     // launch-wide channel tables: target i's entries start at its chan0
     std::vector<DevChan> chan_all;
     std::vector<float> f1_all, fval_all;
     std::vector<int32_t> foff_all;
-    int64_t zero_flag_bytes = 0;
-    std::vector<Offs> offs;
-    int64_t rows = 0, tiles = 0, nunits = 0;
-    std::vector<int64_t> unit_base;
+    int64_t tiles = 0;
+    h.dss.resize(jobs.size());
     for (size_t s = 0; s < jobs.size(); ++s) {
         const vista_grid_desc* g = jobs[s].g;
-        DevStack& S = dss[s];
+        DevStack& S = h.dss[s];
         memset(&S, 0, sizeof(S));
         S.nu = g->nu; S.nv = g->nv; S.nchan = g->nchan;
         S.tiles_u = (g->nu + tu.tu - 1) / tu.tu;
@@ -312,253 +320,353 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
         S.nblocks = (g->nchan + tu.jc - 1) / tu.jc;
         S.inv_du = 1.0 / g->du;
         S.inv_dv = 1.0 / g->dv;
-        S.target_begin = (int32_t)dts.size();
+        S.target_begin = (int32_t)h.dts.size();
         S.tile_base = tiles;
-        S.unit_base = nunits;
-        tile_base.push_back(tiles);
-        unit_base.push_back(nunits);
-        tiles += (int64_t)S.tiles_u * S.tiles_v;
-        nunits += (int64_t)S.tiles_u * S.tiles_v * S.nblocks;
-        for (HostTarget* h : jobs[s].targets) {
-            if (h->t.nrow == 0) continue;
-            DevTarget T;
-            memset(&T, 0, sizeof(T));
-            T.row_base = rows;
-            T.nrow = h->t.nrow;
-            T.nchan = h->t.nchan;
-            T.npol = h->t.npol;
-            T.weight_per_chan = h->t.weight_per_chan;
-            T.stack = (int32_t)s;
-            T.kin_lo = h->plan.kin_lo;
-            T.kin_hi = h->plan.kin_hi;
-            T.nphase = h->plan.nphase;
-            T.nblocks = S.nblocks;
-            T.l = h->t.l; T.m = h->t.m; T.nm1 = h->plan.nm1;
-            T.chan0 = (int32_t)chan_all.size();
-            chan_all.insert(chan_all.end(), h->plan.chan.begin(), h->plan.chan.end());
-            f1_all.insert(f1_all.end(), h->plan.f1.begin(), h->plan.f1.end());
-            for (int32_t f : h->plan.foff) foff_all.push_back(f + (int32_t)fval_all.size());
-            fval_all.insert(fval_all.end(), h->plan.fval.begin(), h->plan.fval.end());
-            if (!h->t.flag) zero_flag_bytes = std::max<int64_t>(zero_flag_bytes, (int64_t)h->t.nchan * h->t.npol);
-            if (chan_all.size() >= 0x7fffffffu || fval_all.size() >= 0x7fffffffu)
-                throw HipFail{hipErrorInvalidValue, "too many channels in one launch"};
-            Offs o;
-            std::vector<int32_t> blk = block_ranges(h->plan, g->nchan, tu.jc);
-            o.blk = put(blk.data(), blk.size() * sizeof(int32_t));
-            if (jsub != tu.jc) {
-                std::vector<int32_t> sblk = block_ranges(h->plan, g->nchan, jsub);
-                o.sblk = put(sblk.data(), sblk.size() * sizeof(int32_t));
-            } else {
-                o.sblk = o.blk;
-            }
-            o.inband = put(h->plan.inband.data(), h->plan.inband.size() * sizeof(int32_t));
-            offs.push_back(o);
-            row_base.push_back(rows);
-            rows += h->t.nrow;
-            dts.push_back(T);
-        }
-        S.target_end = (int32_t)dts.size();
-    }
-    row_base.push_back(rows);
-    tile_base.push_back(tiles);
-    unit_base.push_back(nunits);
-    if (rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
-    if (nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
-
-    VISTA_HIP(hipEventRecord(ev.e[0], stream));
-
-    // ---- device residency of the inputs
-    size_t ti = 0;
-    for (size_t s = 0; s < jobs.size(); ++s) {
-        for (HostTarget* h : jobs[s].targets) {
-            if (h->t.nrow == 0) continue;
-            DevTarget& T = dts[ti++];
-            const vista_target& t = h->t;
-            if (t.mem == VISTA_MEM_DEVICE) {
-                T.uvw = t.uvw; T.vis = (const float2*)t.vis; T.weight = t.weight; T.flag = t.flag;
-            } else {
-                size_t nr = (size_t)t.nrow, ns = nr * t.nchan * t.npol;
-                size_t b_w = (t.weight_per_chan ? ns : nr * t.npol) * sizeof(float);
-                double* du = mem.alloc_n<double>(nr * 3);
-                float2* dv = mem.alloc_n<float2>(ns);
-                float* dw = (float*)mem.alloc(b_w);
-                VISTA_HIP(hipMemcpyAsync(du, t.uvw, nr * 3 * sizeof(double), hipMemcpyHostToDevice, stream));
-                VISTA_HIP(hipMemcpyAsync(dv, t.vis, ns * 8, hipMemcpyHostToDevice, stream));
-                VISTA_HIP(hipMemcpyAsync(dw, t.weight, b_w, hipMemcpyHostToDevice, stream));
-                T.uvw = du; T.vis = dv; T.weight = dw; T.flag = nullptr;
-                if (t.flag) {
-                    uint8_t* df = mem.alloc_n<uint8_t>(ns);
-                    VISTA_HIP(hipMemcpyAsync(df, t.flag, ns, hipMemcpyHostToDevice, stream));
-                    T.flag = df;
-                }
-            }
-        }
-    }
-    const size_t o_chan = put(chan_all.data(), chan_all.size() * sizeof(DevChan));
-    const size_t o_f1 = put(f1_all.data(), f1_all.size() * sizeof(float));
-    const size_t o_foff = put(foff_all.data(), foff_all.size() * sizeof(int32_t));
-    const size_t o_fval = put(fval_all.data(), fval_all.size() * sizeof(float));
-    unsigned char* d_arena = mem.alloc_n<unsigned char>(std::max<size_t>(arena.size(), 1));
-    VISTA_HIP(hipMemcpyAsync(d_arena, arena.data(), arena.size(), hipMemcpyHostToDevice, stream));
-    const DevChan* d_chan = (const DevChan*)(d_arena + o_chan);
-    const float* d_f1 = (const float*)(d_arena + o_f1);
-    const int32_t* d_foff = (const int32_t*)(d_arena + o_foff);
-    const float* d_fval = (const float*)(d_arena + o_fval);
-    for (size_t i = 0; i < dts.size(); ++i) {
-        dts[i].chan = d_chan + dts[i].chan0;
-        dts[i].f1 = d_f1 + dts[i].chan0;
-        dts[i].foff = d_foff + dts[i].chan0;
-        dts[i].fval = d_fval;
-        dts[i].blk = (const int32_t*)(d_arena + offs[i].blk);
-        dts[i].sblk = (const int32_t*)(d_arena + offs[i].sblk);
-        dts[i].inband = (const int32_t*)(d_arena + offs[i].inband);
-    }
-    unsigned long long* d_stats = mem.alloc_n<unsigned long long>(8 * jobs.size());
-    check_launch(launch_fill_u64(d_stats, 0ull, 8 * (int64_t)jobs.size(), stream), "fill");
-    for (size_t s = 0; s < jobs.size(); ++s) {
-        DevStack& S = dss[s];
-        S.stats = d_stats + 8 * s;
+        S.unit_base = h.nunits;
         S.out_vis = (float2*)jobs[s].out.sum_wvis;
         S.out_w = (float*)jobs[s].out.sum_w;
         S.out_cnt = (uint32_t*)jobs[s].out.count;
         S.out_vis64 = (double2*)jobs[s].out.sum_wvis64;
         S.out_w64 = (double*)jobs[s].out.sum_w64;
+        S.st_s = jobs[s].st_s;
+        S.st_c = jobs[s].st_c;
+        S.st_n = jobs[s].st_n;
+        S.carry = jobs[s].carry;
+        S.last = jobs[s].last;
+        h.stats_index.push_back(jobs[s].index);
+        h.tile_base.push_back(tiles);
+        h.unit_base.push_back(h.nunits);
+        tiles += (int64_t)S.tiles_u * S.tiles_v;
+        h.nunits += (int64_t)S.tiles_u * S.tiles_v * S.nblocks;
+        for (HostTarget* ht : jobs[s].targets) {
+            if (ht->t.nrow == 0) continue;
+            DevTarget T;
+            memset(&T, 0, sizeof(T));
+            T.row_base = h.rows;
+            T.nrow = ht->t.nrow;
+            T.nchan = ht->t.nchan;
+            T.npol = ht->t.npol;
+            T.weight_per_chan = ht->t.weight_per_chan;
+            T.stack = (int32_t)s;
+            T.kin_lo = ht->plan.kin_lo;
+            T.kin_hi = ht->plan.kin_hi;
+            T.nphase = ht->plan.nphase;
+            T.nblocks = S.nblocks;
+            T.l = ht->t.l; T.m = ht->t.m; T.nm1 = ht->plan.nm1;
+            T.chan0 = (int32_t)chan_all.size();
+            chan_all.insert(chan_all.end(), ht->plan.chan.begin(), ht->plan.chan.end());
+            f1_all.insert(f1_all.end(), ht->plan.f1.begin(), ht->plan.f1.end());
+            for (int32_t f : ht->plan.foff) foff_all.push_back(f + (int32_t)fval_all.size());
+            fval_all.insert(fval_all.end(), ht->plan.fval.begin(), ht->plan.fval.end());
+            if (!ht->t.flag)
+                h.zero_flag_bytes = std::max<int64_t>(h.zero_flag_bytes, (int64_t)ht->t.nchan * ht->t.npol);
+            if (chan_all.size() >= 0x7fffffffu || fval_all.size() >= 0x7fffffffu)
+                throw HipFail{hipErrorInvalidValue, "too many channels in one launch"};
+            if (T.npol != 2 || T.weight_per_chan) h.npol_all = 0;   // the specialised path: 2 pols, row weights
+            HostLaunch::Offs o;
+            std::vector<int32_t> blk = block_ranges(ht->plan, g->nchan, tu.jc);
+            o.blk = put(blk.data(), blk.size() * sizeof(int32_t));
+            if (jsub != tu.jc) {
+                std::vector<int32_t> sblk = block_ranges(ht->plan, g->nchan, jsub);
+                o.sblk = put(sblk.data(), sblk.size() * sizeof(int32_t));
+            } else {
+                o.sblk = o.blk;
+            }
+            o.inband = put(ht->plan.inband.data(), ht->plan.inband.size() * sizeof(int32_t));
+            h.offs.push_back(o);
+            h.row_base.push_back(h.rows);
+            h.rows += ht->t.nrow;
+            h.dts.push_back(T);
+            h.hts.push_back(ht);
+        }
+        S.target_end = (int32_t)h.dts.size();
     }
-    DevTarget* d_t = mem.alloc_n<DevTarget>(std::max<size_t>(1, dts.size()));
-    DevStack* d_s = mem.alloc_n<DevStack>(dss.size());
-    int64_t* d_rb = mem.alloc_n<int64_t>(row_base.size());
-    int64_t* d_tb = mem.alloc_n<int64_t>(tile_base.size());
-    int64_t* d_ub = mem.alloc_n<int64_t>(unit_base.size());
-    if (!dts.empty())
-        VISTA_HIP(hipMemcpyAsync(d_t, dts.data(), dts.size() * sizeof(DevTarget), hipMemcpyHostToDevice, stream));
-    VISTA_HIP(hipMemcpyAsync(d_s, dss.data(), dss.size() * sizeof(DevStack), hipMemcpyHostToDevice, stream));
-    VISTA_HIP(hipMemcpyAsync(d_rb, row_base.data(), row_base.size() * 8, hipMemcpyHostToDevice, stream));
-    VISTA_HIP(hipMemcpyAsync(d_tb, tile_base.data(), tile_base.size() * 8, hipMemcpyHostToDevice, stream));
-    VISTA_HIP(hipMemcpyAsync(d_ub, unit_base.data(), unit_base.size() * 8, hipMemcpyHostToDevice, stream));
+    h.row_base.push_back(h.rows);
+    h.tile_base.push_back(tiles);
+    h.unit_base.push_back(h.nunits);
+    if (h.rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
+    if (h.nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
+    h.o_chan = put(chan_all.data(), chan_all.size() * sizeof(DevChan));
+    h.o_f1 = put(f1_all.data(), f1_all.size() * sizeof(float));
+    h.o_foff = put(foff_all.data(), foff_all.size() * sizeof(int32_t));
+    h.o_fval = put(fval_all.data(), fval_all.size() * sizeof(float));
+    return h;
+}
 
-    LaunchDesc L;
-    memset(&L, 0, sizeof(L));
-    L.targets = d_t;
-    L.stacks = d_s;
-    L.target_row_base = d_rb;
-    L.stack_tile_base = d_tb;
-    L.stack_unit_base = d_ub;
-    L.ntargets = (int32_t)dts.size();
-    L.nstacks = (int32_t)dss.size();
-    L.tu = tu.tu; L.tv = tu.tv; L.jc = tu.jc; L.jsub = jsub;
-    L.nrows = rows;
-    L.mode = mode;
-    L.kahan = kahan;
-    L.phase_fp32 = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
-    L.chan_all = d_chan;
-    L.f1_all = d_f1;
-    L.foff_all = d_foff;
-    L.fval_all = d_fval;
-    const bool packed = mode == kModeAtomic;
-    if (packed && rows > 0) {
-        L.rowctx = mem.alloc_n<RowCtx>(rows);
-        if (zero_flag_bytes > 0) {
-            int64_t words = (zero_flag_bytes + 3) / 4;
-            uint32_t* z = mem.alloc_n<uint32_t>(words);
-            check_launch(launch_fill_u32(z, 0u, words, stream), "fill");
-            L.zero_flags = (const uint8_t*)z;
+// Sizes of the fixed device buffers of the launch sequence.
+struct Capacity {
+    int64_t rows = 0, targets = 0, stacks = 0, arena = 0, units = 0, recs = 0, zflag = 0;
+    static Capacity of(const HostLaunch& h) {
+        Capacity c;
+        c.rows = h.rows;
+        c.targets = (int64_t)h.dts.size();
+        c.stacks = (int64_t)h.dss.size();
+        c.arena = (int64_t)h.arena.size();
+        c.units = h.nunits;
+        c.zflag = h.zero_flag_bytes;
+        return c;
+    }
+    Capacity max_with(const Capacity& o) const {
+        Capacity c;
+        c.rows = std::max(rows, o.rows); c.targets = std::max(targets, o.targets);
+        c.stacks = std::max(stacks, o.stacks); c.arena = std::max(arena, o.arena);
+        c.units = std::max(units, o.units); c.recs = std::max(recs, o.recs); c.zflag = std::max(zflag, o.zflag);
+        return c;
+    }
+    bool covers(const Capacity& o) const {
+        return rows >= o.rows && targets >= o.targets && stacks >= o.stacks && arena >= o.arena &&
+               units >= o.units && recs >= o.recs && zflag >= o.zflag;
+    }
+};
+
+// The device side of launches: fixed buffers sized by a capacity, the count pass (run
+// eagerly, it sizes the record buffers), and the rest of the sequence -- emit, sort, unit
+// offsets, record starts, work list, accumulation -- which reads every count from device
+// memory, records no memset and never synchronises, so it can be captured once in a
+// hipGraph and replayed for every launch that fits the capacity.
+class Launcher {
+  public:
+    Launcher(hipStream_t s, const Tuning& tu, uint32_t flags)
+        : s_(s), tu_(tu), mem_(s), recmem_(s) {
+        mode_ = (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
+        kahan_ = (flags & VISTA_F_KAHAN) ? 1 : 0;
+        phase_fp32_ = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
+        jsub_ = mode_ == kModeOrdered ? tu.jc / tu.waves : tu.jc;
+        if (!shape_ok(tu, flags)) throw HipFail{hipErrorInvalidValue, "unsupported launch shape (tile/jblock/waves)"};
+    }
+    ~Launcher() { drop_graph(); }
+    int jsub() const { return jsub_; }
+
+    // Grow the buffers to cover c (record buffers separately: they are sized last).
+    void reserve(const Capacity& want) {
+        Capacity c = cap_.max_with(want);
+        if (!cap_.covers(Capacity{c.rows, c.targets, c.stacks, c.arena, c.units, 0, c.zflag}) || !fixed_) {
+            drop_graph();
+            mem_.release();
+            fixed_ = true;
+            d_L_ = mem_.alloc_n<LaunchDesc>(1);
+            d_t_ = mem_.alloc_n<DevTarget>(std::max<int64_t>(1, c.targets));
+            d_s_ = mem_.alloc_n<DevStack>(std::max<int64_t>(1, c.stacks));
+            d_rb_ = mem_.alloc_n<int64_t>(c.targets + 1);
+            d_tb_ = mem_.alloc_n<int64_t>(c.stacks + 1);
+            d_ub_ = mem_.alloc_n<int64_t>(c.stacks + 1);
+            d_arena_ = mem_.alloc_n<unsigned char>(std::max<int64_t>(256, c.arena));
+            rowctx_ = mode_ == kModeAtomic ? mem_.alloc_n<RowCtx>(std::max<int64_t>(1, c.rows)) : nullptr;
+            zflags_ = nullptr;
+            if (c.zflag > 0) {
+                int64_t words = (c.zflag + 3) / 4;
+                uint32_t* z = mem_.alloc_n<uint32_t>(words);
+                check_launch(launch_fill_u32(z, 0u, words, s_), "fill");
+                zflags_ = (const uint8_t*)z;
+            }
+            cnt_ = mem_.alloc_n<uint32_t>(std::max<int64_t>(1, c.rows));
+            off_ = mem_.alloc_n<uint32_t>(c.rows + 1);
+            sums_ = mem_.alloc_n<uint64_t>(scan_temp_elems(c.rows));
+            unit_off_ = mem_.alloc_n<uint32_t>(c.units + 1);
+            okeys_ = mem_.alloc_n<uint32_t>(std::max<int64_t>(1, c.units));
+            order_ = mem_.alloc_n<uint64_t>(std::max<int64_t>(1, c.units));
+            otmp_ = mem_.alloc(radix_sort_temp_bytes(std::max<int64_t>(1, c.units)));
+            counter_ = mem_.alloc_n<uint32_t>(1);
+            cap_ = Capacity{c.rows, c.targets, c.stacks, c.arena, c.units, cap_.recs, c.zflag};
+            recs_ok_ = false;
+        }
+        if (!recs_ok_ || want.recs > cap_.recs) {
+            drop_graph();
+            recmem_.release();
+            const int64_t r = std::max<int64_t>(std::max(want.recs, cap_.recs), 1);
+            keys_ = recmem_.alloc_n<uint32_t>(r);
+            vals_ = recmem_.alloc_n<uint64_t>(r);
+            stmp_ = recmem_.alloc(radix_sort_temp_bytes(r));
+            lens_ = recmem_.alloc_n<uint32_t>(r);
+            pre_ = recmem_.alloc_n<uint64_t>(r + 1);
+            psums_ = recmem_.alloc_n<uint64_t>(scan_temp_elems(r));
+            cap_.recs = r;
+            recs_ok_ = true;
         }
     }
-    LaunchDesc* d_L = mem.alloc_n<LaunchDesc>(1);
-    VISTA_HIP(hipMemcpyAsync(d_L, &L, sizeof(L), hipMemcpyHostToDevice, stream));
 
-    // ---- binning: records of (row, tile run, block), grouped by (tile, block) unit
-    int64_t nrec = 0;
-    uint32_t* unit_off = mem.alloc_n<uint32_t>(nunits + 1);
-    uint64_t* vals = nullptr;
-    if (rows > 0) {
-        uint32_t* cnt = mem.alloc_n<uint32_t>(rows);
-        uint32_t* off = mem.alloc_n<uint32_t>(rows + 1);
-        uint64_t* sums = mem.alloc_n<uint64_t>(scan_temp_elems(rows));
-        check_launch(launch_track(L, d_L, cnt, nullptr, nullptr, nullptr, 0, stream), "track count");
-        check_launch(exclusive_scan_u32_to_u32(cnt, nullptr, rows, off, sums, stream), "scan");
-        int64_t nb = (int64_t)scan_temp_elems(rows) - 1;
+    // Upload launch h into the fixed buffers and run the count pass (which also writes
+    // the row contexts and the outside-uv counts).  Returns the number of records.
+    int64_t prepare(HostLaunch& h, unsigned long long* d_stats) {
+        if (!cap_.covers(Capacity::of(h)) || !fixed_) throw HipFail{hipErrorInvalidValue, "launch exceeds capacity"};
+        const DevChan* d_chan = (const DevChan*)(d_arena_ + h.o_chan);
+        const float* d_f1 = (const float*)(d_arena_ + h.o_f1);
+        const int32_t* d_foff = (const int32_t*)(d_arena_ + h.o_foff);
+        const float* d_fval = (const float*)(d_arena_ + h.o_fval);
+        for (size_t i = 0; i < h.dts.size(); ++i) {
+            DevTarget& T = h.dts[i];
+            T.chan = d_chan + T.chan0;
+            T.f1 = d_f1 + T.chan0;
+            T.foff = d_foff + T.chan0;
+            T.fval = d_fval;
+            T.blk = (const int32_t*)(d_arena_ + h.offs[i].blk);
+            T.sblk = (const int32_t*)(d_arena_ + h.offs[i].sblk);
+            T.inband = (const int32_t*)(d_arena_ + h.offs[i].inband);
+        }
+        for (size_t s = 0; s < h.dss.size(); ++s) h.dss[s].stats = d_stats + 8 * h.stats_index[s];
+        LaunchDesc& L = L_;
+        memset(&L, 0, sizeof(L));
+        L.targets = d_t_;
+        L.stacks = d_s_;
+        L.target_row_base = d_rb_;
+        L.stack_tile_base = d_tb_;
+        L.stack_unit_base = d_ub_;
+        L.ntargets = (int32_t)h.dts.size();
+        L.nstacks = (int32_t)h.dss.size();
+        L.tu = tu_.tu; L.tv = tu_.tv; L.jc = tu_.jc; L.jsub = jsub_;
+        L.nrows = h.rows;
+        L.mode = mode_;
+        L.kahan = kahan_;
+        L.phase_fp32 = phase_fp32_;
+        L.nunits = h.nunits;
+        L.chan_all = d_chan;
+        L.f1_all = d_f1;
+        L.foff_all = d_foff;
+        L.fval_all = d_fval;
+        L.rowctx = rowctx_;
+        L.zero_flags = zflags_;
+        npol_ = h.npol_all;
+        // host sources stay alive until the stream has passed these copies (the count
+        // below synchronises)
+        VISTA_HIP(hipMemcpyAsync(d_arena_, h.arena.data(), h.arena.size(), hipMemcpyHostToDevice, s_));
+        if (!h.dts.empty())
+            VISTA_HIP(hipMemcpyAsync(d_t_, h.dts.data(), h.dts.size() * sizeof(DevTarget), hipMemcpyHostToDevice, s_));
+        VISTA_HIP(hipMemcpyAsync(d_s_, h.dss.data(), h.dss.size() * sizeof(DevStack), hipMemcpyHostToDevice, s_));
+        VISTA_HIP(hipMemcpyAsync(d_rb_, h.row_base.data(), h.row_base.size() * 8, hipMemcpyHostToDevice, s_));
+        VISTA_HIP(hipMemcpyAsync(d_tb_, h.tile_base.data(), h.tile_base.size() * 8, hipMemcpyHostToDevice, s_));
+        VISTA_HIP(hipMemcpyAsync(d_ub_, h.unit_base.data(), h.unit_base.size() * 8, hipMemcpyHostToDevice, s_));
+        VISTA_HIP(hipMemcpyAsync(d_L_, &L, sizeof(L), hipMemcpyHostToDevice, s_));
+        // count pass: records per row, their exclusive scan (total at the scan's end slot)
+        check_launch(launch_track(cap_.rows, d_L_, cnt_, nullptr, nullptr, nullptr, 0, s_), "track count");
+        check_launch(exclusive_scan_u32_to_u32(cnt_, nrows_dev(), cap_.rows, off_, sums_, s_), "scan");
         uint64_t total = 0;
-        VISTA_HIP(hipMemcpyAsync(&total, sums + nb, 8, hipMemcpyDeviceToHost, stream));
-        VISTA_HIP(hipStreamSynchronize(stream));
+        VISTA_HIP(hipMemcpyAsync(&total, nrec_dev(), 8, hipMemcpyDeviceToHost, s_));
+        VISTA_HIP(hipStreamSynchronize(s_));
         if (total >= 0xffffffffull) throw HipFail{hipErrorInvalidValue, "too many track records in one launch"};
-        nrec = (int64_t)total;
-        if (nrec > 0) {
-            uint32_t* keys = mem.alloc_n<uint32_t>(nrec);
-            vals = mem.alloc_n<uint64_t>(nrec);
-            void* stmp = mem.alloc(radix_sort_temp_bytes(nrec));
-            check_launch(launch_track(L, d_L, nullptr, off, keys, vals, 1, stream), "track emit");
-            int bits = 1;
-            while (bits < 32 && (int64_t(1) << bits) < nunits) ++bits;
-            check_launch(radix_sort_pairs(keys, vals, nullptr, nrec, bits, stmp, stream), "sort");
-            check_launch(launch_unit_offsets(keys, nullptr, nrec, nunits, unit_off, stream), "unit offsets");
-        }
+        return (int64_t)total;
     }
-    if (nrec == 0) check_launch(launch_fill_u32(unit_off, 0u, nunits + 1, stream), "fill");
 
-    if (packed) {
-        // ---- record starts in the units' sample streams, and the work list: every unit of
-        // every stack (units without records still write their zero cells), most samples
-        // first, all on the device
-        uint64_t* pre = mem.alloc_n<uint64_t>(nrec + 1);
-        {
-            uint32_t* lens = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nrec));
-            uint64_t* sums = mem.alloc_n<uint64_t>(scan_temp_elems(nrec));
-            check_launch(launch_record_prefix(vals, nrec, lens, pre, sums, stream), "record prefix");
-        }
-        uint32_t* okeys = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nunits));
-        uint64_t* order = mem.alloc_n<uint64_t>(std::max<int64_t>(1, nunits));
-        void* otmp = mem.alloc(radix_sort_temp_bytes(std::max<int64_t>(1, nunits)));
-        check_launch(launch_unit_order(unit_off, pre, nunits, okeys, order, otmp, stream), "unit order");
-        uint32_t* counter = mem.alloc_n<uint32_t>(1);
-        check_launch(launch_fill_u32(counter, 0u, 1, stream), "fill");
-        if (!vals) vals = mem.alloc_n<uint64_t>(1);
-        VISTA_HIP(hipEventRecord(ev.e[1], stream));
-        int npol_all = 2;
-        for (auto& T : dts)
-            if (T.npol != 2 || T.weight_per_chan) npol_all = 0;   // the specialised path: 2 pols, row weights
-        int per_cu = tu.wg_per_cu > 0 ? tu.wg_per_cu
-                                      : accum_packed_max_blocks_per_cu(tu.tu, tu.tv, tu.jc, tu.waves, npol_all);
+    // The rest of the sequence for the uploaded launch.  ev (optional, eager only) gets
+    // its events 1 and 2 around the accumulation.
+    void sequence(Events* ev) {
+        check_launch(launch_track(cap_.rows, d_L_, nullptr, off_, keys_, vals_, 1, s_), "track emit");
+        int bits = 1;
+        while (bits < 32 && (int64_t(1) << bits) < cap_.units) ++bits;
+        check_launch(radix_sort_pairs(keys_, vals_, nrec_dev(), cap_.recs, bits, stmp_, s_), "sort");
+        check_launch(launch_unit_offsets(keys_, nrec_dev(), cap_.recs, nunits_dev(), unit_off_, s_), "unit offsets");
+        check_launch(launch_record_prefix(vals_, nrec_dev(), cap_.recs, lens_, pre_, psums_, s_), "record prefix");
+        check_launch(launch_unit_order(unit_off_, pre_, nunits_dev(), cap_.units, okeys_, order_, otmp_, s_),
+                     "unit order");
+        check_launch(launch_fill_u32(counter_, 0u, 1, s_), "fill");
+        if (ev) VISTA_HIP(hipEventRecord(ev->e[1], s_));
+        int per_cu = tu_.wg_per_cu;
+        if (per_cu <= 0)
+            per_cu = mode_ == kModeAtomic
+                         ? accum_packed_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, npol_)
+                         : accum_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, mode_, kahan_, npol_);
         if (per_cu < 1) per_cu = 1;
-        int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, nunits));
-        check_launch(launch_accum_packed(L, d_L, order, nunits, counter, unit_off, vals, pre, (int)grid, tu.waves,
-                                         npol_all, stream),
-                     "accumulate");
-    } else {
-    // ---- work list: every (tile, block) unit of every stack, heaviest first (units
-    // without records still write their zero cells)
-    std::vector<uint32_t> uoff(nunits + 1);
-    VISTA_HIP(hipMemcpyAsync(uoff.data(), unit_off, (nunits + 1) * 4, hipMemcpyDeviceToHost, stream));
-    VISTA_HIP(hipStreamSynchronize(stream));
-    std::vector<uint32_t> order(nunits);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return uoff[a + 1] - uoff[a] > uoff[b + 1] - uoff[b]; });
-    uint32_t* d_order = mem.alloc_n<uint32_t>(std::max<int64_t>(1, nunits));
-    if (nunits > 0)
-        VISTA_HIP(hipMemcpyAsync(d_order, order.data(), nunits * 4, hipMemcpyHostToDevice, stream));
-    uint32_t* counter = mem.alloc_n<uint32_t>(1);
-    check_launch(launch_fill_u32(counter, 0u, 1, stream), "fill");
-    if (!vals) vals = mem.alloc_n<uint64_t>(1);
-
-    VISTA_HIP(hipEventRecord(ev.e[1], stream));
-    int npol_all = 2;
-    for (auto& T : dts)
-        if (T.npol != 2 || T.weight_per_chan) npol_all = 0;   // the specialised path: 2 pols, row weights
-    int per_cu = tu.wg_per_cu > 0 ? tu.wg_per_cu
-                                  : accum_max_blocks_per_cu(tu.tu, tu.tv, tu.jc, tu.waves, mode, kahan, npol_all);
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, nunits));
-    check_launch(launch_accum_impl(L, d_L, d_order, nunits, counter, unit_off, vals, (int)grid, tu.waves, npol_all,
-                                   stream),
-                 "accumulate");
+        const int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, cap_.units));
+        if (mode_ == kModeAtomic)
+            check_launch(launch_accum_packed(L_, d_L_, order_, counter_, unit_off_, vals_, pre_, (int)grid, tu_.waves,
+                                             npol_, s_),
+                         "accumulate");
+        else
+            check_launch(launch_accum_impl(L_, d_L_, order_, counter_, unit_off_, vals_, (int)grid, tu_.waves, npol_,
+                                           s_),
+                         "accumulate");
+        if (ev) VISTA_HIP(hipEventRecord(ev->e[2], s_));
     }
-    VISTA_HIP(hipEventRecord(ev.e[2], stream));
 
-    std::vector<unsigned long long> st(8 * jobs.size());
-    VISTA_HIP(hipMemcpyAsync(st.data(), d_stats, st.size() * 8, hipMemcpyDeviceToHost, stream));
-    VISTA_HIP(hipEventRecord(ev.e[3], stream));
-    VISTA_HIP(hipStreamSynchronize(stream));
+    // Replay the captured sequence (capturing it first, or again after the buffers or
+    // the specialisation changed).
+    void replay() {
+        if (!exec_ || graph_npol_ != npol_) {
+            drop_graph();
+            VISTA_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+            try {
+                sequence(nullptr);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(s_, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            VISTA_HIP(hipStreamEndCapture(s_, &graph_));
+            VISTA_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+            graph_npol_ = npol_;
+            ++captures_;
+        }
+        VISTA_HIP(hipGraphLaunch(exec_, s_));
+    }
+    int captures() const { return captures_; }
+    const Capacity& capacity() const { return cap_; }
+
+  private:
+    const int64_t* nrows_dev() const { return (const int64_t*)((const char*)d_L_ + offsetof(LaunchDesc, nrows)); }
+    const int64_t* nunits_dev() const { return (const int64_t*)((const char*)d_L_ + offsetof(LaunchDesc, nunits)); }
+    const int64_t* nrec_dev() const { return (const int64_t*)(sums_ + (scan_temp_elems(cap_.rows) - 1)); }
+    void drop_graph() {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+    }
+
+    hipStream_t s_;
+    Tuning tu_;
+    int mode_ = kModeAtomic, kahan_ = 0, phase_fp32_ = 0, jsub_ = 0, npol_ = 2;
+    DevMem mem_, recmem_;
+    Capacity cap_;
+    bool fixed_ = false, recs_ok_ = false;
+    LaunchDesc L_{};
+    LaunchDesc* d_L_ = nullptr;
+    DevTarget* d_t_ = nullptr;
+    DevStack* d_s_ = nullptr;
+    int64_t *d_rb_ = nullptr, *d_tb_ = nullptr, *d_ub_ = nullptr;
+    unsigned char* d_arena_ = nullptr;
+    RowCtx* rowctx_ = nullptr;
+    const uint8_t* zflags_ = nullptr;
+    uint32_t *cnt_ = nullptr, *off_ = nullptr, *unit_off_ = nullptr, *okeys_ = nullptr, *counter_ = nullptr;
+    uint64_t *sums_ = nullptr, *order_ = nullptr;
+    void* otmp_ = nullptr;
+    uint32_t* keys_ = nullptr;
+    uint64_t* vals_ = nullptr;
+    void* stmp_ = nullptr;
+    uint32_t* lens_ = nullptr;
+    uint64_t *pre_ = nullptr, *psums_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    int graph_npol_ = -1, captures_ = 0;
+};
+
+// Point the launch's targets at device copies of their data: device-resident inputs as
+// they are, host inputs copied into `mem` (stream-ordered on s).
+static void make_resident(HostLaunch& h, DevMem& mem, hipStream_t s) {
+    for (size_t i = 0; i < h.dts.size(); ++i) {
+        DevTarget& T = h.dts[i];
+        const vista_target& t = h.hts[i]->t;
+        if (t.mem == VISTA_MEM_DEVICE) {
+            T.uvw = t.uvw; T.vis = (const float2*)t.vis; T.weight = t.weight; T.flag = t.flag;
+            continue;
+        }
+        size_t nr = (size_t)t.nrow, ns = nr * t.nchan * t.npol;
+        size_t b_w = (t.weight_per_chan ? ns : nr * t.npol) * sizeof(float);
+        double* du = mem.alloc_n<double>(nr * 3);
+        float2* dv = mem.alloc_n<float2>(ns);
+        float* dw = (float*)mem.alloc(b_w);
+        VISTA_HIP(hipMemcpyAsync(du, t.uvw, nr * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        VISTA_HIP(hipMemcpyAsync(dv, t.vis, ns * 8, hipMemcpyHostToDevice, s));
+        VISTA_HIP(hipMemcpyAsync(dw, t.weight, b_w, hipMemcpyHostToDevice, s));
+        T.uvw = du; T.vis = dv; T.weight = dw; T.flag = nullptr;
+        if (t.flag) {
+            uint8_t* df = mem.alloc_n<uint8_t>(ns);
+            VISTA_HIP(hipMemcpyAsync(df, t.flag, ns, hipMemcpyHostToDevice, s));
+            T.flag = df;
+        }
+    }
+}
+
+static void collect_stats(std::vector<StackJob>& jobs, const std::vector<unsigned long long>& st) {
     for (size_t s = 0; s < jobs.size(); ++s) {
         vista_stats& o = jobs[s].stats;
         memset(&o, 0, sizeof(o));
@@ -566,24 +674,51 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
             o.n_samples += h->n_samples;
             o.n_outside_band += h->n_outside_band;
         }
-        o.n_flagged = st[8 * s + 1];
-        o.n_bad_weight = st[8 * s + 2];
-        o.n_outside_uv = st[8 * s + 3];
-        o.n_used = st[8 * s + 5];
-        o.n_contrib = st[8 * s + 6];
-        jobs[s].overflow = st[8 * s + 7] != 0;
+        const size_t k = 8 * (size_t)jobs[s].index;
+        o.n_flagged = st[k + 1];
+        o.n_bad_weight = st[k + 2];
+        o.n_outside_uv = st[k + 3];
+        o.n_used = st[k + 5];
+        o.n_contrib = st[k + 6];
+        jobs[s].overflow = st[k + 7] != 0;
     }
+}
+
+// Stack every job in one eager pass (the plain form: one launch sequence).  All output
+// cells of every job are written.
+static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t flags, hipStream_t stream,
+                     vista_timings* tim) {
+    DevMem mem(stream);
+    Events ev;
+    Launcher ln(stream, tu, flags);
+    for (size_t s = 0; s < jobs.size(); ++s) jobs[s].index = (int32_t)s;
+    HostLaunch h = build_launch(jobs, tu, ln.jsub());
+    VISTA_HIP(hipEventRecord(ev.e[0], stream));
+    make_resident(h, mem, stream);
+    unsigned long long* d_stats = mem.alloc_n<unsigned long long>(8 * jobs.size());
+    check_launch(launch_fill_u64(d_stats, 0ull, 8 * (int64_t)jobs.size(), stream), "fill");
+    ln.reserve(Capacity::of(h));
+    const int64_t nrec = ln.prepare(h, d_stats);
+    Capacity c = Capacity::of(h);
+    c.recs = nrec;
+    ln.reserve(c);
+    ln.sequence(&ev);
+    std::vector<unsigned long long> st(8 * jobs.size());
+    VISTA_HIP(hipMemcpyAsync(st.data(), d_stats, st.size() * 8, hipMemcpyDeviceToHost, stream));
+    VISTA_HIP(hipEventRecord(ev.e[3], stream));
+    VISTA_HIP(hipStreamSynchronize(stream));
+    collect_stats(jobs, st);
     if (tim) {
         tim->bin_ms = ev.ms(0, 1);
         tim->accum_ms = ev.ms(1, 2);
         tim->finalize_ms = ev.ms(2, 3);
         tim->total_ms = ev.ms(0, 3);
+        tim->h2d_ms = 0;
         tim->n_records = nrec;
-        tim->n_units = nunits;
+        tim->n_units = h.nunits;
         tim->n_accum_launches = 1;
         tim->n_waves = 1;
     }
-    mem.release();
 }
 
 // Resolve the user's outputs to device pointers; host outputs get device temporaries
@@ -900,37 +1035,252 @@ int vista_batch_set_stream_budget(vista_batch* b, int64_t bytes) {
     return VISTA_OK;
 }
 
+// Device bytes a streamed target occupies in staging (uvw, vis, weights, flags).
+static size_t staged_bytes(const vista_target& t) {
+    const size_t nr = (size_t)t.nrow, ns = nr * t.nchan * t.npol;
+    const size_t b_w = (t.weight_per_chan ? ns : nr * t.npol) * sizeof(float);
+    return align256(nr * 3 * sizeof(double)) + align256(ns * 8) + align256(b_w) + (t.flag ? align256(ns) : 0);
+}
+
+static int64_t default_stream_budget() {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess || fr == 0) return (int64_t)1 << 30;
+    return (int64_t)(fr / 8);   // two staging buffers take a quarter of the free memory
+}
+
 int vista_batch_run(vista_batch* b) {
     if (!b) return fail(VISTA_E_ARG, "batch is NULL");
     if (b->state != 0) return fail(VISTA_E_STATE, b->state == 1 ? "batch already ran" : "batch is poisoned");
     return guarded(&b->state, [&]() -> int {
-        b->keep = std::make_unique<DevMem>(b->stream);
-        size_t ns = b->g.size();
+        // the batch runs on streams of its own (a capture needs a stream other than the
+        // legacy default one), ordered after the caller's stream and before it again
+        struct StreamGuard {
+            hipStream_t s = nullptr, c = nullptr;
+            std::vector<hipEvent_t> ev;
+            ~StreamGuard() {
+                if (c) (void)hipStreamSynchronize(c);
+                if (s) (void)hipStreamSynchronize(s);
+                for (auto e : ev) (void)hipEventDestroy(e);
+                if (s) (void)hipStreamDestroy(s);
+                if (c) (void)hipStreamDestroy(c);
+            }
+            hipEvent_t make(unsigned fl) {
+                hipEvent_t e;
+                VISTA_HIP(hipEventCreateWithFlags(&e, fl));
+                ev.push_back(e);
+                return e;
+            }
+        } g;
+        VISTA_HIP(hipStreamCreateWithFlags(&g.s, hipStreamNonBlocking));
+        VISTA_HIP(hipStreamCreateWithFlags(&g.c, hipStreamNonBlocking));
+        hipStream_t us = b->stream;
+        hipStream_t st = g.c;
+        b->keep = std::make_unique<DevMem>(us);
+        const size_t ns = b->g.size();
+        const uint32_t flags = b->g[0].flags;
+        const bool kahan = (flags & VISTA_F_KAHAN) != 0;
         b->res.assign(ns, {});
-        std::vector<StackJob> jobs(ns);
         for (size_t s = 0; s < ns; ++s) {
             const vista_grid_desc& g = b->g[s];
-            size_t nc = (size_t)g.nu * g.nv * g.nchan;
+            const size_t nc = (size_t)g.nu * g.nv * g.nchan;
             auto& R = b->res[s];
             R.vis = b->keep->alloc_n<float2>(nc);
             R.w = b->keep->alloc_n<float>(nc);
             R.cnt = b->keep->alloc_n<uint32_t>(nc);
             R.vis64 = b->keep->alloc_n<double2>(nc);
             R.w64 = b->keep->alloc_n<double>(nc);
-            jobs[s].g = &b->g[s];
-            for (auto& h : b->targets[s]) jobs[s].targets.push_back(h.get());
-            jobs[s].out.sum_wvis = R.vis;
-            jobs[s].out.sum_w = R.w;
-            jobs[s].out.count = R.cnt;
-            jobs[s].out.sum_wvis64 = R.vis64;
-            jobs[s].out.sum_w64 = R.w64;
-            jobs[s].out.mem = VISTA_MEM_DEVICE;
         }
-        run_jobs(jobs, b->tune, b->g[0].flags, b->stream, &b->tim);
+        // ---- waves: device-resident targets go in the first; targets in host memory are
+        // packed, in order, into waves of at most `budget` staged bytes
+        const int64_t budget = b->stream_budget > 0 ? b->stream_budget : default_stream_budget();
+        struct Item { int32_t stack; HostTarget* h; size_t off; };
+        std::vector<std::vector<Item>> waves(1);
+        std::vector<size_t> wbytes(1, 0);
+        for (size_t s = 0; s < ns; ++s)
+            for (auto& hp : b->targets[s]) {
+                HostTarget* h = hp.get();
+                if (h->t.nrow == 0 || h->t.mem == VISTA_MEM_DEVICE) {
+                    waves[0].push_back({(int32_t)s, h, 0});
+                    continue;
+                }
+                const size_t nb = staged_bytes(h->t);
+                if ((int64_t)nb > budget) throw NoMem{"a target is larger than the stream budget"};
+                if (wbytes.back() > 0 && (int64_t)(wbytes.back() + nb) > budget) {
+                    waves.emplace_back();
+                    wbytes.push_back(0);
+                }
+                waves.back().push_back({(int32_t)s, h, wbytes.back()});
+                wbytes.back() += nb;
+            }
+        const size_t nw = waves.size();
+        // a stack takes part in the waves holding its targets (a stack without targets in
+        // the first, so that its cells are written)
+        std::vector<std::vector<char>> member(nw, std::vector<char>(ns, 0));
+        for (size_t w = 0; w < nw; ++w)
+            for (auto& it : waves[w]) member[w][it.stack] = 1;
+        for (size_t s = 0; s < ns; ++s)
+            if (b->targets[s].empty()) member[0][s] = 1;
+        std::vector<int> last(ns, -1), nwaves(ns, 0);
+        for (size_t w = 0; w < nw; ++w)
+            for (size_t s = 0; s < ns; ++s)
+                if (member[w][s]) {
+                    last[s] = (int)w;
+                    ++nwaves[s];
+                }
+        // ---- carried state of the stacks spread over several waves
+        std::vector<float*> cs_s(ns, nullptr), cs_c(ns, nullptr);
+        std::vector<uint32_t*> cs_n(ns, nullptr);
         for (size_t s = 0; s < ns; ++s) {
-            b->res[s].st = jobs[s].stats;
-            b->res[s].overflow = jobs[s].overflow;
+            if (nwaves[s] < 2) continue;
+            const vista_grid_desc& g = b->g[s];
+            const int64_t nc = (int64_t)g.nu * g.nv * g.nchan;
+            cs_s[s] = b->keep->alloc_n<float>(3 * nc);
+            cs_n[s] = b->keep->alloc_n<uint32_t>(nc);
+            if (kahan) cs_c[s] = b->keep->alloc_n<float>(3 * nc);
         }
+        unsigned long long* d_stats = b->keep->alloc_n<unsigned long long>(8 * ns);
+        size_t maxw = 0;
+        for (size_t w = 0; w < nw; ++w) maxw = std::max(maxw, wbytes[w]);
+        unsigned char* stage[2] = {nullptr, nullptr};
+        if (maxw > 0) {
+            stage[0] = b->keep->alloc_n<unsigned char>(maxw);
+            if (nw > 1) stage[1] = b->keep->alloc_n<unsigned char>(maxw);
+        }
+        // ---- the batch's streams start after the caller's stream (and these allocations)
+        hipEvent_t e_in = g.make(hipEventDisableTiming);
+        VISTA_HIP(hipEventRecord(e_in, us));
+        VISTA_HIP(hipStreamWaitEvent(st, e_in, 0));
+        VISTA_HIP(hipStreamWaitEvent(g.s, e_in, 0));
+        for (size_t s = 0; s < ns; ++s) {
+            if (!cs_s[s]) continue;
+            const vista_grid_desc& gd = b->g[s];
+            const int64_t nc = (int64_t)gd.nu * gd.nv * gd.nchan;
+            check_launch(launch_fill_u32((uint32_t*)cs_s[s], 0u, 3 * nc, st), "fill");
+            check_launch(launch_fill_u32(cs_n[s], 0u, nc, st), "fill");
+            if (cs_c[s]) check_launch(launch_fill_u32((uint32_t*)cs_c[s], 0u, 3 * nc, st), "fill");
+        }
+        check_launch(launch_fill_u64(d_stats, 0ull, 8 * (int64_t)ns, st), "fill");
+        // ---- one host launch per wave
+        Launcher ln(st, b->tune, flags);
+        std::vector<std::vector<StackJob>> wj(nw);
+        std::vector<HostLaunch> hl(nw);
+        Capacity cap;
+        for (size_t w = 0; w < nw; ++w) {
+            std::vector<int> slot(ns, -1);
+            for (size_t s = 0; s < ns; ++s) {
+                if (!member[w][s]) continue;
+                StackJob J;
+                J.g = &b->g[s];
+                J.index = (int32_t)s;
+                auto& R = b->res[s];
+                J.out.sum_wvis = R.vis; J.out.sum_w = R.w; J.out.count = R.cnt;
+                J.out.sum_wvis64 = R.vis64; J.out.sum_w64 = R.w64;
+                J.out.mem = VISTA_MEM_DEVICE;
+                J.carry = nwaves[s] > 1 ? 1 : 0;
+                J.last = (int)w == last[s] ? 1 : 0;
+                J.st_s = cs_s[s]; J.st_c = cs_c[s]; J.st_n = cs_n[s];
+                slot[s] = (int)wj[w].size();
+                wj[w].push_back(J);
+            }
+            for (auto& it : waves[w]) wj[w][slot[it.stack]].targets.push_back(it.h);
+            hl[w] = build_launch(wj[w], b->tune, ln.jsub());
+            cap = cap.max_with(Capacity::of(hl[w]));
+        }
+        ln.reserve(cap);
+        std::vector<hipEvent_t> copied(nw), done(nw), t0(nw), t1(nw), t2(nw), c0(nw), c1(nw);
+        for (size_t w = 0; w < nw; ++w) {
+            copied[w] = g.make(hipEventDisableTiming);
+            done[w] = g.make(hipEventDisableTiming);
+            t0[w] = g.make(hipEventDefault); t1[w] = g.make(hipEventDefault); t2[w] = g.make(hipEventDefault);
+            c0[w] = g.make(hipEventDefault); c1[w] = g.make(hipEventDefault);
+        }
+        hipEvent_t e_start = g.make(hipEventDefault), e_end = g.make(hipEventDefault);
+        VISTA_HIP(hipEventRecord(e_start, st));
+        // device pointers of wave w's targets; streamed ones are copied into its buffer
+        auto stage_wave = [&](size_t w) {
+            HostLaunch& h = hl[w];
+            unsigned char* base = stage[w & 1];
+            if (w >= 2) VISTA_HIP(hipStreamWaitEvent(g.s, done[w - 2], 0));   // that buffer's last reader
+            VISTA_HIP(hipEventRecord(c0[w], g.s));
+            for (size_t i = 0; i < h.dts.size(); ++i) {
+                DevTarget& T = h.dts[i];
+                const vista_target& t = h.hts[i]->t;
+                if (t.mem == VISTA_MEM_DEVICE) {
+                    T.uvw = t.uvw; T.vis = (const float2*)t.vis; T.weight = t.weight; T.flag = t.flag;
+                    continue;
+                }
+                size_t off = 0;
+                for (auto& it : waves[w])
+                    if (it.h == h.hts[i]) off = it.off;
+                const size_t nr = (size_t)t.nrow, nsm = nr * t.nchan * t.npol;
+                const size_t b_w = (t.weight_per_chan ? nsm : nr * t.npol) * sizeof(float);
+                unsigned char* p = base + off;
+                VISTA_HIP(hipMemcpyAsync(p, t.uvw, nr * 24, hipMemcpyHostToDevice, g.s));
+                T.uvw = (const double*)p; p += align256(nr * 24);
+                VISTA_HIP(hipMemcpyAsync(p, t.vis, nsm * 8, hipMemcpyHostToDevice, g.s));
+                T.vis = (const float2*)p; p += align256(nsm * 8);
+                VISTA_HIP(hipMemcpyAsync(p, t.weight, b_w, hipMemcpyHostToDevice, g.s));
+                T.weight = (const float*)p; p += align256(b_w);
+                T.flag = nullptr;
+                if (t.flag) {
+                    VISTA_HIP(hipMemcpyAsync(p, t.flag, nsm, hipMemcpyHostToDevice, g.s));
+                    T.flag = (const uint8_t*)p;
+                }
+            }
+            VISTA_HIP(hipEventRecord(c1[w], g.s));
+            VISTA_HIP(hipEventRecord(copied[w], g.s));
+        };
+        int64_t nrec_total = 0;
+        stage_wave(0);
+        for (size_t w = 0; w < nw; ++w) {
+            if (w + 1 < nw) stage_wave(w + 1);     // overlaps this wave's compute
+            VISTA_HIP(hipStreamWaitEvent(st, copied[w], 0));
+            VISTA_HIP(hipEventRecord(t0[w], st));
+            const int64_t nrec = ln.prepare(hl[w], d_stats);
+            nrec_total += nrec;
+            Capacity c = ln.capacity();
+            c.recs = nrec;
+            ln.reserve(c);
+            VISTA_HIP(hipEventRecord(t1[w], st));
+            ln.replay();
+            VISTA_HIP(hipEventRecord(t2[w], st));
+            VISTA_HIP(hipEventRecord(done[w], st));
+        }
+        std::vector<unsigned long long> stv(8 * ns);
+        VISTA_HIP(hipMemcpyAsync(stv.data(), d_stats, stv.size() * 8, hipMemcpyDeviceToHost, st));
+        VISTA_HIP(hipEventRecord(e_end, st));
+        VISTA_HIP(hipStreamWaitEvent(us, e_end, 0));   // the caller's stream resumes after the batch
+        VISTA_HIP(hipStreamSynchronize(st));
+        VISTA_HIP(hipStreamSynchronize(g.s));
+        // per-stack classification over all waves
+        std::vector<StackJob> all(ns);
+        for (size_t s = 0; s < ns; ++s) {
+            all[s].g = &b->g[s];
+            all[s].index = (int32_t)s;
+            for (auto& hp : b->targets[s]) all[s].targets.push_back(hp.get());
+        }
+        collect_stats(all, stv);
+        for (size_t s = 0; s < ns; ++s) {
+            b->res[s].st = all[s].stats;
+            b->res[s].overflow = all[s].overflow;
+        }
+        vista_timings& T = b->tim;
+        memset(&T, 0, sizeof(T));
+        auto ms = [](hipEvent_t a, hipEvent_t z) {
+            float t = 0;
+            (void)hipEventElapsedTime(&t, a, z);
+            return (double)t;
+        };
+        for (size_t w = 0; w < nw; ++w) {
+            T.bin_ms += ms(t0[w], t1[w]);
+            T.accum_ms += ms(t1[w], t2[w]);
+            if (wbytes[w] > 0) T.h2d_ms += ms(c0[w], c1[w]);
+        }
+        T.total_ms = ms(e_start, e_end);
+        T.n_records = nrec_total;
+        T.n_units = cap.units;
+        T.n_accum_launches = (int32_t)nw;
+        T.n_waves = (int32_t)nw;
         b->state = 1;
         return VISTA_OK;
     });

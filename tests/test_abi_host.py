@@ -154,3 +154,4 @@ def test_failure_paths_forced_from_host(monkeypatch):
         s.close()
         for k in env:
             monkeypatch.delenv(k)
+

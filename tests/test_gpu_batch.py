@@ -1,0 +1,125 @@
+"""Batched form on the GPU: several stacks in one graph-replayed launch sequence, inputs
+streamed from pinned host memory in waves with the grid state carried between waves,
+all against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2609_01897_amd import vista  # noqa: E402
+from tests.gpu_util import compare  # noqa: E402
+
+
+def _pinned(t):
+    """The target with every array in pinned host memory."""
+    d = t.to("cpu")
+    for k in ("uvw", "vis", "weight", "flag"):
+        v = getattr(d, k)
+        if v is not None:
+            setattr(d, k, v.pin_memory())
+    return d
+
+
+def _batch(grids, targets_per_stack, flags=0, budget=None, fp64=False, tuning=None):
+    gs = [dict(g, flags=int(g.get("flags", 0)) | flags) for g in grids]
+    b = vista.Batch(gs, tuning=tuning)
+    if budget:
+        b.set_stream_budget(budget)
+    for s, ts in enumerate(targets_per_stack):
+        for t in ts:
+            b.add(s, t)
+    b.run()
+    tim = b.timings()
+    res = []
+    for s, g in enumerate(gs):
+        out = vista.alloc_outputs(g, fp64=fp64)
+        st = b.finalize(s, out)
+        res.append(({k: v.cpu().numpy() for k, v in out.items()}, st))
+    b.close()
+    return res, tim
+
+
+def _stacks():
+    grids, hs = [], []
+    for i, name in enumerate(["small", "tiny", "c1"]):
+        cfg = synth.config(name)
+        grids.append(synth.make_grid(cfg))
+        hs.append(synth.make_targets(cfg, n=min(cfg.n_targets, 3 + i)))
+    return grids, hs
+
+
+@pytest.mark.parametrize("flags", [0, "kahan", "deterministic"])
+def test_streamed_waves_match_oracle(flags):
+    """Pinned host targets, a staging budget that forces several waves: every stack still
+    matches the oracle (plain, compensated and deterministic modes)."""
+    fl = {0: 0, "kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC}[flags]
+    grids, hs = _stacks()
+    pinned = [[_pinned(t) for t in ts] for ts in hs]
+    res, tim = _batch(grids, pinned, flags=fl, budget=9 << 20)
+    assert tim["n_waves"] >= 3, tim
+    for s, g in enumerate(grids):
+        o = oracle.stack(g, hs[s])
+        out, st = res[s]
+        compare(o, out, st=st)
+
+
+def test_mixed_resident_and_streamed_targets():
+    grids, hs = _stacks()
+    mixed = [[t.to("cuda") if i % 2 == 0 else _pinned(t) for i, t in enumerate(ts)] for ts in hs]
+    res, tim = _batch(grids, mixed, budget=9 << 20)
+    assert tim["n_waves"] >= 2
+    for s, g in enumerate(grids):
+        compare(oracle.stack(g, hs[s]), res[s][0], st=res[s][1])
+
+
+def test_streamed_kahan_fp64_outputs():
+    """Compensated carry across waves keeps the FP64 outputs close to the oracle."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    hs = synth.make_targets(cfg)
+    res, tim = _batch([g], [[_pinned(t) for t in hs]], flags=vista.F_KAHAN, budget=9 << 20, fp64=True)
+    assert tim["n_waves"] >= 2
+    out, st = res[0]
+    o = oracle.stack(g, hs)
+    nz = o["N"] > 0
+    e = np.abs(out["sum_wvis64"] - o["S"])[nz] / o["A"][nz]
+    assert e.max() < 1e-6, e.max()
+
+
+def test_deterministic_batch_is_bit_identical():
+    """Two runs of the same deterministic streamed batch give the same bits."""
+    grids, hs = _stacks()
+    r1, _ = _batch(grids, [[_pinned(t) for t in ts] for ts in hs], flags=vista.F_DETERMINISTIC, budget=9 << 20)
+    r2, _ = _batch(grids, [[_pinned(t) for t in ts] for ts in hs], flags=vista.F_DETERMINISTIC, budget=9 << 20)
+    for (a, _), (b, _) in zip(r1, r2):
+        for k in ("sum_wvis", "sum_w", "count"):
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8))
+
+
+def test_batch_with_an_empty_stack():
+    grids, hs = _stacks()
+    hs[1] = []
+    res, _ = _batch(grids, [[t.to("cuda") for t in ts] for ts in hs])
+    assert not res[1][0]["count"].any() and not res[1][0]["sum_w"].any()
+    for s in (0, 2):
+        compare(oracle.stack(grids[s], hs[s]), res[s][0], st=res[s][1])
+
+
+def test_target_over_stream_budget_is_rejected():
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    t = _pinned(synth.make_target(cfg, 0))
+    b = vista.Batch([g])
+    b.set_stream_budget(1 << 20)
+    b.add(0, t)
+    with pytest.raises(vista.VistaError) as e:
+        b.run()
+    assert e.value.code == vista.VISTA_E_NOMEM
+    b.close()
