@@ -97,6 +97,79 @@ def copy_probe(nbytes, steps):
                       "ms_per_launch": ms, "GB/s": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
+BATCH_STACKS = 64
+BATCH_MU = math.log(4.0)     # targets per stack ~ clip(round(lognormal(log 4, 1)), 1, 64)
+BATCH_N_INT = 10
+
+
+def batched_leg(reps: int):
+    """The batched recipe, reduced to fit a one-minute bench: 64 stacks with lognormal
+    target counts and mixed channel layouts, stacked (a) one stack per launch sequence,
+    (b) as one batch (one captured graph), (c) as one batch with Kahan compensation.
+    Every form writes every stack's output grid (the batch writes them in place)."""
+    import torch
+    import synth
+    from paper_2609_01897_amd import vista
+    sizes = synth.batch_stack_sizes(BATCH_STACKS, seed=20260904, lo=1, hi=64, mu=BATCH_MU)
+    base = synth.config("c4", n_int=BATCH_N_INT)
+    t0 = time.perf_counter()
+    stacks = []
+    for s, n in enumerate(sizes):
+        cfg = synth.config("c4", n_int=BATCH_N_INT, seed=base.seed + 1000 * (s + 1))
+        stacks.append([synth.make_target(cfg, i, device="cuda") for i in range(n)])
+    grid = synth.make_grid(base)
+    torch.cuda.synchronize()
+    nsamp = sum(int(t.vis.numel()) for ts in stacks for t in ts)
+    log("batched recipe: %d stacks, %d targets, %.3g samples, generated in %.1f s"
+        % (len(stacks), sum(sizes), nsamp, time.perf_counter() - t0))
+    outs = [vista.alloc_outputs(grid) for _ in stacks]
+
+    def plain():
+        for s, ts in enumerate(stacks):
+            vista.stack(grid, ts, out=outs[s])
+
+    def batched(flags):
+        g = dict(grid, flags=flags)
+        b = vista.Batch([g] * len(stacks))
+        for s, ts in enumerate(stacks):
+            for t in ts:
+                b.add(s, t)
+            b.set_output(s, outs[s])            # written in place by the run
+        b.run()
+        for s in range(len(stacks)):
+            b.finalize(s)
+        tim = b.timings()
+        b.close()
+        return tim
+
+    def timed(fn, *a):
+        fn(*a)                                  # warm-up (code objects, pools, graph path)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn(*a)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    ms_plain = timed(plain)
+    ms_batch = timed(batched, 0)
+    ms_kahan = timed(batched, vista.F_KAHAN)
+    log("batched recipe: plain %.1f ms, batched %.1f ms, batched+Kahan %.1f ms" % (ms_plain, ms_batch, ms_kahan))
+    del stacks, outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": "batched recipe reduced: %d stacks, targets per stack lognormal(log 4, 1) in [1, 64] "
+                    "(%d total), 12-50 antennas, %d integrations, channels from {128, 480, 960, 3840}, "
+                    "grid 256x256x256 per stack" % (len(sizes), sum(sizes), BATCH_N_INT),
+        "samples": nsamp,
+        "plain_one_stack_per_launch_ms": ms_plain,
+        "batched_graph_ms": ms_batch,
+        "batched_kahan_ms": ms_kahan,
+        "speedup_batched_vs_plain": ms_plain / ms_batch,
+        "speedup_batched_kahan_vs_plain": ms_plain / ms_kahan,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +180,7 @@ def main():
     ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32")
     ap.add_argument("--cpu-targets", type=int, default=8, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel on MIB MiB, --steps times (calibrates "
@@ -217,6 +291,10 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on %d targets" % args.cpu_targets)
         res["cpu_baseline"] = cpu_baseline(targets, grid, args.cpu_targets)
+    if not args.no_batched:
+        del targets, out
+        torch.cuda.empty_cache()
+        res["batched"] = batched_leg(reps=2)
     print(json.dumps(res), flush=True)
 
 

@@ -47,8 +47,13 @@ enum { VISTA_MEM_HOST = 0, VISTA_MEM_HOST_PINNED = 1, VISTA_MEM_DEVICE = 2 };
 
 /* Grid flags. */
 enum {
-    VISTA_F_KAHAN = 1u << 0,            /* compensated FP32 accumulation (ordered path) */
-    VISTA_F_DETERMINISTIC = 1u << 1,    /* bit-identical results from run to run */
+    VISTA_F_KAHAN = 1u << 0,            /* compensated FP32 accumulation: grid state kept in
+                                           FP32 is updated with Kahan's compensated addition
+                                           (the state carried across the waves of a batch;
+                                           with VISTA_F_DETERMINISTIC also the per-tile sums).
+                                           Without DETERMINISTIC the per-tile sums are FP64. */
+    VISTA_F_DETERMINISTIC = 1u << 1,    /* every addition in a fixed order: bit-identical
+                                           results from run to run (slower) */
     VISTA_F_SPECTRAL_NEAREST = 1u << 2, /* each input channel goes whole to the rest
                                            channel holding nu_obs (1+z) */
     VISTA_F_PHASE_FP32 = 1u << 3        /* ablation: form u_lambda and the phase turns in
@@ -96,8 +101,8 @@ typedef struct {
 /* Outputs, dense [nchan][nv][nu] over the whole grid.  Any pointer may be NULL to skip
  * that output.  sum_wvis is complex64, sum_w float, count uint32 (contributions, one per
  * (sample, rest channel) pair).  sum_wvis64 (complex128) and sum_w64 (double) receive
- * the compensated sums s - c in FP64 when VISTA_F_KAHAN is set, the FP32 sums widened
- * otherwise. */
+ * the sums before their rounding to FP32: the FP64 per-tile sums, or s - c of a
+ * compensated FP32 state (VISTA_F_KAHAN with a carried or ordered state). */
 typedef struct {
     void* sum_wvis;
     void* sum_w;
@@ -182,7 +187,13 @@ int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t)
 int vista_batch_set_tuning(vista_batch* b, const vista_tuning* tu);
 /* Device memory the batch may use for streamed input staging (bytes; 0 = default). */
 int vista_batch_set_stream_budget(vista_batch* b, int64_t bytes);
+/* Register the outputs of one stack before vista_batch_run: VISTA_MEM_DEVICE outputs
+ * are then written by the run itself (no copy at finalize), and only the outputs given
+ * are produced.  Other memory kinds are filled at finalize.  Errors: ARG, STATE. */
+int vista_batch_set_output(vista_batch* b, int32_t stack, const vista_output* o);
 int vista_batch_run(vista_batch* b);
+/* Copy one stack's results into o (may be NULL when its outputs were registered) and
+ * return its classification in *st (may be NULL).  Errors: ARG, STATE, HIP, RANGE. */
 int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, vista_stats* st);
 int vista_batch_timings(const vista_batch* b, vista_timings* t);
 int vista_batch_destroy(vista_batch* b);

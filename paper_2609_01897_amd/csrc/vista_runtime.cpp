@@ -172,14 +172,14 @@ struct Tuning {
 // Launch shapes the kernels are built for: the packed kernel's (plain mode) or the
 // ordered kernel's (deterministic and compensated modes).
 static bool shape_ok(const Tuning& t, uint32_t flags) {
-    if (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN))
+    if (flags & VISTA_F_DETERMINISTIC)
         return accum_shape_supported(t.tu, t.tv, t.jc, t.waves, kModeOrdered, (flags & VISTA_F_KAHAN) ? 1 : 0);
     return accum_packed_shape_supported(t.tu, t.tv, t.jc, t.waves);
 }
 
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
-    if (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) {
+    if (flags & VISTA_F_DETERMINISTIC) {
         t.tu = 8; t.tv = 4; t.jc = 128; t.waves = 8;   // ordered: 16-channel slices per wave
     }
     return t;
@@ -229,6 +229,7 @@ struct vista_batch {
         bool overflow = false;
     };
     std::vector<Result> res;
+    std::vector<vista_output> reg;    // outputs registered before the run (mem < 0: none)
     std::unique_ptr<DevMem> keep;
 };
 
@@ -428,7 +429,7 @@ class Launcher {
   public:
     Launcher(hipStream_t s, const Tuning& tu, uint32_t flags)
         : s_(s), tu_(tu), mem_(s), recmem_(s) {
-        mode_ = (flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN)) ? kModeOrdered : kModeAtomic;
+        mode_ = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
         kahan_ = (flags & VISTA_F_KAHAN) ? 1 : 0;
         phase_fp32_ = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
         jsub_ = mode_ == kModeOrdered ? tu.jc / tu.waves : tu.jc;
@@ -993,6 +994,9 @@ int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_str
         b->g.assign(g, g + n_stacks);
         b->stream = (hipStream_t)hip_stream;
         b->targets.resize(n_stacks);
+        vista_output none{};
+        none.mem = -1;
+        b->reg.assign(n_stacks, none);
         b->tune = default_tuning(g[0].flags);
         *out = b;
         return VISTA_OK;
@@ -1084,11 +1088,18 @@ int vista_batch_run(vista_batch* b) {
             const vista_grid_desc& g = b->g[s];
             const size_t nc = (size_t)g.nu * g.nv * g.nchan;
             auto& R = b->res[s];
-            R.vis = b->keep->alloc_n<float2>(nc);
-            R.w = b->keep->alloc_n<float>(nc);
-            R.cnt = b->keep->alloc_n<uint32_t>(nc);
-            R.vis64 = b->keep->alloc_n<double2>(nc);
-            R.w64 = b->keep->alloc_n<double>(nc);
+            const vista_output& o = b->reg[s];
+            if (o.mem == VISTA_MEM_DEVICE) {          // written in place
+                R.vis = (float2*)o.sum_wvis; R.w = (float*)o.sum_w; R.cnt = (uint32_t*)o.count;
+                R.vis64 = (double2*)o.sum_wvis64; R.w64 = (double*)o.sum_w64;
+                continue;
+            }
+            const bool any = o.mem < 0;               // nothing registered: keep everything
+            if (any || o.sum_wvis) R.vis = b->keep->alloc_n<float2>(nc);
+            if (any || o.sum_w) R.w = b->keep->alloc_n<float>(nc);
+            if (any || o.count) R.cnt = b->keep->alloc_n<uint32_t>(nc);
+            if (any || o.sum_wvis64) R.vis64 = b->keep->alloc_n<double2>(nc);
+            if (any || o.sum_w64) R.w64 = b->keep->alloc_n<double>(nc);
         }
         // ---- waves: device-resident targets go in the first; targets in host memory are
         // packed, in order, into waves of at most `budget` staged bytes
@@ -1286,23 +1297,40 @@ int vista_batch_run(vista_batch* b) {
     });
 }
 
+int vista_batch_set_output(vista_batch* b, int32_t stack, const vista_output* o) {
+    if (!b || !o) return fail(VISTA_E_ARG, "NULL argument");
+    if (b->state != 0) return fail(VISTA_E_STATE, "batch already ran");
+    if (stack < 0 || stack >= (int32_t)b->g.size()) return fail(VISTA_E_ARG, "stack index out of range");
+    std::string why;
+    if (!check_output(o, &why)) return fail(VISTA_E_ARG, why);
+    b->reg[stack] = *o;
+    return VISTA_OK;
+}
+
 int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, vista_stats* st) {
     if (!b) return fail(VISTA_E_ARG, "batch is NULL");
     if (b->state != 1) return fail(VISTA_E_STATE, b->state == 0 ? "batch has not run" : "batch is poisoned");
     if (stack < 0 || stack >= (int32_t)b->g.size()) return fail(VISTA_E_ARG, "stack index out of range");
     std::string why;
     if (!check_output(o, &why)) return fail(VISTA_E_ARG, why);
+    const vista_output& reg = b->reg[stack];
+    if (!o && reg.mem >= 0 && reg.mem != VISTA_MEM_DEVICE) o = &reg;   // registered host outputs
     return guarded(&b->state, [&]() -> int {
         const vista_grid_desc& g = b->g[stack];
         size_t nc = (size_t)g.nu * g.nv * g.nchan;
         auto& R = b->res[stack];
-        hipMemcpyKind kind = (o && o->mem == VISTA_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (o) {
-            if (o->sum_wvis) VISTA_HIP(hipMemcpyAsync(o->sum_wvis, R.vis, nc * 8, kind, b->stream));
-            if (o->sum_w) VISTA_HIP(hipMemcpyAsync(o->sum_w, R.w, nc * 4, kind, b->stream));
-            if (o->count) VISTA_HIP(hipMemcpyAsync(o->count, R.cnt, nc * 4, kind, b->stream));
-            if (o->sum_wvis64) VISTA_HIP(hipMemcpyAsync(o->sum_wvis64, R.vis64, nc * 16, kind, b->stream));
-            if (o->sum_w64) VISTA_HIP(hipMemcpyAsync(o->sum_w64, R.w64, nc * 8, kind, b->stream));
+            hipMemcpyKind kind = o->mem == VISTA_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+            auto copy = [&](void* dst, const void* src, size_t n, const char* what) {
+                if (!dst || dst == src) return;
+                if (!src) throw HipFail{hipErrorInvalidValue, std::string("output not kept by the run: ") + what};
+                VISTA_HIP(hipMemcpyAsync(dst, src, n, kind, b->stream));
+            };
+            copy(o->sum_wvis, R.vis, nc * 8, "sum_wvis");
+            copy(o->sum_w, R.w, nc * 4, "sum_w");
+            copy(o->count, R.cnt, nc * 4, "count");
+            copy(o->sum_wvis64, R.vis64, nc * 16, "sum_wvis64");
+            copy(o->sum_w64, R.w64, nc * 8, "sum_w64");
         }
         VISTA_HIP(hipStreamSynchronize(b->stream));
         if (st) *st = R.st;

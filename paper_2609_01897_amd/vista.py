@@ -90,6 +90,7 @@ SYMBOLS = {
                              C.c_void_p, C.c_void_p], C.c_int),
     "vista_debug_rotate": ([C.POINTER(GridDesc), C.POINTER(TargetDesc), C.c_void_p, C.c_void_p], C.c_int),
     "vista_debug_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "vista_batch_set_output": ([C.c_void_p, C.c_int32, C.POINTER(Output)], C.c_int),
     "vista_last_error": ([], C.c_char_p),
     "vista_version": ([], C.c_char_p),
 }
@@ -263,15 +264,19 @@ class Batch:
     def set_stream_budget(self, nbytes: int):
         _check(lib().vista_batch_set_stream_budget(self.h, int(nbytes)))
 
+    def set_output(self, stack_index: int, out: dict):
+        """Register a stack's outputs before run(); device outputs are written in place."""
+        o = _output(out)
+        self._keep.append(out)
+        _check(lib().vista_batch_set_output(self.h, int(stack_index), C.byref(o)))
+
     def run(self):
         _check(lib().vista_batch_run(self.h))
 
-    def finalize(self, stack_index: int, out: dict) -> dict:
-        o = Output(_ptr(out.get("sum_wvis")), _ptr(out.get("sum_w")), _ptr(out.get("count")),
-                   _ptr(out.get("sum_wvis64")), _ptr(out.get("sum_w64")),
-                   _mem_of(next(v for v in out.values() if v is not None)))
+    def finalize(self, stack_index: int, out: dict | None = None) -> dict:
         st = Stats()
-        _check(lib().vista_batch_finalize(self.h, int(stack_index), C.byref(o), C.byref(st)))
+        o = C.byref(_output(out)) if out is not None else None
+        _check(lib().vista_batch_finalize(self.h, int(stack_index), o, C.byref(st)))
         return st.as_dict()
 
     def timings(self) -> dict:
@@ -290,6 +295,12 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _output(out: dict) -> Output:
+    return Output(_ptr(out.get("sum_wvis")), _ptr(out.get("sum_w")), _ptr(out.get("count")),
+                  _ptr(out.get("sum_wvis64")), _ptr(out.get("sum_w64")),
+                  _mem_of(next(v for v in out.values() if v is not None)))
 
 
 def debug_indices(grid: dict, t, stream=None) -> dict:

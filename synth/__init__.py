@@ -7,6 +7,7 @@ method's arithmetic (no phase re-centring, no rest-frame rebinning, no
 gridding).  Random numbers are drawn here and handed to both sides as inputs.
 """
 from .configs import CONFIGS, config, grid_for
-from .generate import Target, make_target, make_targets, make_grid
+from .generate import Target, batch_stack_sizes, make_target, make_targets, make_grid
 
-__all__ = ["CONFIGS", "config", "grid_for", "Target", "make_target", "make_targets", "make_grid"]
+__all__ = ["CONFIGS", "config", "grid_for", "Target", "batch_stack_sizes", "make_target", "make_targets",
+           "make_grid"]

@@ -27,7 +27,9 @@ def _pinned(t):
     return d
 
 
-def _batch(grids, targets_per_stack, flags=0, budget=None, fp64=False, tuning=None):
+def _batch(grids, targets_per_stack, flags=0, budget=None, fp64=False, tuning=None, register=False):
+    """Run a batch; register=True hands the device outputs over before the run (written
+    in place), otherwise finalize copies them out."""
     gs = [dict(g, flags=int(g.get("flags", 0)) | flags) for g in grids]
     b = vista.Batch(gs, tuning=tuning)
     if budget:
@@ -35,13 +37,16 @@ def _batch(grids, targets_per_stack, flags=0, budget=None, fp64=False, tuning=No
     for s, ts in enumerate(targets_per_stack):
         for t in ts:
             b.add(s, t)
+    outs = [vista.alloc_outputs(g, fp64=fp64) for g in gs]
+    if register:
+        for s, out in enumerate(outs):
+            b.set_output(s, out)
     b.run()
     tim = b.timings()
     res = []
     for s, g in enumerate(gs):
-        out = vista.alloc_outputs(g, fp64=fp64)
-        st = b.finalize(s, out)
-        res.append(({k: v.cpu().numpy() for k, v in out.items()}, st))
+        st = b.finalize(s, None if register else outs[s])
+        res.append(({k: v.cpu().numpy() for k, v in outs[s].items()}, st))
     b.close()
     return res, tim
 
@@ -55,11 +60,12 @@ def _stacks():
     return grids, hs
 
 
-@pytest.mark.parametrize("flags", [0, "kahan", "deterministic"])
+@pytest.mark.parametrize("flags", [0, "kahan", "deterministic", "deterministic_kahan"])
 def test_streamed_waves_match_oracle(flags):
     """Pinned host targets, a staging budget that forces several waves: every stack still
     matches the oracle (plain, compensated and deterministic modes)."""
-    fl = {0: 0, "kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC}[flags]
+    fl = {0: 0, "kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC,
+          "deterministic_kahan": vista.F_DETERMINISTIC | vista.F_KAHAN}[flags]
     grids, hs = _stacks()
     pinned = [[_pinned(t) for t in ts] for ts in hs]
     res, tim = _batch(grids, pinned, flags=fl, budget=9 << 20)
@@ -123,3 +129,14 @@ def test_target_over_stream_budget_is_rejected():
         b.run()
     assert e.value.code == vista.VISTA_E_NOMEM
     b.close()
+
+
+@pytest.mark.parametrize("budget", [None, 9 << 20])
+def test_registered_outputs_written_in_place(budget):
+    """Outputs handed over before the run receive the results directly (one wave and
+    several)."""
+    grids, hs = _stacks()
+    ts = [[_pinned(t) for t in x] for x in hs] if budget else [[t.to("cuda") for t in x] for x in hs]
+    res, _ = _batch(grids, ts, budget=budget, register=True)
+    for s, g in enumerate(grids):
+        compare(oracle.stack(g, hs[s]), res[s][0], st=res[s][1])

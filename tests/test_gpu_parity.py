@@ -20,7 +20,8 @@ if not torch.cuda.is_available():
 from paper_2609_01897_amd import vista  # noqa: E402
 from tests.gpu_util import compare, gpu_stack, targets_on_gpu  # noqa: E402
 
-MODES = {"atomic": 0, "deterministic": vista.F_DETERMINISTIC, "kahan": vista.F_KAHAN}
+MODES = {"atomic": 0, "deterministic": vista.F_DETERMINISTIC, "kahan": vista.F_KAHAN,
+         "deterministic_kahan": vista.F_DETERMINISTIC | vista.F_KAHAN}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -107,7 +108,7 @@ def test_phase_fp32_ablation_loses_cycles():
 
 @pytest.mark.parametrize("variant", ["descending", "jitter_width", "perchan_badw", "nearest", "odd_small_grid",
                                      "npol1", "npol4", "no_flags"])
-@pytest.mark.parametrize("mode", ["atomic", "kahan"])
+@pytest.mark.parametrize("mode", ["atomic", "deterministic_kahan"])
 def test_edge_layouts(variant, mode):
     cfg = synth.config("small")
     kw = {}
@@ -158,10 +159,15 @@ def test_no_targets_gives_zero_grid():
     assert st["n_samples"] == 0
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128), (4, 4, 256),
-                                   (8, 2, 256), (4, 2, 512)])
+PACKED_SHAPES = [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128), (4, 4, 256), (8, 2, 256),
+                 (4, 2, 512), (4, 4, 128), (8, 4, 64), (8, 2, 128), (4, 2, 256)]
+ORDERED_SHAPES = PACKED_SHAPES[:8]
+
+
+@pytest.mark.parametrize("shape", PACKED_SHAPES)
 def test_every_tile_shape_matches(shape):
-    """The autotuner's candidates change only speed: counts identical, sums in tolerance."""
+    """The autotuner's candidates change only speed: counts identical, sums in tolerance
+    (plain and compensated; the ordered kernel on the shapes it is built for)."""
     cfg = synth.config("small")
     hs, ds = targets_on_gpu(cfg)
     g = synth.make_grid(cfg)
@@ -171,6 +177,9 @@ def test_every_tile_shape_matches(shape):
     compare(o, out, st=st)
     out, st = gpu_stack(g, ds, flags=vista.F_KAHAN, tuning=tu)
     compare(o, out, st=st)
+    if shape in ORDERED_SHAPES:
+        out, st = gpu_stack(g, ds, flags=vista.F_DETERMINISTIC | vista.F_KAHAN, tuning=tu)
+        compare(o, out, st=st)
 
 
 def test_deterministic_mode_is_bit_identical():
@@ -184,12 +193,15 @@ def test_deterministic_mode_is_bit_identical():
             assert np.array_equal(out[k].view(np.uint8), ref[k].view(np.uint8))
 
 
-def test_kahan_fp64_outputs():
+@pytest.mark.parametrize("flags", ["kahan", "deterministic_kahan"])
+def test_kahan_fp64_outputs(flags):
+    """The FP64 outputs (FP64 tile sums, or s - c of the compensated FP32 tile sums) are
+    much closer to the oracle than the 1e-5 of the FP32 outputs."""
     cfg = synth.config("small")
     hs, ds = targets_on_gpu(cfg)
     g = synth.make_grid(cfg)
     o = oracle.stack(g, hs)
-    out, st = gpu_stack(g, ds, flags=vista.F_KAHAN, fp64=True)
+    out, st = gpu_stack(g, ds, flags=MODES[flags], fp64=True)
     nz = o["N"] > 0
     e = np.abs(out["sum_wvis64"] - o["S"])[nz] / o["A"][nz]
     assert e.max() < 1e-6
