@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=8, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel on MIB MiB, --steps times (calibrates "
@@ -220,6 +221,17 @@ def main():
     log("generated %d targets on the GPU in %.1f s" % (ntg, time.perf_counter() - t0))
     nbytes, nsamp = algorithmic_bytes(targets, grid)
     out = vista.alloc_outputs(grid)
+
+    tuned = None
+    if tuning is None and not args.no_autotune:
+        t0 = time.perf_counter()
+        s = vista.Stack(grid, flags=flags)
+        for t in targets:
+            s.add(t)
+        tuned = s.autotune()
+        s.close()
+        tuning = tuned
+        log("autotuned launch shape %s in %.1f s" % (tuned, time.perf_counter() - t0))
 
     def step():
         s = vista.Stack(grid, flags=flags, tuning=tuning)
@@ -278,6 +290,7 @@ def main():
             "binning_ms": sum(binms) / len(binms),
             "records": tim["n_records"],
             "units": tim["n_units"],
+            "launch_shape": dict(tuning or {}, source="autotuned" if tuned else ("given" if tuning else "default")),
         },
         "roofline": {
             "bound": "hbm",

@@ -230,6 +230,10 @@ int vista_debug_copy(void* dst, const void* src, size_t nbytes, void* hip_stream
  * the stack's targets must be VISTA_MEM_DEVICE. */
 int vista_stack_autotune(vista_stack* s, vista_tuning* best);
 
+/* The same for a batch: every stack's device-resident targets in one launch per
+ * candidate; the result applies to vista_batch_run. */
+int vista_batch_autotune(vista_batch* b, vista_tuning* best);
+
 const char* vista_last_error(void);
 const char* vista_version(void);
 

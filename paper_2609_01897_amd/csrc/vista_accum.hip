@@ -572,6 +572,18 @@ hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, cons
     X(8, 2, 128)               \
     X(4, 2, 256)
 
+int accum_packed_shape_list(int* tu, int* tv, int* jc, int cap) {
+    int n = 0;
+#define X(a, b, c)            \
+    if (n < cap) {            \
+        tu[n] = a; tv[n] = b; jc[n] = c; \
+    }                         \
+    ++n;
+    VISTA_PACKED_SHAPES(X)
+#undef X
+    return n;
+}
+
 bool accum_packed_shape_supported(int tu, int tv, int jc, int waves) {
     if (waves < 1 || waves > 16) return false;
 #define X(a, b, c) \

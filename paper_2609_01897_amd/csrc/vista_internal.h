@@ -172,6 +172,10 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t st
 hipError_t launch_debug_rotate(const DevTarget* t, float2* out, int64_t nrow, int32_t nchan, int32_t npol,
                                int phase_fp32, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
+// *flag |= 1 when a and b differ anywhere in [0, n) (the caller zeroes *flag).
+hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint32_t* flag, hipStream_t stream);
+// Launch shapes the kernels are built for, in order (atomic: the packed kernel's list).
+int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 
 }  // namespace vista

@@ -188,6 +188,15 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     if (i < n) p[i] = v;
 }
 
+// flag <- 1 if a[i] != b[i] for some i (flag zeroed by the caller).
+__global__ void k_diff_u32(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, int64_t n,
+                           uint32_t* __restrict__ flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool d = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d |= a[i] != b[i];
+    if (__any(d) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flag, 1u);
+}
+
 // Plain 16-byte-vector copy: reads and writes every byte once (byte-counter calibration).
 __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -697,6 +706,13 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t st
     return hipGetLastError();
 }
 
+hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint32_t* flag, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 16);
+    hipLaunchKernelGGL(k_diff_u32, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, n, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, v, n);
@@ -736,6 +752,21 @@ static int occ_one(int waves) {
                                                      0) != hipSuccess)
         return 0;
     return nb;
+}
+
+int accum_packed_shape_list(int* tu, int* tv, int* jc, int cap);
+
+int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap) {
+    if (mode == kModeAtomic) return accum_packed_shape_list(tu, tv, jc, cap);
+    int n = 0;
+#define X(a, b, c)            \
+    if (n < cap) {            \
+        tu[n] = a; tv[n] = b; jc[n] = c; \
+    }                         \
+    ++n;
+    VISTA_SHAPES(X)
+#undef X
+    return n;
 }
 
 size_t accum_lds_bytes(int tu, int tv, int jc, int mode, int kahan) {

@@ -722,6 +722,94 @@ static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t fla
     }
 }
 
+// ------------------------------------------------------------------------ autotuning
+
+// Candidate launch shapes of a mode: every (tile, block) shape the kernel is built for,
+// with 16 wavefronts per workgroup, and with 8 where two workgroups share a compute
+// unit's LDS.  The first candidate is the mode's default.
+static std::vector<Tuning> tuning_candidates(uint32_t flags) {
+    const int mode = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
+    const int kahan = (flags & VISTA_F_KAHAN) ? 1 : 0;
+    int tu[64], tv[64], jc[64];
+    const int n = std::min(accum_shape_list(mode, tu, tv, jc, 64), 64);
+    std::vector<Tuning> out{default_tuning(flags)};
+    for (int i = 0; i < n; ++i)
+        for (int waves : {16, 8}) {
+            Tuning t;
+            t.tu = tu[i]; t.tv = tv[i]; t.jc = jc[i]; t.waves = waves;
+            if (!shape_ok(t, flags)) continue;
+            if (waves == 8 && accum_lds_bytes(t.tu, t.tv, t.jc, mode, kahan) > 80 * 1024) continue;
+            if (t.tu == out[0].tu && t.tv == out[0].tv && t.jc == out[0].jc && t.waves == out[0].waves) continue;
+            out.push_back(t);
+        }
+    return out;
+}
+
+// Time every candidate shape on the jobs (device-resident targets; each job's outputs are
+// scratch buffers with a count grid) and return the fastest whose count grids equal the
+// default shape's bit for bit.  reps runs per candidate, the median time counts.
+static Tuning autotune_jobs(std::vector<StackJob>& jobs, uint32_t flags, hipStream_t stream, int reps,
+                            double* best_ms) {
+    DevMem mem(stream);
+    std::vector<uint32_t*> ref(jobs.size());
+    std::vector<int64_t> ncell(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const vista_grid_desc* g = jobs[j].g;
+        ncell[j] = (int64_t)g->nu * g->nv * g->nchan;
+        ref[j] = mem.alloc_n<uint32_t>(ncell[j]);
+    }
+    uint32_t* flag = mem.alloc_n<uint32_t>(1);
+    std::vector<Tuning> cand = tuning_candidates(flags);
+    Tuning best = cand[0];
+    double best_t = 1e300;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        std::vector<double> ts;
+        for (int r = 0; r < std::max(1, reps); ++r) {
+            vista_timings tim{};
+            run_jobs(jobs, cand[c], flags, stream, &tim);
+            ts.push_back(tim.total_ms);
+        }
+        std::sort(ts.begin(), ts.end());
+        const double t = ts[ts.size() / 2];
+        bool same = true;
+        if (c == 0) {
+            for (size_t j = 0; j < jobs.size(); ++j)
+                VISTA_HIP(hipMemcpyAsync(ref[j], jobs[j].out.count, ncell[j] * 4, hipMemcpyDeviceToDevice, stream));
+        } else {
+            check_launch(launch_fill_u32(flag, 0u, 1, stream), "fill");
+            for (size_t j = 0; j < jobs.size(); ++j)
+                check_launch(launch_diff_u32(ref[j], (const uint32_t*)jobs[j].out.count, ncell[j], flag, stream),
+                             "compare");
+            uint32_t h = 0;
+            VISTA_HIP(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, stream));
+            VISTA_HIP(hipStreamSynchronize(stream));
+            same = h == 0;
+        }
+        if (same && t < best_t) {
+            best_t = t;
+            best = cand[c];
+        }
+    }
+    VISTA_HIP(hipStreamSynchronize(stream));
+    if (best_ms) *best_ms = best_t;
+    return best;
+}
+
+// Scratch outputs (sum_wvis, sum_w, count) of one job, for autotuning.
+static void scratch_outputs(StackJob& J, DevMem& mem) {
+    const size_t nc = (size_t)J.g->nu * J.g->nv * J.g->nchan;
+    J.out = vista_output{};
+    J.out.sum_wvis = mem.alloc(nc * 8);
+    J.out.sum_w = mem.alloc(nc * 4);
+    J.out.count = mem.alloc(nc * 4);
+    J.out.mem = VISTA_MEM_DEVICE;
+}
+
+static void to_public(const Tuning& t, vista_tuning* o) {
+    if (!o) return;
+    o->tile_u = t.tu; o->tile_v = t.tv; o->jblock = t.jc; o->waves = t.waves; o->wg_per_cu = t.wg_per_cu;
+}
+
 // Resolve the user's outputs to device pointers; host outputs get device temporaries
 // that are copied back afterwards.
 struct OutputPlan {
@@ -1357,7 +1445,49 @@ int vista_batch_destroy(vista_batch* b) {
 
 int vista_stack_autotune(vista_stack* s, vista_tuning* best) {
     if (!s) return fail(VISTA_E_ARG, "stack is NULL");
-    return fail(VISTA_E_STATE, "autotuning is not available in this build");
+    if (s->state != 0) return fail(VISTA_E_STATE, "stack is not open");
+    for (auto& h : s->targets)
+        if (h->t.mem != VISTA_MEM_DEVICE && h->t.nrow > 0)
+            return fail(VISTA_E_ARG, "autotuning needs VISTA_MEM_DEVICE targets");
+    return guarded(nullptr, [&]() -> int {
+        DevMem mem(s->stream);
+        std::vector<StackJob> jobs(1);
+        jobs[0].g = &s->g;
+        for (auto& h : s->targets) jobs[0].targets.push_back(h.get());
+        scratch_outputs(jobs[0], mem);
+        const Tuning t = autotune_jobs(jobs, s->g.flags, s->stream, 2, nullptr);
+        mem.release();
+        VISTA_HIP(hipStreamSynchronize(s->stream));
+        s->tune = t;
+        s->tune_set = true;
+        to_public(t, best);
+        return VISTA_OK;
+    });
+}
+
+int vista_batch_autotune(vista_batch* b, vista_tuning* best) {
+    if (!b) return fail(VISTA_E_ARG, "batch is NULL");
+    if (b->state != 0) return fail(VISTA_E_STATE, "batch already ran");
+    for (auto& ts : b->targets)
+        for (auto& h : ts)
+            if (h->t.mem != VISTA_MEM_DEVICE && h->t.nrow > 0)
+                return fail(VISTA_E_ARG, "autotuning needs VISTA_MEM_DEVICE targets");
+    return guarded(nullptr, [&]() -> int {
+        DevMem mem(b->stream);
+        std::vector<StackJob> jobs(b->g.size());
+        for (size_t s = 0; s < jobs.size(); ++s) {
+            jobs[s].g = &b->g[s];
+            for (auto& h : b->targets[s]) jobs[s].targets.push_back(h.get());
+            scratch_outputs(jobs[s], mem);
+        }
+        const Tuning t = autotune_jobs(jobs, b->g[0].flags, b->stream, 2, nullptr);
+        mem.release();
+        VISTA_HIP(hipStreamSynchronize(b->stream));
+        b->tune = t;
+        b->tune_set = true;
+        to_public(t, best);
+        return VISTA_OK;
+    });
 }
 
 }  // extern "C"

@@ -76,6 +76,7 @@ SYMBOLS = {
     "vista_stack_timings": ([C.c_void_p, C.POINTER(Timings)], C.c_int),
     "vista_stack_destroy": ([C.c_void_p], C.c_int),
     "vista_stack_autotune": ([C.c_void_p, C.POINTER(Tuning)], C.c_int),
+    "vista_batch_autotune": ([C.c_void_p, C.POINTER(Tuning)], C.c_int),
     "vista_batch_create": ([C.c_int32, C.POINTER(GridDesc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "vista_batch_add_target": ([C.c_void_p, C.c_int32, C.POINTER(TargetDesc)], C.c_int),
     "vista_batch_set_tuning": ([C.c_void_p, C.POINTER(Tuning)], C.c_int),
@@ -195,6 +196,12 @@ class Stack:
         _check(lib().vista_stack_finalize(self.h, C.byref(o), C.byref(st)))
         return st.as_dict()
 
+    def autotune(self) -> dict:
+        """Time the built launch shapes on this stack's targets and keep the fastest."""
+        tu = Tuning()
+        _check(lib().vista_stack_autotune(self.h, C.byref(tu)))
+        return dict(tile_u=tu.tile_u, tile_v=tu.tile_v, jblock=tu.jblock, waves=tu.waves)
+
     def timings(self) -> dict:
         t = Timings()
         _check(lib().vista_stack_timings(self.h, C.byref(t)))
@@ -278,6 +285,12 @@ class Batch:
         o = C.byref(_output(out)) if out is not None else None
         _check(lib().vista_batch_finalize(self.h, int(stack_index), o, C.byref(st)))
         return st.as_dict()
+
+    def autotune(self) -> dict:
+        """Time the built launch shapes on this batch's targets and keep the fastest."""
+        tu = Tuning()
+        _check(lib().vista_batch_autotune(self.h, C.byref(tu)))
+        return dict(tile_u=tu.tile_u, tile_v=tu.tile_v, jblock=tu.jblock, waves=tu.waves)
 
     def timings(self) -> dict:
         t = Timings()

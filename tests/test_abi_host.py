@@ -155,3 +155,16 @@ def test_failure_paths_forced_from_host(monkeypatch):
         for k in env:
             monkeypatch.delenv(k)
 
+
+
+def test_autotune_needs_device_targets():
+    """Host-memory targets cannot be timed in place: the autotuner refuses them before any
+    device work."""
+    cfg = synth.config("tiny")
+    g = synth.make_grid(cfg)
+    s = vista.Stack(g)
+    s.add(synth.make_target(cfg, 0))
+    with pytest.raises(vista.VistaError) as e:
+        s.autotune()
+    assert e.value.code == vista.VISTA_E_ARG
+    s.close()

@@ -140,3 +140,35 @@ def test_registered_outputs_written_in_place(budget):
     res, _ = _batch(grids, ts, budget=budget, register=True)
     for s, g in enumerate(grids):
         compare(oracle.stack(g, hs[s]), res[s][0], st=res[s][1])
+
+
+def test_stack_autotune_keeps_results():
+    """The autotuner picks one of the built shapes; the tuned stack still matches."""
+    cfg = synth.config("small")
+    hs = synth.make_targets(cfg)
+    g = synth.make_grid(cfg)
+    s = vista.Stack(g)
+    for t in hs:
+        s.add(t.to("cuda"))
+    best = s.autotune()
+    assert best["tile_u"] > 0 and best["waves"] in (8, 16), best
+    out = vista.alloc_outputs(g)
+    st = s.finalize(out)
+    s.close()
+    compare(oracle.stack(g, hs), {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+
+
+def test_batch_autotune_keeps_results():
+    grids, hs = _stacks()
+    b = vista.Batch(grids)
+    for s, ts in enumerate(hs):
+        for t in ts:
+            b.add(s, t.to("cuda"))
+    best = b.autotune()
+    assert best["jblock"] > 0
+    b.run()
+    for s, g in enumerate(grids):
+        out = vista.alloc_outputs(g)
+        st = b.finalize(s, out)
+        compare(oracle.stack(g, hs[s]), {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+    b.close()
