@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "stacked vis·chan·pol/s + HBM GB/s vs peak; batched/compensated vs plain speedup"
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, AMD public specification
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "accum_c2_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2609_01897_amd", "csrc", "vista_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_01897_amd", "csrc", "vista_accum.hip")
 
 
 def log(msg):
