@@ -494,7 +494,10 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     if (!l0) break;
                 }
                 if (s >= sw1) break;
-                load_window(wb + cur);         // the record holding s and the 63 after it
+                // the record holding s and the 63 after it.  The cursor is the window's last
+                // record starting at or before s; when s is the window's end, that record ends
+                // at s and the one holding s is the first past the window.
+                load_window(s >= wend ? wb + nwin : wb + cur);
                 cur = 0;
             }
         }

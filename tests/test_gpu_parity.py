@@ -152,6 +152,46 @@ def test_empty_and_single_channel_targets():
     compare(o, out, st=st)
 
 
+def _one_tile_one_channel(cfg, g, i, k=None):
+    """Target i of cfg reduced to its channel k (None: one channel spanning the band), every
+    row moved into the 8 x 8 cells at the grid centre (u, v >= 0, under four cells)."""
+    import dataclasses
+    if k is None:
+        h = synth.make_target(cfg, i, nchan=1, with_width=True, n_int=96)
+    else:
+        h = synth.make_target(cfg, i, n_int=96)
+        width = np.full(1, abs(h.chan_freq[1] - h.chan_freq[0]))
+        sl = lambda x: None if x is None else x[:, k:k + 1].contiguous()
+        h = dataclasses.replace(h, vis=sl(h.vis), flag=sl(h.flag), chan_freq=h.chan_freq[k:k + 1].copy(),
+                                chan_width=width)
+    a = float(np.max(h.chan_freq)) / 299792458.0
+    uv = h.uvw[:, :2].abs()
+    h.uvw[:, :2] = uv * (3.5 * g["du"] / (float(uv.max()) * a))
+    return h
+
+
+@pytest.mark.parametrize("waves", [1, 4, 16])
+@pytest.mark.parametrize("wide", [False, True])
+def test_long_runs_of_one_channel_records(wide, waves):
+    """Units whose sample streams are thousands of one-channel records in a row (one-channel
+    targets, every row in one uv tile): windows of 64 records then end exactly where a
+    chunk starts, and the walk must resume at the record past the window."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    # narrow: a channel whose overlap set is rest channel 64 alone (the first of block 1);
+    # wide: one channel spanning the band (dozens of rest channels, two blocks)
+    hs = [_one_tile_one_channel(cfg, g, i, None if wide else k) for i, k in ((0, 110), (1, 117), (2, 36))]
+    o = oracle.stack(g, hs)
+    assert o["stats"]["n_outside_uv"] == 0 and o["stats"]["n_outside_band"] == 0
+    cells = np.argwhere(o["N"] > 0)
+    assert cells[:, 1].min() >= 48 and cells[:, 1].max() < 56 and cells[:, 2].min() >= 48 and cells[:, 2].max() < 56
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs], tuning=dict(tile_u=8, tile_v=8, jblock=64, waves=waves))
+    compare(o, out, st=st)
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=vista.F_KAHAN,
+                        tuning=dict(tile_u=8, tile_v=8, jblock=64, waves=waves))
+    compare(o, out, st=st)
+
+
 def test_no_targets_gives_zero_grid():
     g = synth.make_grid("small")
     out, st = gpu_stack(g, [])
