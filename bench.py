@@ -8,8 +8,11 @@ Default workload: 50 targets x 43 antennas (903 baselines) x 120 integrations x 
 240 channels x 2 polarisations, z ~ U(1.5, 3.5), onto a 512 x 512 x 960 grid.
 
 Prints one JSON line: throughput in stacked vis*chan*pol samples/s, the accumulation
-kernel against the HBM roofline (algorithmic bytes / its hipEvent-timed duration), and
-the FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+kernel against the HBM roofline (algorithmic bytes / its hipEvent-timed duration), the
+device's measured copy bandwidth, the FP64 CPU oracle timed on a bounded sample of the
+same workload on the host cores, and two more legs: many small stacks stacked one per
+launch against one batched graph launch (plain and compensated), and a stack streamed
+from pinned host memory in waves (its end-to-end rate includes the host-to-device copies).
 """
 from __future__ import annotations
 
@@ -50,13 +53,14 @@ def algorithmic_bytes(targets, grid, kahan=False):
     return nb, ns
 
 
-def counter_traffic():
+def counter_traffic(config_name, shape):
     """Counter-measured HBM bytes of one accumulation launch, if the committed summary was
-    taken on the current kernel source."""
+    taken on the current kernel source, on this workload and in this launch shape."""
     try:
         d = json.load(open(PROFILE_COUNTERS))
         h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if d.get("kernel_sha256") == h:
+        want = {k: int(shape[k]) for k in ("tile_u", "tile_v", "jblock", "waves")} if shape else None
+        if d.get("kernel_sha256") == h and d.get("config") == config_name and d.get("launch_shape") == want:
             return d.get("hbm_bytes_per_launch")
     except Exception:
         pass
@@ -95,6 +99,102 @@ def copy_probe(nbytes, steps):
     ms = e0.elapsed_time(e1) / steps
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": steps + 1,
                       "ms_per_launch": ms, "GB/s": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
+
+
+def hbm_copy_rate(nbytes=4 << 30, reps=5):
+    """Measured copy bandwidth of the device (the library's plain 16-byte-vector copy kernel,
+    read + written bytes over hipEvent time), reported beside the specification peak."""
+    import torch
+    from paper_2609_01897_amd import vista
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    vista.debug_copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        vista.debug_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+STREAM_TARGETS = 8
+STREAM_WAVE_TARGETS = 3
+
+
+def streamed_leg():
+    """The streamed recipe, reduced to a bounded sample: one stack of 8 targets of the
+    full-scale shape (903 baselines x 60 integrations x 3840 channels x 2 pols; grid
+    1024 x 1024 x 1920 with Kahan compensation) whose visibilities, flags, uvw and weights
+    sit in pinned host memory.  The batch copies them to the device in waves of 3 targets on
+    its copy stream, double-buffered against compute, and carries the compensated grid state
+    across the waves.  The end-to-end rate includes every host-to-device byte."""
+    import dataclasses
+    import torch
+    import synth
+    from paper_2609_01897_amd import vista
+    cfg = synth.config("c5")
+    grid = synth.make_grid(cfg)
+    t0 = time.perf_counter()
+    pin = lambda x: None if x is None else torch.empty(x.shape, dtype=x.dtype, pin_memory=True).copy_(x)
+    hs = []
+    for i in range(STREAM_TARGETS):
+        d = synth.make_target(cfg, i, device="cuda")
+        hs.append(dataclasses.replace(d, uvw=pin(d.uvw), vis=pin(d.vis), weight=pin(d.weight), flag=pin(d.flag)))
+        del d
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    nsamp = sum(int(t.vis.numel()) for t in hs)
+    staged = [sum(((int(x.numel()) * x.element_size() + 255) // 256) * 256 for x in (t.uvw, t.vis, t.weight, t.flag))
+              for t in hs]
+    in_bytes = sum(int(x.numel()) * x.element_size() for t in hs for x in (t.uvw, t.vis, t.weight, t.flag))
+    log("streamed recipe: %d targets, %.3g samples, %.1f GB in pinned host memory, prepared in %.1f s"
+        % (len(hs), nsamp, in_bytes / 1e9, time.perf_counter() - t0))
+    out = vista.alloc_outputs(grid)
+
+    def run():
+        b = vista.Batch([dict(grid, flags=vista.F_KAHAN)])
+        b.set_stream_budget(STREAM_WAVE_TARGETS * max(staged))
+        for t in hs:
+            b.add(0, t)
+        b.set_output(0, out)
+        b.run()
+        st = b.finalize(0)
+        tim = b.timings()
+        b.close()
+        return st, tim
+
+    run()                                       # warm-up (pools, code objects)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, tim = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    assert st["n_samples"] == nsamp, (st, nsamp)
+    compute_ms = tim["bin_ms"] + tim["accum_ms"]
+    log("streamed recipe: %.1f ms end to end over %d waves (host-to-device copies %.1f ms, device compute %.1f ms)"
+        % (ms, tim["n_waves"], tim["h2d_ms"], compute_ms))
+    del out, hs
+    torch.cuda.empty_cache()
+    return {
+        "workload": "streamed recipe reduced: 1 stack of %d targets x 903 baselines x 60 integrations x 3840 chan x "
+                    "2 pol from pinned host memory, waves of %d targets, grid 1024x1024x1920, Kahan"
+                    % (STREAM_TARGETS, STREAM_WAVE_TARGETS),
+        "samples": nsamp,
+        "input_bytes": in_bytes,
+        "waves": tim["n_waves"],
+        "end_to_end_ms": ms,
+        "samples_per_s_end_to_end": nsamp / (ms / 1e3),
+        "input_GBps_end_to_end": in_bytes / (ms / 1e3) / 1e9,
+        "h2d_copy_ms": tim["h2d_ms"],
+        "h2d_GBps": in_bytes / (tim["h2d_ms"] / 1e3) / 1e9 if tim["h2d_ms"] > 0 else None,
+        "device_compute_ms": compute_ms,
+        "samples_per_s_device": nsamp / (compute_ms / 1e3),
+    }
 
 
 BATCH_STACKS = 64
@@ -181,6 +281,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=8, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -201,6 +302,8 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe << 20, args.steps)
         return
+    copy_gbps = hbm_copy_rate()
+    log("measured copy bandwidth %.0f GB/s (specification peak %.0f GB/s)" % (copy_gbps, PEAK_HBM_GBS))
     cfg = synth.config(args.config)
     ntg = args.targets or cfg.n_targets
     grid = synth.make_grid(cfg)
@@ -263,7 +366,7 @@ def main():
     log("step %.2f ms, accumulate %.2f ms, binning %.2f ms; %.3e samples/s; %.0f GB/s algorithmic" % (
         ms, acc_ms, sum(binms) / len(binms), value, achieved))
     assert st["n_samples"] == nsamp, (st, nsamp)
-    traffic = counter_traffic()
+    traffic = counter_traffic(cfg.name, tuning)
 
     res = {
         "metric": METRIC,
@@ -300,14 +403,17 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
         },
+        "hbm_copy_GBps": copy_gbps,
     }
     if not args.no_cpu:
         log("timing the FP64 oracle on %d targets" % args.cpu_targets)
         res["cpu_baseline"] = cpu_baseline(targets, grid, args.cpu_targets)
+    del targets, out                          # the other legs bring their own inputs
+    torch.cuda.empty_cache()
     if not args.no_batched:
-        del targets, out
-        torch.cuda.empty_cache()
         res["batched"] = batched_leg(reps=2)
+    if not args.no_streamed:
+        res["streamed"] = streamed_leg()
     print(json.dumps(res), flush=True)
 
 

@@ -6,8 +6,9 @@
 // start in it.  A workgroup owns one unit at a time: its cells live in LDS (FP64 sums and a
 // u32 count per cell), so every cell of the grid is written exactly once, from one place.
 // The unit's stream is split into equal sample ranges, one per wavefront, and a wavefront
-// walks its range in chunks of 64 consecutive samples, one per lane, whatever records they
-// come from: no lane idles at record ends.  Each lane finds its record in a window of 64
+// walks its range in chunks of 128 consecutive samples, two adjacent ones per lane (records
+// are padded to whole pairs), whatever records they come from: no lane idles at record
+// ends.  Each lane finds its record in a window of 64
 // records held one per lane (the starts falling inside the chunk are few and are tested
 // one by one), takes the record's context from that lane with ds_bpermute, and loads its
 // own channel-table entry, visibilities and flags.  The loads of the next chunk are in
@@ -573,7 +574,10 @@ hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, cons
     X(4, 4, 128)               \
     X(8, 4, 64)                \
     X(8, 2, 128)               \
-    X(4, 2, 256)
+    X(4, 2, 256)               \
+    X(16, 2, 160)              \
+    X(8, 2, 320)               \
+    X(8, 4, 160)
 
 int accum_packed_shape_list(int* tu, int* tv, int* jc, int cap) {
     int n = 0;

@@ -198,9 +198,24 @@ __global__ void k_diff_u32(const uint32_t* __restrict__ a, const uint32_t* __res
 }
 
 // Plain 16-byte-vector copy: reads and writes every byte once (byte-counter calibration).
-__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+// Plain copy of n 16-byte vectors: four independent loads in flight per thread before their
+// stores, streaming (nontemporal) hints.  It measures the device's copy bandwidth and
+// calibrates the byte counters.
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+__global__ void k_copy16(const v4u32* __restrict__ src, v4u32* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const v4u32 a = __builtin_nontemporal_load(src + i);
+        const v4u32 b = __builtin_nontemporal_load(src + i + stride);
+        const v4u32 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const v4u32 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------------ accumulation
@@ -701,8 +716,8 @@ hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_
 
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t stream) {
     if (n16 <= 0) return hipSuccess;
-    int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
-    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint4*)src, (uint4*)dst, n16);
+    int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 256);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, stream, (const v4u32*)src, (v4u32*)dst, n16);
     return hipGetLastError();
 }
 

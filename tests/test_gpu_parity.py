@@ -200,7 +200,8 @@ def test_no_targets_gives_zero_grid():
 
 
 PACKED_SHAPES = [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128), (4, 4, 256), (8, 2, 256),
-                 (4, 2, 512), (4, 4, 128), (8, 4, 64), (8, 2, 128), (4, 2, 256)]
+                 (4, 2, 512), (4, 4, 128), (8, 4, 64), (8, 2, 128), (4, 2, 256), (16, 2, 160), (8, 2, 320),
+                 (8, 4, 160)]
 ORDERED_SHAPES = PACKED_SHAPES[:8]
 
 
@@ -282,3 +283,14 @@ def test_batch_equals_plain():
         o = oracle.stack(g, hs_all[s])
         compare(o, {k: v.cpu().numpy() for k, v in out.items()}, st=st)
     b.close()
+
+
+@pytest.mark.parametrize("n16", [1, 1000, 256 * 256 * 256 * 4 + 5])
+def test_copy_kernel_copies_every_vector(n16):
+    """The plain copy kernel (bandwidth measurement, counter calibration): every 16-byte
+    vector copied, including the unrolled path at the largest grid and a ragged tail."""
+    src = torch.randint(0, 256, (n16 * 16,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    vista.debug_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
