@@ -53,6 +53,8 @@ def lib():
         _lib.ora_plan_spectral_grid.argtypes = [i32, p, p, p, p, C.c_double, i32, C.POINTER(C.c_double),
                                                 C.POINTER(C.c_double)]
         _lib.ora_check.argtypes = [C.POINTER(_Grid), i32, C.POINTER(_Target)]
+        _lib.ora_rebin_window.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, C.POINTER(C.c_double)]
+        _lib.ora_rebin_rows.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, p, p, p, p]
     return _lib
 
 
@@ -188,3 +190,34 @@ def plan_spectral_grid(chan_freqs, chan_widths, zs, central_freq: float, nchan_o
     if rc:
         raise ValueError("oracle rejected the inputs")
     return lo.value, df.value
+
+
+def rebin_window(target, central_freq: float, dfreq: float, nout: int) -> float:
+    """Lower edge of the target's own output window of nout channels of width dfreq:
+    centred on central_freq, moved to the nearest edge of its rest-frame band when it does
+    not fit (``ora_rebin_window``)."""
+    h = _host(target)
+    t = _target(h)
+    lo = C.c_double(0.0)
+    if lib().ora_rebin_window(C.byref(t), float(central_freq), float(dfreq), int(nout), C.byref(lo)):
+        raise ValueError("oracle rejected the inputs")
+    return lo.value
+
+
+def rebin_rows(target, freq_lo: float, dfreq: float, nout: int) -> dict:
+    """The target's rows rebinned onto [freq_lo + j dfreq, freq_lo + (j+1) dfreq), j < nout
+    (``ora_rebin_rows``): vis complex128 [nrow, nout, npol] (Eq. 3 per row, flagged inputs
+    left out), flag uint8 (1 where nothing unflagged overlaps), wsum float64 (the Eq. 3
+    normaliser), uvw float64 [nrow, 3] (divided by 1 + z)."""
+    h = _host(target)
+    t = _target(h)
+    nrow, npol = int(h["uvw"].shape[0]), int(h["weight"].shape[-1])
+    out = np.zeros((nrow, int(nout), npol, 2), np.float64)
+    flag = np.zeros((nrow, int(nout), npol), np.uint8)
+    wsum = np.zeros((nrow, int(nout), npol), np.float64)
+    uvw = np.zeros((nrow, 3), np.float64)
+    rc = lib().ora_rebin_rows(C.byref(t), float(freq_lo), float(dfreq), int(nout), out.ctypes.data,
+                              flag.ctypes.data, wsum.ctypes.data, uvw.ctypes.data)
+    if rc:
+        raise ValueError("oracle rejected the inputs (code %d)" % rc)
+    return dict(vis=out.view(np.complex128)[..., 0], flag=flag, wsum=wsum, uvw=uvw)

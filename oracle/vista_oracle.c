@@ -24,6 +24,11 @@
  *   The paper casts visibilities to double before the phase multiply (Sec. 3.2, last
  *   paragraph); so does this file, and everything else is double too.
  *
+ * It also computes the paper's own per-row product (ora_rebin_window, ora_rebin_rows):
+ * each target's rows rebinned onto the target's own output window by Eq. 3 with the
+ * Eq. 4 weights, normalised per row and output channel, after the same Eq. 2 shift, and
+ * its uvw divided by 1 + z (Eq. 1 without the rotation R).
+ *
  * Build with -ffp-contract=off and without fast-math: the cell and channel indices
  * must follow exactly the operation sequence written here.
  *
@@ -414,5 +419,93 @@ int ora_plan_spectral_grid(int32_t n, const double* const* chan_freq, const doub
     if (!(wmax > 0.0)) return -1;
     *dfreq = wmax;
     *freq_lo = central_freq - 0.5 * (double)nchan_out * wmax;
+    return 0;
+}
+
+/* ------------------------------------------------------------------- rebinned rows */
+
+/* The lower edge of one target's own output window (Sec. 3.1): nout channels of the common
+ * rest width dfreq, centred on central_freq.  When that window does not fit inside the
+ * target's rest-frame band [lo, hi] (the outermost rest edges of its channels), it moves to
+ * the nearest band edge: its upper edge down to hi if it overhangs there, and then, if it
+ * still starts below lo (which a window wider than the band does), its lower edge up to
+ * lo. */
+int ora_rebin_window(const ora_target* t, double central_freq, double dfreq, int32_t nout, double* freq_lo) {
+    if (!t || t->nchan < 1 || nout < 1 || !(dfreq > 0.0) || !isfinite(dfreq) || !isfinite(central_freq))
+        return -1;
+    if (t->nchan == 1 && !t->chan_width) return -1;
+    double opz = 1.0 + t->z;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t k = 0; k < t->nchan; ++k) {
+        double W = ora_width(t->chan_freq, t->chan_width, t->nchan, k);
+        lo = fmin(lo, (t->chan_freq[k] - 0.5 * W) * opz);
+        hi = fmax(hi, (t->chan_freq[k] + 0.5 * W) * opz);
+    }
+    double wid = (double)nout * dfreq;
+    double s = central_freq - 0.5 * wid;
+    if (s + wid > hi) s = hi - wid;
+    if (s < lo) s = lo;
+    *freq_lo = s;
+    return 0;
+}
+
+/* One target's rows rebinned onto its own window [freq_lo + j dfreq, freq_lo + (j+1) dfreq),
+ * j < nout, row by row (the product of the paper's per-row kernel, Sec. 3.2):
+ *   out[r][j][p] = sum_k f_kj V'(r,k,p) / sum_k f_kj,
+ * the sums over the input channels k whose Eq. 4 overlap f_kj with channel j is above the
+ * sliver threshold and whose sample (r, k, p) is not flagged; V' is the Eq. 2-rotated
+ * visibility, in double.  Where no such channel exists the output is 0 and flagged.
+ * wsum[r][j][p] = sum_k f_kj (0 where flagged).  uvw_out[r] = uvw[r] / (1 + z), the
+ * rest-frame baseline of Eq. 1 (the rotation R of Eq. 1 is not applied).  Visibility
+ * weights do not enter Eq. 3.  The data arrays must hold all channels. */
+int ora_rebin_rows(const ora_target* t, double freq_lo, double dfreq, int32_t nout, double* out,
+                   uint8_t* oflag, double* wsum, double* uvw_out) {
+    ora_grid g;
+    g.nu = 1; g.nv = 1; g.nchan = nout; g.du = 1.0; g.dv = 1.0;
+    g.freq_lo = freq_lo; g.dfreq = dfreq; g.flags = 0;
+    if (ora_check(&g, 1, t)) return -1;
+    if (t->kbeg != 0 || t->kend != t->nchan) return -1;
+    ora_table tb;
+    int rc = ora_build_table(&g, t, &tb);
+    if (rc) { ora_free_table(&tb); return rc; }
+    const int32_t np = t->npol, nk = t->nchan;
+    const double nm1 = ora_n_minus_1(t->l, t->m), opz = 1.0 + t->z;
+    double* num = (double*)malloc(sizeof(double) * 2 * (size_t)nout * np);
+    double* den = (double*)malloc(sizeof(double) * (size_t)nout * np);
+    if (!num || !den) { free(num); free(den); ora_free_table(&tb); return -3; }
+    for (int64_t r = 0; r < t->nrow; ++r) {
+        memset(num, 0, sizeof(double) * 2 * (size_t)nout * np);
+        memset(den, 0, sizeof(double) * (size_t)nout * np);
+        for (int32_t k = 0; k < nk; ++k) {
+            double pc, ps;
+            ora_phasor(t->uvw + 3 * r, tb.a[k], t->l, t->m, nm1, &pc, &ps);
+            for (int32_t q = tb.start[k]; q < tb.start[k + 1]; ++q) {
+                const int32_t j = tb.j[q];
+                const double f = tb.f[q];
+                for (int32_t p = 0; p < np; ++p) {
+                    size_t e = ((size_t)r * nk + k) * np + p;
+                    if (t->flag && t->flag[e]) continue;
+                    double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
+                    num[2 * ((size_t)j * np + p)] += f * (vr * pc - vi * ps);
+                    num[2 * ((size_t)j * np + p) + 1] += f * (vr * ps + vi * pc);
+                    den[(size_t)j * np + p] += f;
+                }
+            }
+        }
+        for (int32_t j = 0; j < nout; ++j)
+            for (int32_t p = 0; p < np; ++p) {
+                size_t o = ((size_t)r * nout + j) * np + p;
+                double d = den[(size_t)j * np + p];
+                out[2 * o] = d > 0.0 ? num[2 * ((size_t)j * np + p)] / d : 0.0;
+                out[2 * o + 1] = d > 0.0 ? num[2 * ((size_t)j * np + p) + 1] / d : 0.0;
+                if (oflag) oflag[o] = d > 0.0 ? 0 : 1;
+                if (wsum) wsum[o] = d;
+            }
+        if (uvw_out)
+            for (int i = 0; i < 3; ++i) uvw_out[3 * r + i] = t->uvw[3 * r + i] / opz;
+    }
+    free(num);
+    free(den);
+    ora_free_table(&tb);
     return 0;
 }
