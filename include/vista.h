@@ -206,6 +206,52 @@ int vista_plan_spectral_grid(int32_t n_targets, const double* const* chan_freq,
                              const double* const* chan_width, const int32_t* nchan, const double* z,
                              double central_freq, int32_t nchan_out, double* freq_lo, double* dfreq);
 
+/* ---- Per-row rebinned product (the paper's per-row kernel output, Sec. 3.2) ----------
+ *
+ * Each row of each target is shifted to the target's position (Eq. 2; the same FP64 turns
+ * and FP32 sine/cosine as the stack) and rebinned onto the target's own output window by
+ * Eq. 3 with the Eq. 4 weights, normalised per row, output channel and polarisation:
+ *   out[r][j][p] = sum_k f_kj V'(r,k,p) / sum_k f_kj,
+ * over the input channels k whose overlap fraction with output channel j is above the
+ * sliver threshold (1e-9) and whose sample (r, k, p) is not flagged.  Visibility weights do
+ * not enter Eq. 3.  The window (Sec. 3.1) is nout channels of the common rest width dfreq
+ * (the paper's Delta nu_new, e.g. from vista_plan_spectral_grid) centred on central_freq;
+ * when it does not fit inside the target's rest-frame band (the outermost rest edges of
+ * its channels), its upper edge moves down to the band's top if it overhangs there, and
+ * then its lower edge up to the band's bottom if it still starts below it.  Rows keep their
+ * order; the baseline becomes uvw / (1 + z) (Eq. 1 without its rotation). */
+typedef struct {
+    int32_t nout;               /* output channels per target, 1..1048576 */
+    double dfreq;               /* rest-frame output channel width [Hz], finite > 0 */
+    double central_freq;        /* rest-frame window centre [Hz], finite */
+} vista_rebin_desc;
+
+typedef struct {                /* one target's outputs, device memory */
+    void* vis;                  /* complex64 [nrow][nout][npol], required; 16-byte aligned
+                                   (8 for npol == 1) */
+    uint8_t* flag;              /* [nrow][nout][npol]: 1 where no unflagged input overlaps
+                                   (vis is 0 there); NULL = not written; npol-byte aligned */
+    float* wsum;                /* [nrow][nout][npol]: the Eq. 3 normaliser sum_k f_kj of the
+                                   unflagged inputs (0 where flagged); NULL = not written;
+                                   4 npol-byte aligned */
+    double* uvw;                /* [nrow][3]: uvw / (1 + z) [m]; NULL = not written */
+} vista_rebin_output;
+
+/* Lower edge [Hz] of target t's output window, computed on the host in FP64 (the same
+ * arithmetic vista_rebin_rows uses).  Only chan_freq, chan_width, nchan and z are read.
+ * Errors: ARG. */
+int vista_rebin_window(const vista_rebin_desc* d, const vista_target* t, double* freq_lo);
+
+/* Rebin n_targets targets (t[i] -> o[i]) in one pass over their rows, on hip_stream; the
+ * call returns when the outputs are written.  Every target's data and outputs must be
+ * VISTA_MEM_DEVICE (the caller owns them; they are not retained).  freq_lo (n_targets
+ * doubles, may be NULL) receives each window's lower edge; tim (may be NULL) the device
+ * time of the rebinning kernels in accum_ms and of the whole call in total_ms.  With
+ * n_targets == 0 nothing is done.  Errors: ARG (descriptor, target or output invalid,
+ * memory not on the device), NOMEM, HIP. */
+int vista_rebin_rows(const vista_rebin_desc* d, int32_t n_targets, const vista_target* t,
+                     const vista_rebin_output* o, void* hip_stream, double* freq_lo, vista_timings* tim);
+
 /* Per (row, channel) indices the GPU computes for one target, for bit-exact checks:
  * iu, iv (the nearest cell before the bounds test, INT32_MIN when not representable),
  * j0 (first rest channel of the channel's overlap set, -1 if empty) and nj (its size).

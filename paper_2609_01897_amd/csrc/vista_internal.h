@@ -110,6 +110,32 @@ struct LaunchDesc {
     const uint8_t* zero_flags;        // a zero row for targets without flags
 };
 
+// One target of a rebinning launch (per-row product): its inputs, outputs and tables.
+//   a[k]      = nu_k / c;
+//   jstart    = [nout+1] CSR offsets, per output channel j, into ek/ef: the input channels
+//               k (ascending) whose Eq. 4 fraction f_kj with channel j is above the sliver
+//               threshold, and those fractions.
+struct RebinTarget {
+    const double* uvw;        // [nrow][3]
+    const float2* vis;        // [nrow][nchan][npol]
+    const uint8_t* flag;      // [nrow][nchan][npol] or nullptr
+    float2* out_vis;          // [nrow][nout][npol]
+    uint8_t* out_flag;        // [nrow][nout][npol] or nullptr
+    float* out_wsum;          // [nrow][nout][npol] or nullptr
+    double* out_uvw;          // [nrow][3] or nullptr
+    const double* a;
+    const int32_t* jstart;
+    const int32_t* ek;
+    const float* ef;
+    int64_t nrow;
+    int32_t nchan, npol, nout, pad;
+    double l, m, nm1, opz;    // direction cosines, n - 1, 1 + z
+};
+// A workgroup's share: rows [row0, row0 + nrows) of target `target`.
+struct RebinBlock {
+    int32_t target, row0, nrows, pad;
+};
+
 constexpr int kModeAtomic = 0;
 constexpr int kModeOrdered = 1;
 
@@ -177,5 +203,9 @@ hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint
 // Launch shapes the kernels are built for, in order (atomic: the packed kernel's list).
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
+// The per-row rebinning (vista_rebin.hip) over `nblocks` row blocks; every target of the
+// launch has `npol` polarisations (1, 2 or 4).
+hipError_t launch_rebin_rows(const RebinTarget* targets, const RebinBlock* blocks, int64_t nblocks, int npol,
+                             hipStream_t stream);
 
 }  // namespace vista

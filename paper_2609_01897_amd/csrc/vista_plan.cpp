@@ -6,6 +6,7 @@
 #include "vista_plan.h"
 
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -188,6 +189,47 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
     p.nphase = std::min(64, span + 1);
     if (p.nphase < 1) p.nphase = 1;
     return p;
+}
+
+double rebin_window(const vista_target* t, double central_freq, double dfreq, int32_t nout) {
+    const double opz = 1.0 + t->z;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t k = 0; k < t->nchan; ++k) {
+        const double W = channel_width(t->chan_freq, t->chan_width, t->nchan, k);
+        lo = fmin(lo, (t->chan_freq[k] - 0.5 * W) * opz);
+        hi = fmax(hi, (t->chan_freq[k] + 0.5 * W) * opz);
+    }
+    const double wid = (double)nout * dfreq;
+    double s = central_freq - 0.5 * wid;
+    if (s + wid > hi) s = hi - wid;
+    if (s < lo) s = lo;
+    return s;
+}
+
+RebinPlan plan_rebin(const vista_target* t, double freq_lo, double dfreq, int32_t nout) {
+    vista_grid_desc g;
+    memset(&g, 0, sizeof(g));
+    g.nu = 1; g.nv = 1; g.du = 1.0; g.dv = 1.0;
+    g.nchan = nout; g.freq_lo = freq_lo; g.dfreq = dfreq; g.flags = 0;
+    const ChannelPlan p = plan_target(&g, t);
+    RebinPlan r;
+    r.nm1 = p.nm1;
+    r.a.resize(t->nchan);
+    for (int32_t k = 0; k < t->nchan; ++k) r.a[k] = p.chan[k].a;
+    r.jstart.assign((size_t)nout + 1, 0);
+    for (int32_t k = 0; k < t->nchan; ++k)
+        for (int32_t q = 0; q < p.nj[k]; ++q) r.jstart[p.j0[k] + q + 1]++;
+    for (int32_t j = 0; j < nout; ++j) r.jstart[j + 1] += r.jstart[j];
+    r.ek.resize(r.jstart[nout]);
+    r.ef.resize(r.jstart[nout]);
+    std::vector<int32_t> fill(r.jstart.begin(), r.jstart.end() - 1);
+    for (int32_t k = 0; k < t->nchan; ++k)
+        for (int32_t q = 0; q < p.nj[k]; ++q) {
+            const int32_t j = p.j0[k] + q, e = fill[j]++;
+            r.ek[e] = k;
+            r.ef[e] = p.fval[p.foff[k] + q];
+        }
+    return r;
 }
 
 bool check_plan(const ChannelPlan& p, std::string* why) {

@@ -42,4 +42,21 @@ std::vector<int32_t> block_ranges(const ChannelPlan& p, int32_t nchan_grid, int3
 // Input channel width W_k (Eq. 4's Delta nu_k): given width, else centred difference.
 double channel_width(const double* f, const double* w, int32_t n, int32_t k);
 
+// Lower edge of target t's own output window (Sec. 3.1): nout channels of width dfreq
+// centred on central_freq, moved to the nearest edge of the target's rest-frame band when
+// it does not fit (upper edge first, then lower edge).
+double rebin_window(const vista_target* t, double central_freq, double dfreq, int32_t nout);
+
+// Per-output-channel lists of the Eq. 4 fractions of target t on its window: for output
+// channel j, entries [jstart[j], jstart[j+1]) of (ek, ef) are the input channels (in
+// ascending order) and their fractions.
+struct RebinPlan {
+    std::vector<double> a;         // [nchan] nu_k / c
+    std::vector<int32_t> jstart;   // [nout+1]
+    std::vector<int32_t> ek;
+    std::vector<float> ef;
+    double nm1 = 0.0;
+};
+RebinPlan plan_rebin(const vista_target* t, double freq_lo, double dfreq, int32_t nout);
+
 }  // namespace vista

@@ -1065,6 +1065,141 @@ int vista_debug_copy(void* dst, const void* src, size_t nbytes, void* hip_stream
     });
 }
 
+// ------------------------------------------------------------------ rebinned rows
+
+static bool check_rebin_desc(const vista_rebin_desc* d, std::string* why) {
+    if (!d) { *why = "rebin descriptor is NULL"; return false; }
+    if (d->nout < 1 || d->nout > (1 << 20)) { *why = "nout must be in 1..1048576"; return false; }
+    if (!(d->dfreq > 0 && std::isfinite(d->dfreq))) { *why = "dfreq must be finite and > 0"; return false; }
+    if (!std::isfinite(d->central_freq)) { *why = "central_freq must be finite"; return false; }
+    return true;
+}
+
+// The channel axis of a target (what the window and the tables read).
+static bool check_channels(const vista_target* t, std::string* why) {
+    if (!t) { *why = "target is NULL"; return false; }
+    vista_target c = *t;
+    c.nrow = 0;
+    return check_target(nullptr, &c, why);
+}
+
+int vista_rebin_window(const vista_rebin_desc* d, const vista_target* t, double* freq_lo) {
+    std::string why;
+    if (!check_rebin_desc(d, &why) || !check_channels(t, &why)) return fail(VISTA_E_ARG, why);
+    if (!freq_lo) return fail(VISTA_E_ARG, "freq_lo is NULL");
+    const double lo = rebin_window(t, d->central_freq, d->dfreq, d->nout);
+    if (!std::isfinite(lo)) return fail(VISTA_E_ARG, "the window's lower edge is not finite");
+    *freq_lo = lo;
+    return VISTA_OK;
+}
+
+int vista_rebin_rows(const vista_rebin_desc* d, int32_t n, const vista_target* t, const vista_rebin_output* o,
+                     void* hip_stream, double* freq_lo, vista_timings* tim) {
+    std::string why;
+    if (!check_rebin_desc(d, &why)) return fail(VISTA_E_ARG, why);
+    if (n < 0) return fail(VISTA_E_ARG, "n_targets must be >= 0");
+    if (n > 0 && (!t || !o)) return fail(VISTA_E_ARG, "targets or outputs are NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        const std::string at = "target " + std::to_string(i) + ": ";
+        if (!check_target(nullptr, &t[i], &why)) return fail(VISTA_E_ARG, at + why);
+        if (t[i].nrow == 0) continue;
+        if (t[i].mem != VISTA_MEM_DEVICE) return fail(VISTA_E_ARG, at + "vista_rebin_rows needs device data");
+        const vista_rebin_output& q = o[i];
+        const size_t np = (size_t)t[i].npol;
+        if (!q.vis) return fail(VISTA_E_ARG, at + "output vis is NULL");
+        if (((uintptr_t)q.vis % (np == 1 ? 8 : 16)) || ((uintptr_t)q.flag % np) || ((uintptr_t)q.wsum % (4 * np)) ||
+            ((uintptr_t)q.uvw % 8))
+            return fail(VISTA_E_ARG, at + "output buffers are not aligned (vis 16 (8 for npol 1), flag npol, "
+                                          "wsum 4 npol, uvw 8 bytes)");
+    }
+    if (n == 0) {
+        if (tim) memset(tim, 0, sizeof(*tim));
+        return VISTA_OK;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    return guarded(nullptr, [&]() -> int {
+        Events ev;
+        VISTA_HIP(hipEventRecord(ev.e[0], stream));
+        DevMem mem(stream);
+        // host tables: one arena, every table 256-byte aligned
+        std::vector<RebinPlan> plans(n);
+        std::vector<double> lo(n, 0.0);
+        std::vector<size_t> off(4 * (size_t)std::max(n, 1));
+        size_t bytes = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            lo[i] = rebin_window(&t[i], d->central_freq, d->dfreq, d->nout);
+            if (!std::isfinite(lo[i])) throw HipFail{hipErrorInvalidValue, "rebin window edge not finite"};
+            plans[i] = plan_rebin(&t[i], lo[i], d->dfreq, d->nout);
+            const RebinPlan& P = plans[i];
+            off[4 * i] = bytes; bytes += align256(P.a.size() * sizeof(double));
+            off[4 * i + 1] = bytes; bytes += align256(P.jstart.size() * sizeof(int32_t));
+            off[4 * i + 2] = bytes; bytes += align256(std::max<size_t>(1, P.ek.size()) * sizeof(int32_t));
+            off[4 * i + 3] = bytes; bytes += align256(std::max<size_t>(1, P.ef.size()) * sizeof(float));
+        }
+        std::vector<unsigned char> arena(std::max<size_t>(bytes, 256), 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const RebinPlan& P = plans[i];
+            memcpy(arena.data() + off[4 * i], P.a.data(), P.a.size() * sizeof(double));
+            memcpy(arena.data() + off[4 * i + 1], P.jstart.data(), P.jstart.size() * sizeof(int32_t));
+            if (!P.ek.empty()) memcpy(arena.data() + off[4 * i + 2], P.ek.data(), P.ek.size() * sizeof(int32_t));
+            if (!P.ef.empty()) memcpy(arena.data() + off[4 * i + 3], P.ef.data(), P.ef.size() * sizeof(float));
+        }
+        unsigned char* darena = mem.alloc_n<unsigned char>(arena.size());
+        std::vector<RebinTarget> dts(std::max(n, 1));
+        for (int32_t i = 0; i < n; ++i) {
+            RebinTarget& T = dts[i];
+            memset(&T, 0, sizeof(T));
+            T.uvw = t[i].uvw; T.vis = (const float2*)t[i].vis; T.flag = t[i].flag;
+            T.out_vis = (float2*)o[i].vis; T.out_flag = o[i].flag; T.out_wsum = o[i].wsum; T.out_uvw = o[i].uvw;
+            T.a = (const double*)(darena + off[4 * i]);
+            T.jstart = (const int32_t*)(darena + off[4 * i + 1]);
+            T.ek = (const int32_t*)(darena + off[4 * i + 2]);
+            T.ef = (const float*)(darena + off[4 * i + 3]);
+            T.nrow = t[i].nrow; T.nchan = t[i].nchan; T.npol = t[i].npol; T.nout = d->nout;
+            T.l = t[i].l; T.m = t[i].m; T.nm1 = plans[i].nm1; T.opz = 1.0 + t[i].z;
+        }
+        // row blocks, grouped by polarisation count: about 2048 outputs per workgroup
+        const int32_t rpb = std::max(1, std::min(64, 2048 / d->nout));
+        std::vector<RebinBlock> blocks;
+        int64_t cls[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // npol 1, 2, 4: [first, count)
+        const int pols[3] = {1, 2, 4};
+        for (int c = 0; c < 3; ++c) {
+            cls[c][0] = (int64_t)blocks.size();
+            for (int32_t i = 0; i < n; ++i) {
+                if (t[i].npol != pols[c]) continue;
+                for (int64_t r0 = 0; r0 < t[i].nrow; r0 += rpb)
+                    blocks.push_back(RebinBlock{i, (int32_t)r0, (int32_t)std::min<int64_t>(rpb, t[i].nrow - r0), 0});
+            }
+            cls[c][1] = (int64_t)blocks.size() - cls[c][0];
+        }
+        RebinTarget* dT = mem.alloc_n<RebinTarget>(dts.size());
+        RebinBlock* dB = mem.alloc_n<RebinBlock>(std::max<size_t>(1, blocks.size()));
+        VISTA_HIP(hipMemcpyAsync(darena, arena.data(), arena.size(), hipMemcpyHostToDevice, stream));
+        VISTA_HIP(hipMemcpyAsync(dT, dts.data(), dts.size() * sizeof(RebinTarget), hipMemcpyHostToDevice, stream));
+        if (!blocks.empty())
+            VISTA_HIP(hipMemcpyAsync(dB, blocks.data(), blocks.size() * sizeof(RebinBlock), hipMemcpyHostToDevice,
+                                     stream));
+        VISTA_HIP(hipEventRecord(ev.e[1], stream));
+        for (int c = 0; c < 3; ++c)
+            check_launch(launch_rebin_rows(dT, dB + cls[c][0], cls[c][1], pols[c], stream), "rebin rows");
+        VISTA_HIP(hipEventRecord(ev.e[2], stream));
+        VISTA_HIP(hipEventRecord(ev.e[3], stream));
+        VISTA_HIP(hipStreamSynchronize(stream));   // the host tables above are read until here
+        mem.release();
+        VISTA_HIP(hipStreamSynchronize(stream));
+        if (freq_lo)
+            for (int32_t i = 0; i < n; ++i) freq_lo[i] = lo[i];
+        if (tim) {
+            memset(tim, 0, sizeof(*tim));
+            tim->bin_ms = ev.ms(0, 1);
+            tim->accum_ms = ev.ms(1, 2);
+            tim->total_ms = ev.ms(0, 3);
+            tim->n_accum_launches = (cls[0][1] > 0) + (cls[1][1] > 0) + (cls[2][1] > 0);
+        }
+        return VISTA_OK;
+    });
+}
+
 // ---------------------------------------------------------------------------- batch
 
 int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_stream, vista_batch** out) {

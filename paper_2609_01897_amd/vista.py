@@ -54,6 +54,14 @@ class Stats(C.Structure):
         return {n: int(getattr(self, n)) for n in STAT_NAMES}
 
 
+class RebinDesc(C.Structure):
+    _fields_ = [("nout", C.c_int32), ("dfreq", C.c_double), ("central_freq", C.c_double)]
+
+
+class RebinOutput(C.Structure):
+    _fields_ = [("vis", C.c_void_p), ("flag", C.c_void_p), ("wsum", C.c_void_p), ("uvw", C.c_void_p)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("tile_u", C.c_int32), ("tile_v", C.c_int32), ("jblock", C.c_int32), ("waves", C.c_int32),
                 ("wg_per_cu", C.c_int32)]
@@ -92,6 +100,9 @@ SYMBOLS = {
     "vista_debug_rotate": ([C.POINTER(GridDesc), C.POINTER(TargetDesc), C.c_void_p, C.c_void_p], C.c_int),
     "vista_debug_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "vista_batch_set_output": ([C.c_void_p, C.c_int32, C.POINTER(Output)], C.c_int),
+    "vista_rebin_window": ([C.POINTER(RebinDesc), C.POINTER(TargetDesc), C.POINTER(C.c_double)], C.c_int),
+    "vista_rebin_rows": ([C.POINTER(RebinDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.POINTER(Timings)], C.c_int),
     "vista_last_error": ([], C.c_char_p),
     "vista_version": ([], C.c_char_p),
 }
@@ -369,3 +380,46 @@ def plan_spectral_grid(chan_freqs, chan_widths, zs, central_freq: float, nchan_o
 
 def version() -> str:
     return lib().vista_version().decode()
+
+
+def rebin_window(t, nout: int, dfreq: float, central_freq: float) -> float:
+    """Lower edge [Hz] of target t's own output window (``vista_rebin_window``)."""
+    keep = []
+    d = RebinDesc(int(nout), float(dfreq), float(central_freq))
+    td = target_desc(t, keep)
+    lo = C.c_double(0.0)
+    _check(lib().vista_rebin_window(C.byref(d), C.byref(td), C.byref(lo)))
+    return lo.value
+
+
+def rebin_rows(targets, nout: int, dfreq: float, central_freq: float, outs=None, want=("vis", "flag", "wsum", "uvw"),
+               stream=None):
+    """Per-row rebinned product of device-resident targets (``vista_rebin_rows``).
+
+    ``outs`` (one dict per target with vis/flag/wsum/uvw tensors, any of the last three may
+    be None) is allocated on the targets' device when not given, with the fields in
+    ``want``.  Returns (outs, freq_lo list, timings dict)."""
+    import torch
+    targets = list(targets)
+    if outs is None:
+        outs = []
+        for t in targets:
+            nrow, npol = int(t.vis.shape[0]), int(t.vis.shape[2])
+            dev = t.vis.device
+            o = dict(vis=torch.empty((nrow, int(nout), npol), dtype=torch.complex64, device=dev))
+            o["flag"] = torch.empty((nrow, int(nout), npol), dtype=torch.uint8, device=dev) if "flag" in want else None
+            o["wsum"] = torch.empty((nrow, int(nout), npol), dtype=torch.float32, device=dev) if "wsum" in want else None
+            o["uvw"] = torch.empty((nrow, 3), dtype=torch.float64, device=dev) if "uvw" in want else None
+            outs.append(o)
+    keep = []
+    n = len(targets)
+    tds = (TargetDesc * max(1, n))(*[target_desc(t, keep) for t in targets])
+    ods = (RebinOutput * max(1, n))(*[RebinOutput(_ptr(o.get("vis")), _ptr(o.get("flag")), _ptr(o.get("wsum")),
+                                                  _ptr(o.get("uvw"))) for o in outs])
+    lo = (C.c_double * max(1, n))()
+    tim = Timings()
+    d = RebinDesc(int(nout), float(dfreq), float(central_freq))
+    s = current_stream() if stream is None else stream
+    _check(lib().vista_rebin_rows(C.byref(d), n, C.cast(tds, C.c_void_p), C.cast(ods, C.c_void_p), s,
+                                  C.cast(lo, C.c_void_p), C.byref(tim)))
+    return outs, [lo[i] for i in range(n)], tim.as_dict()

@@ -168,3 +168,44 @@ def test_autotune_needs_device_targets():
         s.autotune()
     assert e.value.code == vista.VISTA_E_ARG
     s.close()
+
+
+@pytest.mark.parametrize("variant", ["plain", "descending", "jitter_width", "single_channel"])
+def test_rebin_window_matches_oracle_bit_for_bit(variant):
+    """The library's window edge (host FP64) equals the oracle's for windows that fit,
+    overhang either end of the rest band, or are wider than it."""
+    import oracle
+    cfg = synth.config("small")
+    kw = {"plain": {}, "descending": dict(descending=True), "jitter_width": dict(chan_jitter=0.4, with_width=True),
+          "single_channel": dict(nchan=1, with_width=True)}[variant]
+    g = synth.make_grid(cfg)
+    for i in range(3):
+        t = synth.make_target(cfg, i, **kw)
+        opz = 1.0 + t.z
+        for central, nout in ((cfg.line_rest, 40), (float(t.chan_freq.min()) * opz, 12),
+                              (float(t.chan_freq.max()) * opz, 12), (cfg.line_rest, 5000)):
+            lo = vista.rebin_window(t, nout, g["dfreq"], central)
+            assert lo == oracle.rebin_window(t, central, g["dfreq"], nout)
+
+
+def test_rebin_validation():
+    """Bad descriptors, host-memory data and missing outputs are refused before any device
+    work."""
+    cfg = synth.config("tiny")
+    g = synth.make_grid(cfg)
+    t = synth.make_target(cfg, 0)
+    for nout, dfreq, central in ((0, g["dfreq"], 1e11), (4, 0.0, 1e11), (4, -1.0, 1e11), (4, g["dfreq"], float("inf")),
+                                 ((1 << 20) + 1, g["dfreq"], 1e11)):
+        with pytest.raises(vista.VistaError) as e:
+            vista.rebin_window(t, nout, dfreq, central)
+        assert e.value.code == vista.VISTA_E_ARG
+    with pytest.raises(vista.VistaError) as e:                 # host data
+        vista.rebin_rows([t], 8, g["dfreq"], cfg.line_rest)
+    assert e.value.code == vista.VISTA_E_ARG and "device" in str(e.value)
+    d = vista.RebinDesc(8, g["dfreq"], cfg.line_rest)
+    rc = vista.lib().vista_rebin_rows(C.byref(d), -1, None, None, None, None, None)
+    assert rc == vista.VISTA_E_ARG
+    rc = vista.lib().vista_rebin_rows(C.byref(d), 1, None, None, None, None, None)
+    assert rc == vista.VISTA_E_ARG
+    rc = vista.lib().vista_rebin_rows(C.byref(d), 0, None, None, None, None, None)   # nothing to do
+    assert rc == vista.VISTA_OK
