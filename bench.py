@@ -197,6 +197,60 @@ def streamed_leg():
     }
 
 
+REBIN_NOUT = 480
+
+
+def rebinned_leg(targets, cfg, grid, reps=3):
+    """The paper's per-row product on the same resident targets: every row of every target
+    rebinned onto its own window of REBIN_NOUT channels of the common rest width around the
+    line (visibilities, flags, normalisers and rest-frame baselines written).  Algorithmic
+    bytes: the input channels the windows reach (8 B vis + 1 B flag per sample) and each
+    row's uvw, plus every output (8 + 1 + 4 B per output sample, 24 B per row)."""
+    import numpy as np
+    import torch
+    from paper_2609_01897_amd import vista
+    dfreq, central = float(grid["dfreq"]), float(cfg.line_rest)
+    outs, los, tim = vista.rebin_rows(targets, REBIN_NOUT, dfreq, central)      # warm-up, allocates
+    torch.cuda.synchronize()
+    nbytes = 0
+    nin = 0
+    nout_samples = 0
+    for t, lo in zip(targets, los):
+        f = np.asarray(t.chan_freq, np.float64)
+        w = np.abs(np.gradient(f)) if t.chan_width is None else np.asarray(t.chan_width, np.float64)
+        opz = 1.0 + float(t.z)
+        reach = ((f + 0.5 * w) * opz > lo) & ((f - 0.5 * w) * opz < lo + REBIN_NOUT * dfreq)
+        nrow, npol = int(t.vis.shape[0]), int(t.vis.shape[2])
+        nin += nrow * int(reach.sum()) * npol
+        nout_samples += nrow * REBIN_NOUT * npol
+        nbytes += nrow * int(reach.sum()) * npol * 9 + nrow * 24 + nrow * REBIN_NOUT * npol * 13 + nrow * 24
+    kernel_ms, call_ms = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, _, tim = vista.rebin_rows(targets, REBIN_NOUT, dfreq, central, outs=outs)
+        call_ms.append((time.perf_counter() - t0) * 1e3)
+        kernel_ms.append(tim["accum_ms"])
+    kms = sorted(kernel_ms)[len(kernel_ms) // 2]
+    cms = sorted(call_ms)[len(call_ms) // 2]
+    achieved = nbytes / (kms / 1e3) / 1e9
+    log("rebinned rows: kernel %.2f ms, call %.2f ms; %.3g input samples, %.0f GB/s algorithmic"
+        % (kms, cms, nin, achieved))
+    del outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": "per-row rebinned product: the %d targets above, each row onto its own window of %d "
+                    "channels of the common rest width around the line" % (len(targets), REBIN_NOUT),
+        "input_samples": nin,
+        "output_samples": nout_samples,
+        "algorithmic_bytes": nbytes,
+        "kernel_ms": kms,
+        "call_ms": cms,
+        "samples_per_s": nin / (cms / 1e3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+    }
+
+
 BATCH_STACKS = 64
 BATCH_MU = math.log(4.0)     # targets per stack ~ clip(round(lognormal(log 4, 1)), 1, 64)
 BATCH_N_INT = 10
@@ -282,6 +336,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed leg")
+    ap.add_argument("--no-rebinned", action="store_true", help="skip the per-row rebinned leg")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -408,7 +463,11 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on %d targets" % args.cpu_targets)
         res["cpu_baseline"] = cpu_baseline(targets, grid, args.cpu_targets)
-    del targets, out                          # the other legs bring their own inputs
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_rebinned:
+        res["rebinned"] = rebinned_leg(targets, cfg, grid)
+    del targets                               # the other legs bring their own inputs
     torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = batched_leg(reps=2)

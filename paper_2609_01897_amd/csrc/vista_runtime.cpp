@@ -1158,8 +1158,9 @@ int vista_rebin_rows(const vista_rebin_desc* d, int32_t n, const vista_target* t
             T.nrow = t[i].nrow; T.nchan = t[i].nchan; T.npol = t[i].npol; T.nout = d->nout;
             T.l = t[i].l; T.m = t[i].m; T.nm1 = plans[i].nm1; T.opz = 1.0 + t[i].z;
         }
-        // row blocks, grouped by polarisation count: about 2048 outputs per workgroup
-        const int32_t rpb = std::max(1, std::min(64, 2048 / d->nout));
+        // row blocks, grouped by polarisation count: a workgroup's thread groups (256 /
+        // min(nout, 256) of them) take 16 rows each
+        const int32_t rpb = std::min(2048, 16 * (256 / std::min(d->nout, 256)));
         std::vector<RebinBlock> blocks;
         int64_t cls[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // npol 1, 2, 4: [first, count)
         const int pols[3] = {1, 2, 4};
