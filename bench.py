@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "stacked vis·chan·pol/s + HBM GB/s vs peak; batched/compensated vs plain speedup"
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, AMD public specification
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "accum_c2_counters.json")
+PROFILE_REBIN = os.path.join(ROOT, "profiles", "rebin_c2_counters.json")
+REBIN_SRC = os.path.join(ROOT, "paper_2609_01897_amd", "csrc", "vista_rebin.hip")
 KERNEL_SRC = os.path.join(ROOT, "paper_2609_01897_amd", "csrc", "vista_accum.hip")
 
 
@@ -61,6 +63,19 @@ def counter_traffic(config_name, shape):
         h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         want = {k: int(shape[k]) for k in ("tile_u", "tile_v", "jblock", "waves")} if shape else None
         if d.get("kernel_sha256") == h and d.get("config") == config_name and d.get("launch_shape") == want:
+            return d.get("hbm_bytes_per_launch")
+    except Exception:
+        pass
+    return None
+
+
+def rebin_counter_traffic(config_name, nout):
+    """Counter-measured HBM bytes of one rebinning launch, if the committed summary was
+    taken on the current kernel source, on this workload and window width."""
+    try:
+        d = json.load(open(PROFILE_REBIN))
+        h = hashlib.sha256(open(REBIN_SRC, "rb").read()).hexdigest()
+        if d.get("kernel_sha256") == h and d.get("config") == config_name and d.get("nout") == nout:
             return d.get("hbm_bytes_per_launch")
     except Exception:
         pass
@@ -247,7 +262,7 @@ def rebinned_leg(targets, cfg, grid, reps=3):
         "call_ms": cms,
         "samples_per_s": nin / (cms / 1e3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": rebin_counter_traffic(cfg.name, REBIN_NOUT)},
     }
 
 
