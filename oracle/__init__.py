@@ -34,7 +34,9 @@ class _Target(C.Structure):
                 ("uvw", C.c_void_p), ("vis", C.c_void_p), ("weight", C.c_void_p),
                 ("flag", C.c_void_p), ("chan_freq", C.c_void_p), ("chan_width", C.c_void_p),
                 ("l", C.c_double), ("m", C.c_double), ("z", C.c_double),
-                ("weight_per_chan", C.c_int32), ("kbeg", C.c_int32), ("kend", C.c_int32)]
+                ("weight_per_chan", C.c_int32), ("kbeg", C.c_int32), ("kend", C.c_int32),
+                ("rotate", C.c_int32), ("ra0", C.c_double), ("dec0", C.c_double), ("ra1", C.c_double),
+                ("dec1", C.c_double)]
 
 
 def lib():
@@ -53,6 +55,7 @@ def lib():
         _lib.ora_plan_spectral_grid.argtypes = [i32, p, p, p, p, C.c_double, i32, C.POINTER(C.c_double),
                                                 C.POINTER(C.c_double)]
         _lib.ora_check.argtypes = [C.POINTER(_Grid), i32, C.POINTER(_Target)]
+        _lib.ora_frame_matrix.argtypes = [C.POINTER(_Target), p, p]
         _lib.ora_rebin_window.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, C.POINTER(C.c_double)]
         _lib.ora_rebin_rows.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, p, p, p, p]
     return _lib
@@ -89,7 +92,9 @@ def _target(h: dict) -> _Target:
     npol = int(h["weight"].shape[-1])
     return _Target(nrow, nchan, npol, ptr(h["uvw"]), ptr(h["vis"]), ptr(h["weight"]), ptr(h["flag"]),
                    ptr(h["chan_freq"]), ptr(h["chan_width"]), float(h["l"]), float(h["m"]),
-                   float(h["z"]), int(bool(h.get("weight_per_chan", False))), h["kbeg"], h["kend"])
+                   float(h["z"]), int(bool(h.get("weight_per_chan", False))), h["kbeg"], h["kend"],
+                   int(bool(h.get("rotate_uvw", False))), float(h.get("ra0", 0.0)), float(h.get("dec0", 0.0)),
+                   float(h.get("ra1", 0.0)), float(h.get("dec1", 0.0)))
 
 
 def stack(grid: dict, targets, jlo: int = 0, jhi: int | None = None, stats: bool = True,
@@ -221,3 +226,14 @@ def rebin_rows(target, freq_lo: float, dfreq: float, nout: int) -> dict:
     if rc:
         raise ValueError("oracle rejected the inputs (code %d)" % rc)
     return dict(vis=out.view(np.complex128)[..., 0], flag=flag, wsum=wsum, uvw=uvw)
+
+
+def rotation(target) -> tuple:
+    """Eq. 1's rotation of the target as the oracle applies it: (R [3, 3], l, m, n - 1)."""
+    h = _host(target)
+    t = _target(h)
+    R = np.zeros(9, np.float64)
+    lm = np.zeros(3, np.float64)
+    if lib().ora_frame_matrix(C.byref(t), R.ctypes.data, lm.ctypes.data):
+        raise ValueError("oracle rejected the target")
+    return R.reshape(3, 3), float(lm[0]), float(lm[1]), float(lm[2])

@@ -56,6 +56,27 @@ def overlap_pairs(grid, freq, width, z):
     return pairs
 
 
+def rotation(t: dict):
+    """Eq. 1's rotation written from its closed-form elements (d = ra1 - ra0):
+    rows (east, north, towards) of the stacking position's uvw frame dotted with those of
+    the phase centre's.  Returns (R, l, m); R is None without the rotation."""
+    if not t.get("rotate_uvw"):
+        return None, float(t["l"]), float(t["m"])
+    a0, d0, a1, d1 = float(t["ra0"]), float(t["dec0"]), float(t["ra1"]), float(t["dec1"])
+    d = a1 - a0
+    sd0, cd0, sd1, cd1 = math.sin(d0), math.cos(d0), math.sin(d1), math.cos(d1)
+    R = [[math.cos(d), sd0 * math.sin(d), -cd0 * math.sin(d)],
+         [-sd1 * math.sin(d), sd1 * sd0 * math.cos(d) + cd1 * cd0, cd1 * sd0 - sd1 * cd0 * math.cos(d)],
+         [cd1 * math.sin(d), sd1 * cd0 - cd1 * sd0 * math.cos(d), sd1 * sd0 + cd1 * cd0 * math.cos(d)]]
+    return R, R[2][0], R[2][1]
+
+
+def _rot(R, u, v, w):
+    if R is None:
+        return u, v, w
+    return tuple(R[i][0] * u + R[i][1] * v + R[i][2] * w for i in range(3))
+
+
 def stack(grid: dict, targets) -> dict:
     """Returns {(j, iv, iu): [S (complex), W, A, N]} and the sample classification."""
     cells = {}
@@ -71,15 +92,16 @@ def stack(grid: dict, targets) -> dict:
         weight = np.asarray(t["weight"], np.float32)
         freq = [float(x) for x in t["chan_freq"]]
         pairs = overlap_pairs(grid, freq, t.get("chan_width"), float(t["z"]))
-        l, m = float(t["l"]), float(t["m"])
+        R, l, m = rotation(t)
         n_minus_1 = -(l * l + m * m) / (1.0 + math.sqrt(1.0 - (l * l + m * m)))
         npol = vis.shape[2]
         for r in range(uvw.shape[0]):
+            ur, vr, _ = _rot(R, float(uvw[r, 0]), float(uvw[r, 1]), float(uvw[r, 2]))
             for k in range(len(freq)):
                 a = freq[k] / C_LIGHT
                 u, v, w = float(uvw[r, 0]) * a, float(uvw[r, 1]) * a, float(uvw[r, 2]) * a
-                ru = round_half_even(u * (1.0 / grid["du"]))
-                rv = round_half_even(v * (1.0 / grid["dv"]))
+                ru = round_half_even((ur * a) * (1.0 / grid["du"]))
+                rv = round_half_even((vr * a) * (1.0 / grid["dv"]))
                 inside = (-(nu_ // 2) <= ru < nu_ - nu_ // 2) and (-(nv_ // 2) <= rv < nv_ - nv_ // 2)
                 turns = u * l + v * m + w * n_minus_1
                 ph = 2.0 * math.pi * (turns - round_half_even(turns))
@@ -153,7 +175,7 @@ def rebin_rows(t: dict, freq_lo: float, dfreq: float, nout: int) -> dict:
     freq = [float(x) for x in t["chan_freq"]]
     z = float(t["z"])
     pairs = overlap_pairs(grid, freq, t.get("chan_width"), z)
-    l, m = float(t["l"]), float(t["m"])
+    R, l, m = rotation(t)
     n_minus_1 = -(l * l + m * m) / (1.0 + math.sqrt(1.0 - (l * l + m * m)))
     nrow, npol = uvw.shape[0], vis.shape[2]
     out = np.zeros((nrow, nout, npol), np.complex128)
@@ -179,4 +201,5 @@ def rebin_rows(t: dict, freq_lo: float, dfreq: float, nout: int) -> dict:
                 out[r, j, p] = num[(j, p)] / d
                 oflag[r, j, p] = 0
                 wsum[r, j, p] = d
-    return dict(vis=out, flag=oflag, wsum=wsum, uvw=uvw / (1.0 + z))
+    ruvw = np.array([_rot(R, *[float(x) for x in uvw[r]]) for r in range(nrow)], np.float64).reshape(nrow, 3)
+    return dict(vis=out, flag=oflag, wsum=wsum, uvw=ruvw / (1.0 + z))

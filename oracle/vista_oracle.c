@@ -24,10 +24,15 @@
  *   The paper casts visibilities to double before the phase multiply (Sec. 3.2, last
  *   paragraph); so does this file, and everything else is double too.
  *
+ * With a target's rotation switched on (Eq. 1's R from the phase centre to the stacking
+ * position, given as two (R.A., Dec.) pairs), (l, m) are the stacking position's
+ * direction cosines and the uv cell is taken from the rotated baseline R (u, v, w); the
+ * Eq. 2 phase still uses the original baseline (its turns are exactly w' - w).
+ *
  * It also computes the paper's own per-row product (ora_rebin_window, ora_rebin_rows):
  * each target's rows rebinned onto the target's own output window by Eq. 3 with the
  * Eq. 4 weights, normalised per row and output channel, after the same Eq. 2 shift, and
- * its uvw divided by 1 + z (Eq. 1 without the rotation R).
+ * its baseline R (u, v, w) / (1 + z) (Eq. 1).
  *
  * Build with -ffp-contract=off and without fast-math: the cell and channel indices
  * must follow exactly the operation sequence written here.
@@ -68,6 +73,9 @@ typedef struct {
     double l, m, z;
     int32_t weight_per_chan;
     int32_t kbeg, kend;       /* the data arrays hold channels [kbeg, kend) */
+    int32_t rotate;           /* 1: Eq. 1's rotation from (ra0, dec0) to (ra1, dec1) [rad];
+                                 l, m are then taken from the angles */
+    double ra0, dec0, ra1, dec1;
 } ora_target;
 
 /* Per-channel rest-frame table of one target: a_k = nu_k / c and the contributing set
@@ -162,6 +170,55 @@ static double ora_n_minus_1(double l, double m) {
     return -q / (1.0 + sqrt(1.0 - q));
 }
 
+/* Eq. 1's rotation R.  The uvw frame of a phase centre (ra, dec) has, in equatorial
+ * coordinates, the axes u = (-sin ra, cos ra, 0) (east), v = (-sin dec cos ra,
+ * -sin dec sin ra, cos dec) (north) and w = (cos dec cos ra, cos dec sin ra, sin dec)
+ * (towards the centre).  A baseline with coordinates (u, v, w) about the phase centre
+ * (ra0, dec0) has coordinates R (u, v, w) about the stacking position (ra1, dec1), with
+ * R[i][j] = axis_i(ra1, dec1) . axis_j(ra0, dec0); R's third row is the stacking
+ * position's direction cosines (l, m, n) about the phase centre, so w' - w is exactly
+ * the Eq. 2 turns u l + v m + w (n - 1).  Without the rotation R is the identity and
+ * (l, m) are the target's given direction cosines. */
+typedef struct {
+    int rotate;
+    double R[9];
+    double l, m, nm1;
+} ora_frame;
+
+static void ora_axes(double ra, double dec, double ax[3][3]) {
+    ax[0][0] = -sin(ra);            ax[0][1] = cos(ra);             ax[0][2] = 0.0;
+    ax[1][0] = -sin(dec) * cos(ra); ax[1][1] = -sin(dec) * sin(ra); ax[1][2] = cos(dec);
+    ax[2][0] = cos(dec) * cos(ra);  ax[2][1] = cos(dec) * sin(ra);  ax[2][2] = sin(dec);
+}
+
+static void ora_make_frame(const ora_target* t, ora_frame* f) {
+    f->rotate = t->rotate;
+    if (t->rotate) {
+        double a0[3][3], a1[3][3];
+        ora_axes(t->ra0, t->dec0, a0);
+        ora_axes(t->ra1, t->dec1, a1);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                f->R[3 * i + j] = a1[i][0] * a0[j][0] + a1[i][1] * a0[j][1] + a1[i][2] * a0[j][2];
+        f->l = f->R[6];
+        f->m = f->R[7];
+    } else {
+        for (int i = 0; i < 9; ++i) f->R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+        f->l = t->l;
+        f->m = t->m;
+    }
+    f->nm1 = ora_n_minus_1(f->l, f->m);
+}
+
+/* The baseline about the stacking position: R (u, v, w). */
+static void ora_rot(const ora_frame* f, const double* uvw, double* out) {
+    if (!f->rotate) {
+        out[0] = uvw[0]; out[1] = uvw[1]; out[2] = uvw[2];
+        return;
+    }
+    for (int i = 0; i < 3; ++i) out[i] = f->R[3 * i] * uvw[0] + f->R[3 * i + 1] * uvw[1] + f->R[3 * i + 2] * uvw[2];
+}
+
 /* Nearest uv cell of a (row, channel): u = u_m a_k in wavelengths, index
  * rint(u / du) counted from the centre cell n/2.  The bounds test is made on the
  * rounded value in double, so a non-finite or huge coordinate is simply outside;
@@ -207,7 +264,13 @@ int ora_check(const ora_grid* g, int32_t ntgt, const ora_target* tg) {
         if (t->kbeg < 0 || t->kend > t->nchan || t->kbeg > t->kend) return -1;
         if (t->nchan == 1 && !t->chan_width) return -1;
         if (!(t->z > -1.0 && isfinite(t->z))) return -1;
-        if (!(t->l * t->l + t->m * t->m < 1.0)) return -1;
+        if (t->rotate != 0 && t->rotate != 1) return -1;
+        if (t->rotate) {
+            if (!(isfinite(t->ra0) && isfinite(t->dec0) && isfinite(t->ra1) && isfinite(t->dec1))) return -1;
+            ora_frame f;
+            ora_make_frame(t, &f);
+            if (!(f.R[8] > 0.0)) return -1;     /* the stacking position must face the phase centre */
+        } else if (!(t->l * t->l + t->m * t->m < 1.0)) return -1;
     }
     return 0;
 }
@@ -259,19 +322,22 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
         for (int32_t i = 0; i < ntgt; ++i) {
             const ora_target* t = &tg[i];
             const ora_table* tb = &tabs[i];
-            double nm1 = ora_n_minus_1(t->l, t->m);
+            ora_frame fr;
+            ora_make_frame(t, &fr);
             int32_t nk = t->kend - t->kbeg;
             for (int64_t r = 0; r < t->nrow; ++r) {
                 const double* uvw = t->uvw + 3 * r;
+                double ur[3];
+                ora_rot(&fr, uvw, ur);
                 for (int32_t k = t->kbeg; k < t->kend; ++k) {
                     int32_t q0 = tb->start[k], q1 = tb->start[k + 1], q;
                     int mine = 0;
                     for (q = q0; q < q1; ++q) mine |= (tb->j[q] >= ja && tb->j[q] < jb);
                     if (!mine) continue;
                     int64_t iu, iv;
-                    if (!ora_cell(g, uvw, tb->a[k], &iu, &iv)) continue;
+                    if (!ora_cell(g, ur, tb->a[k], &iu, &iv)) continue;
                     double pc, ps;
-                    ora_phasor(uvw, tb->a[k], t->l, t->m, nm1, &pc, &ps);
+                    ora_phasor(uvw, tb->a[k], fr.l, fr.m, fr.nm1, &pc, &ps);
                     int32_t kk = k - t->kbeg;
                     for (int32_t p = 0; p < t->npol; ++p) {
                         size_t e = ((size_t)r * nk + kk) * t->npol + p;
@@ -302,12 +368,16 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
         for (int32_t i = 0; i < ntgt; ++i) {
             const ora_target* t = &tg[i];
             const ora_table* tb = &tabs[i];
+            ora_frame fr;
+            ora_make_frame(t, &fr);
             int32_t nk = t->kend - t->kbeg;
             for (int64_t r = 0; r < t->nrow; ++r) {
+                double ur[3];
+                ora_rot(&fr, t->uvw + 3 * r, ur);
                 for (int32_t k = t->kbeg; k < t->kend; ++k) {
                     int32_t nj = tb->start[k + 1] - tb->start[k];
                     int64_t iu, iv;
-                    int inside = nj > 0 ? ora_cell(g, t->uvw + 3 * r, tb->a[k], &iu, &iv) : 0;
+                    int inside = nj > 0 ? ora_cell(g, ur, tb->a[k], &iu, &iv) : 0;
                     int32_t kk = k - t->kbeg;
                     for (int32_t p = 0; p < t->npol; ++p) {
                         size_t e = ((size_t)r * nk + kk) * t->npol + p;
@@ -339,11 +409,15 @@ int ora_indices(const ora_grid* g, const ora_target* t, int64_t* iu, int64_t* iv
     int rc = ora_build_table(g, t, &tb);
     if (rc) { ora_free_table(&tb); return rc; }
     int32_t nk = t->kend - t->kbeg;
+    ora_frame fr;
+    ora_make_frame(t, &fr);
     for (int64_t r = 0; r < t->nrow; ++r) {
+        double ur[3];
+        ora_rot(&fr, t->uvw + 3 * r, ur);
         for (int32_t k = t->kbeg; k < t->kend; ++k) {
             size_t e = (size_t)r * nk + (k - t->kbeg);
             int64_t a, b;
-            ora_cell(g, t->uvw + 3 * r, tb.a[k], &a, &b);
+            ora_cell(g, ur, tb.a[k], &a, &b);
             iu[e] = a;
             iv[e] = b;
             int32_t n = tb.start[k + 1] - tb.start[k];
@@ -359,12 +433,13 @@ int ora_indices(const ora_grid* g, const ora_target* t, int64_t* iu, int64_t* iv
  * of flags and weights: out [nrow][kend-kbeg][npol][2]. */
 int ora_rotate(const ora_target* t, double* out) {
     if (t->nchan < 1 || t->kbeg < 0 || t->kend > t->nchan || t->kbeg > t->kend) return -1;
-    double nm1 = ora_n_minus_1(t->l, t->m);
+    ora_frame fr;
+    ora_make_frame(t, &fr);
     int32_t nk = t->kend - t->kbeg;
     for (int64_t r = 0; r < t->nrow; ++r) {
         for (int32_t k = t->kbeg; k < t->kend; ++k) {
             double pc, ps;
-            ora_phasor(t->uvw + 3 * r, t->chan_freq[k] / ORA_C, t->l, t->m, nm1, &pc, &ps);
+            ora_phasor(t->uvw + 3 * r, t->chan_freq[k] / ORA_C, fr.l, fr.m, fr.nm1, &pc, &ps);
             for (int32_t p = 0; p < t->npol; ++p) {
                 size_t e = ((size_t)r * nk + (k - t->kbeg)) * t->npol + p;
                 double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
@@ -455,8 +530,8 @@ int ora_rebin_window(const ora_target* t, double central_freq, double dfreq, int
  * the sums over the input channels k whose Eq. 4 overlap f_kj with channel j is above the
  * sliver threshold and whose sample (r, k, p) is not flagged; V' is the Eq. 2-rotated
  * visibility, in double.  Where no such channel exists the output is 0 and flagged.
- * wsum[r][j][p] = sum_k f_kj (0 where flagged).  uvw_out[r] = uvw[r] / (1 + z), the
- * rest-frame baseline of Eq. 1 (the rotation R of Eq. 1 is not applied).  Visibility
+ * wsum[r][j][p] = sum_k f_kj (0 where flagged).  uvw_out[r] = R uvw[r] / (1 + z), the
+ * rest-frame baseline of Eq. 1 (R the identity unless the target asks for the rotation).  Visibility
  * weights do not enter Eq. 3.  The data arrays must hold all channels. */
 int ora_rebin_rows(const ora_target* t, double freq_lo, double dfreq, int32_t nout, double* out,
                    uint8_t* oflag, double* wsum, double* uvw_out) {
@@ -469,7 +544,9 @@ int ora_rebin_rows(const ora_target* t, double freq_lo, double dfreq, int32_t no
     int rc = ora_build_table(&g, t, &tb);
     if (rc) { ora_free_table(&tb); return rc; }
     const int32_t np = t->npol, nk = t->nchan;
-    const double nm1 = ora_n_minus_1(t->l, t->m), opz = 1.0 + t->z;
+    const double opz = 1.0 + t->z;
+    ora_frame fr;
+    ora_make_frame(t, &fr);
     double* num = (double*)malloc(sizeof(double) * 2 * (size_t)nout * np);
     double* den = (double*)malloc(sizeof(double) * (size_t)nout * np);
     if (!num || !den) { free(num); free(den); ora_free_table(&tb); return -3; }
@@ -478,7 +555,7 @@ int ora_rebin_rows(const ora_target* t, double freq_lo, double dfreq, int32_t no
         memset(den, 0, sizeof(double) * (size_t)nout * np);
         for (int32_t k = 0; k < nk; ++k) {
             double pc, ps;
-            ora_phasor(t->uvw + 3 * r, tb.a[k], t->l, t->m, nm1, &pc, &ps);
+            ora_phasor(t->uvw + 3 * r, tb.a[k], fr.l, fr.m, fr.nm1, &pc, &ps);
             for (int32_t q = tb.start[k]; q < tb.start[k + 1]; ++q) {
                 const int32_t j = tb.j[q];
                 const double f = tb.f[q];
@@ -501,11 +578,28 @@ int ora_rebin_rows(const ora_target* t, double freq_lo, double dfreq, int32_t no
                 if (oflag) oflag[o] = d > 0.0 ? 0 : 1;
                 if (wsum) wsum[o] = d;
             }
-        if (uvw_out)
-            for (int i = 0; i < 3; ++i) uvw_out[3 * r + i] = t->uvw[3 * r + i] / opz;
+        if (uvw_out) {
+            double ur[3];
+            ora_rot(&fr, t->uvw + 3 * r, ur);
+            for (int i = 0; i < 3; ++i) uvw_out[3 * r + i] = ur[i] / opz;
+        }
     }
     free(num);
     free(den);
     ora_free_table(&tb);
+    return 0;
+}
+
+
+/* Eq. 1's rotation of one target as the oracle uses it: R (row-major 3 x 3) and the
+ * direction cosines (l, m) with n - 1 (for tests). */
+int ora_frame_matrix(const ora_target* t, double* R, double* lm_nm1) {
+    if (!t || (t->rotate != 0 && t->rotate != 1)) return -1;
+    ora_frame f;
+    ora_make_frame(t, &f);
+    for (int i = 0; i < 9; ++i) R[i] = f.R[i];
+    lm_nm1[0] = f.l;
+    lm_nm1[1] = f.m;
+    lm_nm1[2] = f.nm1;
     return 0;
 }

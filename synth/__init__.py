@@ -7,7 +7,7 @@ method's arithmetic (no phase re-centring, no rest-frame rebinning, no
 gridding).  Random numbers are drawn here and handed to both sides as inputs.
 """
 from .configs import CONFIGS, config, grid_for
-from .generate import Target, batch_stack_sizes, make_target, make_targets, make_grid
+from .generate import Target, batch_stack_sizes, make_target, make_targets, make_grid, radec_of_offset
 
 __all__ = ["CONFIGS", "config", "grid_for", "Target", "batch_stack_sizes", "make_target", "make_targets",
-           "make_grid"]
+           "make_grid", "radec_of_offset"]

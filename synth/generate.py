@@ -47,6 +47,13 @@ class Target:
     z: float
     weight_per_chan: bool = False
     meta: dict = dataclasses.field(default_factory=dict)
+    # the phase centre (ra0, dec0) and the stacking position (ra1, dec1) [rad], consistent
+    # with (l, m); rotate_uvw asks the stack to apply Eq. 1's rotation between them
+    ra0: float = 0.0
+    dec0: float = 0.0
+    ra1: float = 0.0
+    dec1: float = 0.0
+    rotate_uvw: bool = False
 
     @property
     def nrow(self) -> int:
@@ -70,7 +77,8 @@ class Target:
         cp = lambda x: None if x is None else x.detach().cpu().numpy()
         return dict(uvw=cp(self.uvw), vis=cp(self.vis), weight=cp(self.weight), flag=cp(self.flag),
                     chan_freq=self.chan_freq, chan_width=self.chan_width, l=self.l, m=self.m,
-                    z=self.z, weight_per_chan=self.weight_per_chan)
+                    z=self.z, weight_per_chan=self.weight_per_chan, rotate_uvw=self.rotate_uvw,
+                    ra0=self.ra0, dec0=self.dec0, ra1=self.ra1, dec1=self.dec1)
 
     def channel_slice(self, k0: int, k1: int) -> dict:
         """Host copy of channels [k0, k1) of every row, with the full frequency axis."""
@@ -79,7 +87,8 @@ class Target:
                  weight=(cp(self.weight) if self.weight_per_chan else self.weight.cpu().numpy()),
                  flag=cp(self.flag), chan_freq=self.chan_freq, chan_width=self.chan_width,
                  l=self.l, m=self.m, z=self.z, weight_per_chan=self.weight_per_chan,
-                 kbeg=k0, kend=k1)
+                 kbeg=k0, kend=k1, rotate_uvw=self.rotate_uvw, ra0=self.ra0, dec0=self.dec0, ra1=self.ra1,
+                 dec1=self.dec1)
         return d
 
 
@@ -196,8 +205,21 @@ def make_target(cfg: Config | str, index: int, device="cpu", *, noiseless: bool 
             flag[r0:r1] = fl.to(torch.uint8)
     meta = dict(n_ant=n_ant, gaussian=gauss, theta=theta, seed=bulk_seed, index=index, cfg=cfg.name,
                 peak=cfg.peak)
+    ra1, dec1 = radec_of_offset(0.0, DECLINATION, l0, m0)
     return Target(uvw=uvw_t, vis=vis, weight=weight, flag=flag, chan_freq=freq, chan_width=width,
-                  l=l0, m=m0, z=zz, weight_per_chan=weight_per_chan, meta=meta)
+                  l=l0, m=m0, z=zz, weight_per_chan=weight_per_chan, meta=meta, ra0=0.0, dec0=DECLINATION,
+                  ra1=ra1, dec1=dec1)
+
+
+def radec_of_offset(ra0: float, dec0: float, l: float, m: float) -> tuple:
+    """(R.A., Dec.) of the direction with direction cosines (l, m) about the phase centre
+    (ra0, dec0): l along the centre's east axis, m along its north axis."""
+    n = math.sqrt(1.0 - l * l - m * m)
+    sr, cr, sd, cd = math.sin(ra0), math.cos(ra0), math.sin(dec0), math.cos(dec0)
+    x = -l * sr - m * sd * cr + n * cd * cr
+    y = l * cr - m * sd * sr + n * cd * sr
+    zc = m * cd + n * sd
+    return math.atan2(y, x), math.asin(max(-1.0, min(1.0, zc)))
 
 
 def make_targets(cfg: Config | str, device="cpu", n: int | None = None, **kw) -> list:
