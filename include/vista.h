@@ -92,10 +92,24 @@ typedef struct {
                                     difference, one-sided at the ends (Eq. 4's Delta nu_k);
                                     required when nchan == 1; host memory */
     double l, m;                 /* direction cosines of the target relative to the phase
-                                    centre, l*l + m*m < 1 */
+                                    centre, l*l + m*m < 1 (ignored with rotate_uvw) */
     double z;                    /* redshift, finite, > -1 */
     int32_t weight_per_chan;     /* 0 or 1 */
     int32_t mem;                 /* VISTA_MEM_* of uvw, vis, weight and flag */
+    int32_t rotate_uvw;          /* 0: l, m as given, baselines not rotated.  1: Eq. 1's
+                                    rotation R from the phase centre (ra0, dec0) to the
+                                    stacking position (ra1, dec1): (l, m) become the stacking
+                                    position's direction cosines about the phase centre, and
+                                    uv cells (and the rebinned rows' baselines) are taken from
+                                    R (u, v, w); the Eq. 2 phase keeps the original baseline
+                                    (its turns equal w' - w).  R[i][j] = axis_i(ra1, dec1) .
+                                    axis_j(ra0, dec0) with the uvw axes of a centre (ra, dec):
+                                    u = (-sin ra, cos ra, 0), v = (-sin dec cos ra,
+                                    -sin dec sin ra, cos dec), w = (cos dec cos ra,
+                                    cos dec sin ra, sin dec) */
+    double ra0, dec0, ra1, dec1; /* [rad], finite, read only with rotate_uvw; the stacking
+                                    position must lie in the phase centre's front hemisphere
+                                    (n > 0) */
 } vista_target;
 
 /* Outputs, dense [nchan][nv][nu] over the whole grid.  Any pointer may be NULL to skip

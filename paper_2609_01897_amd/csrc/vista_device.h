@@ -42,6 +42,19 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 #define VISTA_CONST
 #endif
 
+// A row's uv coordinates for cell assignment: the baseline rotated by Eq. 1's R when the
+// target asks for it (the same FP64 operation sequence as the definition), else as given.
+__device__ __forceinline__ void cell_uv(const DevTarget& T, double U, double V, double W, double* Ur,
+                                        double* Vr) {
+    if (T.rotate) {
+        *Ur = T.rot[0] * U + T.rot[1] * V + T.rot[2] * W;
+        *Vr = T.rot[3] * U + T.rot[4] * V + T.rot[5] * W;
+    } else {
+        *Ur = U;
+        *Vr = V;
+    }
+}
+
 // Pointers read from descriptors are generic; casting them to the global address space
 // lets the compiler use global (not flat) memory instructions.
 template <class T>

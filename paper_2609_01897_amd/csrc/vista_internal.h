@@ -47,6 +47,9 @@ struct DevTarget {
     int32_t nblocks;          // entries of blk
     int32_t chan0;            // index of channel 0 in the launch-wide channel tables
     double l, m, nm1;         // direction cosines, n - 1
+    double rot[6];            // with `rotate`: the first two rows of Eq. 1's R (uv cells from
+                              // R (u, v, w)); the Eq. 2 phase keeps the original baseline
+    int32_t rotate, pad_rot;
 };
 
 // Context of row g of a launch, written once by the binning pass and read by the packed
@@ -130,6 +133,8 @@ struct RebinTarget {
     int64_t nrow;
     int32_t nchan, npol, nout, pad;
     double l, m, nm1, opz;    // direction cosines, n - 1, 1 + z
+    double R[9];              // Eq. 1's rotation (with `rotate`) of the output baselines
+    int32_t rotate, pad_rot;
 };
 // A workgroup's share: rows [row0, row0 + nrows) of target `target`.
 struct RebinBlock {

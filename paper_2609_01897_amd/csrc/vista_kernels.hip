@@ -111,8 +111,7 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
             // the row's context for the packed accumulation
             const double U = T.uvw[3 * r], V = T.uvw[3 * r + 1], W = T.uvw[3 * r + 2];
             RowCtx c;
-            c.U = U;
-            c.V = V;
+            cell_uv(T, U, V, W, &c.U, &c.V);        // uv cells: the (rotated) baseline
             if (L.phase_fp32)
                 c.T = (double)((float)U * (float)T.l + (float)V * (float)T.m + (float)W * (float)T.nm1);
             else
@@ -128,7 +127,8 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
             L.rowctx[g] = c;
         }
         if (T.kin_lo < T.kin_hi) {
-            double U = T.uvw[3 * r], V = T.uvw[3 * r + 1];
+            double U, V;
+            cell_uv(T, T.uvw[3 * r], T.uvw[3 * r + 1], T.uvw[3 * r + 2], &U, &V);
             Track tr = in_grid(T.chan, T.kin_lo, T.kin_hi, U, V, S.inv_du, S.inv_dv, S.nu, S.nv);
             int32_t inb_all = T.inband[T.kin_hi] - T.inband[T.kin_lo];
             int32_t inb_in = T.inband[tr.gb] - T.inband[tr.ga];
@@ -457,10 +457,19 @@ __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict_
             r_l = (int32_t)r;
             if (valid) {
                 const VISTA_GLOBAL double* uvw = gptr(Tl->uvw) + 3 * r;
-                U_l = uvw[0];
-                V_l = uvw[1];
-                const double Wm = uvw[2];
-                T_l = phase_fp32 ? Wm : U_l * Tl->l + V_l * Tl->m + Wm * Tl->nm1;
+                const double Um = uvw[0], Vm = uvw[1], Wm = uvw[2];
+                if (Tl->rotate) {                    // uv cells: Eq. 1's rotated baseline
+                    U_l = Tl->rot[0] * Um + Tl->rot[1] * Vm + Tl->rot[2] * Wm;
+                    V_l = Tl->rot[3] * Um + Tl->rot[4] * Vm + Tl->rot[5] * Wm;
+                } else {
+                    U_l = Um;
+                    V_l = Vm;
+                }
+                // Eq. 2 turns per unit a_k from the original baseline (formed in FP32 under
+                // the ablation)
+                T_l = phase_fp32 ? (double)((float)Um * (float)Tl->l + (float)Vm * (float)Tl->m +
+                                            (float)Wm * (float)Tl->nm1)
+                                 : Um * Tl->l + Vm * Tl->m + Wm * Tl->nm1;
                 const int np = Tl->npol;
                 const VISTA_GLOBAL float* wp = gptr(Tl->weight) + (size_t)r * np;
                 const bool rw = !Tl->weight_per_chan;
@@ -538,9 +547,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum(const LaunchDesc* __restrict_
             }
             float c, s;
             if (phase_fp32) {
-                const float a32 = (float)ld.a;
-                phasor_fp32((float)it.U * a32, (float)it.V * a32, (float)it.trow * a32, (float)T.l, (float)T.m,
-                            (float)T.nm1, &c, &s);
+                const float t = (float)it.trow * (float)ld.a;
+                sincos_turns(t - rintf(t), &s, &c);
             } else {
                 phasor(it.trow, ld.a, &c, &s);
             }
@@ -661,8 +669,10 @@ __global__ void k_debug_indices(const DevTarget* __restrict__ Tp, const DevStack
     int64_t r = e / nchan;
     int32_t k = (int32_t)(e % nchan);
     DevChan ce = T.chan[k];
-    double ru = cell_coord(T.uvw[3 * r], ce.a, S.inv_du);
-    double rv = cell_coord(T.uvw[3 * r + 1], ce.a, S.inv_dv);
+    double U, V;
+    cell_uv(T, T.uvw[3 * r], T.uvw[3 * r + 1], T.uvw[3 * r + 2], &U, &V);
+    double ru = cell_coord(U, ce.a, S.inv_du);
+    double rv = cell_coord(V, ce.a, S.inv_dv);
     iu[e] = fabs(ru) < 2.0e9 ? (int32_t)ru + S.nu / 2 : INT32_MIN;
     iv[e] = fabs(rv) < 2.0e9 ? (int32_t)rv + S.nv / 2 : INT32_MIN;
     int32_t n = (int32_t)(ce.jn >> 24);

@@ -31,6 +31,31 @@ double channel_width(const double* f, const double* w, int32_t n, int32_t k) {
     return fabs(f[k + 1] - f[k - 1]) / 2.0;
 }
 
+Frame make_frame(const vista_target* t) {
+    Frame f;
+    f.rotate = t->rotate_uvw;
+    if (t->rotate_uvw) {
+        // uvw axes (east, north, towards) of the two centres in equatorial coordinates
+        auto axes = [](double ra, double dec, double ax[3][3]) {
+            ax[0][0] = -sin(ra);            ax[0][1] = cos(ra);             ax[0][2] = 0.0;
+            ax[1][0] = -sin(dec) * cos(ra); ax[1][1] = -sin(dec) * sin(ra); ax[1][2] = cos(dec);
+            ax[2][0] = cos(dec) * cos(ra);  ax[2][1] = cos(dec) * sin(ra);  ax[2][2] = sin(dec);
+        };
+        double a0[3][3], a1[3][3];
+        axes(t->ra0, t->dec0, a0);
+        axes(t->ra1, t->dec1, a1);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                f.R[3 * i + j] = a1[i][0] * a0[j][0] + a1[i][1] * a0[j][1] + a1[i][2] * a0[j][2];
+        f.l = f.R[6];
+        f.m = f.R[7];
+    } else {
+        f.l = t->l;
+        f.m = t->m;
+    }
+    return f;
+}
+
 bool check_grid(const vista_grid_desc* g, std::string* why) {
     if (!g) { *why = "grid descriptor is NULL"; return false; }
     if (g->nu < 1 || g->nv < 1 || g->nu > 65535 || g->nv > 65535) {
@@ -68,7 +93,17 @@ bool check_target(const vista_grid_desc* g, const vista_target* t, std::string* 
     if (t->nrow > 0 && (!t->uvw || !t->vis || !t->weight)) { *why = "uvw, vis and weight are required"; return false; }
     if (t->nchan == 1 && !t->chan_width) { *why = "nchan == 1 needs chan_width"; return false; }
     if (!(t->z > -1.0 && isfinite(t->z))) { *why = fmt("z must be finite and > -1 (got %g)", t->z); return false; }
-    if (!(isfinite(t->l) && isfinite(t->m) && t->l * t->l + t->m * t->m < 1.0)) {
+    if (t->rotate_uvw != 0 && t->rotate_uvw != 1) { *why = "rotate_uvw must be 0 or 1"; return false; }
+    if (t->rotate_uvw) {
+        if (!(isfinite(t->ra0) && isfinite(t->dec0) && isfinite(t->ra1) && isfinite(t->dec1))) {
+            *why = "ra0, dec0, ra1, dec1 must be finite";
+            return false;
+        }
+        if (!(make_frame(t).R[8] > 0.0)) {
+            *why = "the stacking position must lie in the phase centre's front hemisphere";
+            return false;
+        }
+    } else if (!(isfinite(t->l) && isfinite(t->m) && t->l * t->l + t->m * t->m < 1.0)) {
         *why = fmt("need l*l + m*m < 1 (got l=%g, m=%g)", t->l, t->m);
         return false;
     }
@@ -111,7 +146,8 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
     ChannelPlan p;
     const int32_t n = t->nchan;
     const double opz = 1.0 + t->z;
-    const double lm2 = t->l * t->l + t->m * t->m;
+    p.frame = make_frame(t);
+    const double lm2 = p.frame.l * p.frame.l + p.frame.m * p.frame.m;
     p.nm1 = -lm2 / (1.0 + sqrt(1.0 - lm2));
     p.chan.resize(n);
     p.f1.assign(n, 0.f);
@@ -214,6 +250,7 @@ RebinPlan plan_rebin(const vista_target* t, double freq_lo, double dfreq, int32_
     const ChannelPlan p = plan_target(&g, t);
     RebinPlan r;
     r.nm1 = p.nm1;
+    r.frame = p.frame;
     r.a.resize(t->nchan);
     for (int32_t k = 0; k < t->nchan; ++k) r.a[k] = p.chan[k].a;
     r.jstart.assign((size_t)nout + 1, 0);

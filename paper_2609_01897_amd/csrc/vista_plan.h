@@ -11,6 +11,16 @@
 
 namespace vista {
 
+// Eq. 1's rotation of a target: R (row-major) from the phase centre's uvw axes to the
+// stacking position's, and the direction cosines (l, m) the Eq. 2 shift uses (the given
+// ones without the rotation, R then the identity).
+struct Frame {
+    int32_t rotate = 0;
+    double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double l = 0.0, m = 0.0;
+};
+Frame make_frame(const vista_target* t);
+
 // Per-target rest-frame plan (Sec. 3.1 and Eq. 3-4), computed in FP64 on the host.
 struct ChannelPlan {
     std::vector<DevChan> chan;     // [nchan]
@@ -23,6 +33,7 @@ struct ChannelPlan {
     int32_t nphase = 1;            // channel distance with disjoint rest-channel sets
     int64_t n_inband = 0;          // channels with nj > 0
     double nm1 = 0.0;              // n - 1 for (l, m)
+    Frame frame;                   // Eq. 1's rotation and the (l, m) in use
 };
 
 // Validation; on failure returns false and fills *why.
@@ -56,6 +67,7 @@ struct RebinPlan {
     std::vector<int32_t> ek;
     std::vector<float> ef;
     double nm1 = 0.0;
+    Frame frame;
 };
 RebinPlan plan_rebin(const vista_target* t, double freq_lo, double dfreq, int32_t nout);
 

@@ -117,11 +117,16 @@ __global__ void __launch_bounds__(256) k_rebin_rows(const RebinTarget* __restric
                 r[q] = (int64_t)B.row0 + (live[q] ? rr : rb);
                 const double U = uvw[3 * r[q]], V = uvw[3 * r[q] + 1], W = uvw[3 * r[q] + 2];
                 trow[q] = U * T.l + V * T.m + W * T.nm1;     // Eq. 2 turns per unit a_k
-                if (T.out_uvw && j == 0 && live[q]) {         // Eq. 1 without the rotation
+                if (T.out_uvw && j == 0 && live[q]) {         // Eq. 1: R (u, v, w) / (1 + z)
                     VISTA_GLOBAL double* ou = (VISTA_GLOBAL double*)T.out_uvw;
-                    ou[3 * r[q]] = U / T.opz;
-                    ou[3 * r[q] + 1] = V / T.opz;
-                    ou[3 * r[q] + 2] = W / T.opz;
+                    if (T.rotate) {
+                        for (int i = 0; i < 3; ++i)
+                            ou[3 * r[q] + i] = (T.R[3 * i] * U + T.R[3 * i + 1] * V + T.R[3 * i + 2] * W) / T.opz;
+                    } else {
+                        ou[3 * r[q]] = U / T.opz;
+                        ou[3 * r[q] + 1] = V / T.opz;
+                        ou[3 * r[q] + 2] = W / T.opz;
+                    }
                 }
             }
             float nr[kRowsInFlight<NPOL>][NPOL], ni[kRowsInFlight<NPOL>][NPOL], dn[kRowsInFlight<NPOL>][NPOL];

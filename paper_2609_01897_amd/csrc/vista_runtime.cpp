@@ -353,7 +353,9 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
             T.kin_hi = ht->plan.kin_hi;
             T.nphase = ht->plan.nphase;
             T.nblocks = S.nblocks;
-            T.l = ht->t.l; T.m = ht->t.m; T.nm1 = ht->plan.nm1;
+            T.l = ht->plan.frame.l; T.m = ht->plan.frame.m; T.nm1 = ht->plan.nm1;
+            T.rotate = ht->plan.frame.rotate;
+            for (int q = 0; q < 6; ++q) T.rot[q] = ht->plan.frame.R[q];
             T.chan0 = (int32_t)chan_all.size();
             chan_all.insert(chan_all.end(), ht->plan.chan.begin(), ht->plan.chan.end());
             f1_all.insert(f1_all.end(), ht->plan.f1.begin(), ht->plan.f1.end());
@@ -1004,6 +1006,8 @@ int vista_debug_indices(const vista_grid_desc* g, const vista_target* t, void* h
         DevTarget T;
         memset(&T, 0, sizeof(T));
         T.uvw = duvw; T.chan = dch; T.nrow = t->nrow; T.nchan = t->nchan; T.npol = t->npol;
+        T.rotate = h.plan.frame.rotate;
+        for (int q = 0; q < 6; ++q) T.rot[q] = h.plan.frame.R[q];
         DevStack S;
         memset(&S, 0, sizeof(S));
         S.nu = g->nu; S.nv = g->nv; S.nchan = g->nchan; S.inv_du = 1.0 / g->du; S.inv_dv = 1.0 / g->dv;
@@ -1040,7 +1044,7 @@ int vista_debug_rotate(const vista_grid_desc* g, const vista_target* t, void* hi
         DevTarget T;
         memset(&T, 0, sizeof(T));
         T.uvw = t->uvw; T.vis = (const float2*)t->vis; T.chan = dch; T.nrow = t->nrow; T.nchan = t->nchan;
-        T.npol = t->npol; T.l = t->l; T.m = t->m; T.nm1 = h.plan.nm1;
+        T.npol = t->npol; T.l = h.plan.frame.l; T.m = h.plan.frame.m; T.nm1 = h.plan.nm1;
         DevTarget* dT = mem.alloc_n<DevTarget>(1);
         VISTA_HIP(hipMemcpyAsync(dT, &T, sizeof(T), hipMemcpyHostToDevice, stream));
         check_launch(launch_debug_rotate(dT, (float2*)out, t->nrow, t->nchan, t->npol,
@@ -1156,7 +1160,9 @@ int vista_rebin_rows(const vista_rebin_desc* d, int32_t n, const vista_target* t
             T.ek = (const int32_t*)(darena + off[4 * i + 2]);
             T.ef = (const float*)(darena + off[4 * i + 3]);
             T.nrow = t[i].nrow; T.nchan = t[i].nchan; T.npol = t[i].npol; T.nout = d->nout;
-            T.l = t[i].l; T.m = t[i].m; T.nm1 = plans[i].nm1; T.opz = 1.0 + t[i].z;
+            T.l = plans[i].frame.l; T.m = plans[i].frame.m; T.nm1 = plans[i].nm1; T.opz = 1.0 + t[i].z;
+            T.rotate = plans[i].frame.rotate;
+            for (int q = 0; q < 9; ++q) T.R[q] = plans[i].frame.R[q];
         }
         // row blocks, grouped by polarisation count: a workgroup's thread groups (256 /
         // min(nout, 256) of them) take 16 rows each

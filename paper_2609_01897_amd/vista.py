@@ -39,7 +39,9 @@ class TargetDesc(C.Structure):
     _fields_ = [("nrow", C.c_int64), ("nchan", C.c_int32), ("npol", C.c_int32), ("uvw", C.c_void_p),
                 ("vis", C.c_void_p), ("weight", C.c_void_p), ("flag", C.c_void_p),
                 ("chan_freq", C.c_void_p), ("chan_width", C.c_void_p), ("l", C.c_double),
-                ("m", C.c_double), ("z", C.c_double), ("weight_per_chan", C.c_int32), ("mem", C.c_int32)]
+                ("m", C.c_double), ("z", C.c_double), ("weight_per_chan", C.c_int32), ("mem", C.c_int32),
+                ("rotate_uvw", C.c_int32), ("ra0", C.c_double), ("dec0", C.c_double), ("ra1", C.c_double),
+                ("dec1", C.c_double)]
 
 
 class Output(C.Structure):
@@ -164,7 +166,9 @@ def target_desc(t, keep: list) -> TargetDesc:
     nrow = int(t.uvw.shape[0])
     return TargetDesc(nrow, int(freq.shape[0]), int(t.vis.shape[2]), _ptr(t.uvw), _ptr(t.vis), _ptr(t.weight),
                       _ptr(t.flag), freq.ctypes.data, None if width is None else width.ctypes.data,
-                      float(t.l), float(t.m), float(t.z), int(bool(t.weight_per_chan)), _mem_of(t.vis))
+                      float(t.l), float(t.m), float(t.z), int(bool(t.weight_per_chan)), _mem_of(t.vis),
+                      int(bool(getattr(t, "rotate_uvw", False))), float(getattr(t, "ra0", 0.0)),
+                      float(getattr(t, "dec0", 0.0)), float(getattr(t, "ra1", 0.0)), float(getattr(t, "dec1", 0.0)))
 
 
 def current_stream():

@@ -209,3 +209,25 @@ def test_rebin_validation():
     assert rc == vista.VISTA_E_ARG
     rc = vista.lib().vista_rebin_rows(C.byref(d), 0, None, None, None, None, None)   # nothing to do
     assert rc == vista.VISTA_OK
+
+
+def test_rotation_fields_validated():
+    """rotate_uvw must be 0 or 1; with it, the angles must be finite and the stacking
+    position in the phase centre's front hemisphere (checked before any device work)."""
+    import dataclasses
+    import math
+    cfg = synth.config("tiny")
+    g = synth.make_grid(cfg)
+    t = synth.make_target(cfg, 0)
+    ok = dataclasses.replace(t, rotate_uvw=True)
+    vista.rebin_window(ok, 8, g["dfreq"], cfg.line_rest)
+    for bad in (dataclasses.replace(t, rotate_uvw=True, dec1=float("nan")),
+                dataclasses.replace(t, rotate_uvw=True, ra1=t.ra0 + math.pi, dec1=-t.dec0)):
+        with pytest.raises(vista.VistaError) as e:
+            vista.rebin_window(bad, 8, g["dfreq"], cfg.line_rest)
+        assert e.value.code == vista.VISTA_E_ARG
+    d = vista.target_desc(t, [])
+    d.rotate_uvw = 2
+    lo = C.c_double()
+    rd = vista.RebinDesc(8, g["dfreq"], cfg.line_rest)
+    assert vista.lib().vista_rebin_window(C.byref(rd), C.byref(d), C.byref(lo)) == vista.VISTA_E_ARG
