@@ -212,6 +212,37 @@ def streamed_leg():
     }
 
 
+def rotated_leg(targets, grid, flags, tuning, out, steps=3):
+    """The same step with Eq. 1's rotation switched on for every target (uv cells from the
+    rotated baseline): whole-step time and the accumulation kernel's hipEvent time."""
+    import dataclasses
+    import torch
+    from paper_2609_01897_amd import vista
+    rot = [dataclasses.replace(t, rotate_uvw=True) for t in targets]
+
+    def step():
+        s = vista.Stack(grid, flags=flags, tuning=tuning)
+        for t in rot:
+            s.add(t)
+        st = s.finalize(out)
+        tim = s.timings()
+        s.close()
+        return st, tim
+
+    step()
+    torch.cuda.synchronize()
+    acc = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, tim = step()
+        acc.append(tim["accum_ms"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    log("rotated: step %.2f ms, accumulate %.2f ms, %d outside uv" % (ms, sum(acc) / len(acc), st["n_outside_uv"]))
+    return {"ms_per_step": ms, "accumulate_ms": sum(acc) / len(acc), "records": tim["n_records"],
+            "n_outside_uv": st["n_outside_uv"]}
+
+
 REBIN_NOUT = 480
 
 
@@ -352,6 +383,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed leg")
     ap.add_argument("--no-rebinned", action="store_true", help="skip the per-row rebinned leg")
+    ap.add_argument("--no-rotated", action="store_true", help="skip the step with Eq. 1's rotation on")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     ap.add_argument("--tuning", default="", help="tile_u,tile_v,jblock,waves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -478,6 +510,8 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on %d targets" % args.cpu_targets)
         res["cpu_baseline"] = cpu_baseline(targets, grid, args.cpu_targets)
+    if not args.no_rotated:
+        res["rotated"] = rotated_leg(targets, grid, flags, tuning, out)
     del out
     torch.cuda.empty_cache()
     if not args.no_rebinned:
