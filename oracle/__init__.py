@@ -56,6 +56,8 @@ def lib():
                                                 C.POINTER(C.c_double)]
         _lib.ora_check.argtypes = [C.POINTER(_Grid), i32, C.POINTER(_Target)]
         _lib.ora_frame_matrix.argtypes = [C.POINTER(_Target), p, p]
+        _lib.ora_image.argtypes = [i32, i32, i32, p, p, p, p]
+        _lib.ora_image_pixels.argtypes = [i32, i32, p, p, i32, p, p, p]
         _lib.ora_rebin_window.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, C.POINTER(C.c_double)]
         _lib.ora_rebin_rows.argtypes = [C.POINTER(_Target), C.c_double, C.c_double, i32, p, p, p, p]
     return _lib
@@ -237,3 +239,32 @@ def rotation(target) -> tuple:
     if lib().ora_frame_matrix(C.byref(t), R.ctypes.data, lm.ctypes.data):
         raise ValueError("oracle rejected the target")
     return R.reshape(3, 3), float(lm[0]), float(lm[1]), float(lm[2])
+
+
+def image(S, W, beam: bool = False):
+    """Dirty image of every channel of a stacked grid by direct Fourier inversion
+    (``ora_image``): S complex [nchan, nv, nu], W [nchan, nv, nu] -> image float64
+    [nchan, nv, nu] (and the dirty beam)."""
+    S = np.ascontiguousarray(np.asarray(S, np.complex128))
+    W = np.ascontiguousarray(np.asarray(W, np.float64))
+    nchan, nv, nu = W.shape
+    img = np.zeros(W.shape, np.float64)
+    bm = np.zeros(W.shape, np.float64) if beam else None
+    if lib().ora_image(nu, nv, nchan, S.ctypes.data, W.ctypes.data, img.ctypes.data,
+                       None if bm is None else bm.ctypes.data):
+        raise ValueError("oracle rejected the inputs")
+    return (img, bm) if beam else img
+
+
+def image_pixels(S, W, q, p):
+    """Selected pixels (q[i], p[i]) of one channel's dirty image (``ora_image_pixels``)."""
+    S = np.ascontiguousarray(np.asarray(S, np.complex128))
+    W = np.ascontiguousarray(np.asarray(W, np.float64))
+    q = np.ascontiguousarray(q, np.int32)
+    p = np.ascontiguousarray(p, np.int32)
+    nv, nu = W.shape
+    out = np.zeros(q.shape[0], np.float64)
+    if lib().ora_image_pixels(nu, nv, S.ctypes.data, W.ctypes.data, int(q.shape[0]), q.ctypes.data,
+                              p.ctypes.data, out.ctypes.data):
+        raise ValueError("oracle rejected the inputs")
+    return out

@@ -603,3 +603,71 @@ int ora_frame_matrix(const ora_target* t, double* R, double* lm_nm1) {
     lm_nm1[2] = f.nm1;
     return 0;
 }
+
+/* ------------------------------------------------------------------- dirty image */
+
+/* The dirty image of one rest channel of a stacked grid by direct Fourier inversion (the
+ * imaging the paper's outlook, Sec. 3.4, would do with an FFT on the stacked product):
+ *   I(q, p) = Re sum_{iv, iu} S[iv][iu] exp(+2 pi i (u x_p + v y_q)) / W_total,
+ * with u = (iu - nu/2) du, v = (iv - nv/2) dv, x_p = (p - nu/2) / (nu du) and
+ * y_q = (q - nv/2) / (nv dv): the phase is 2 pi ((iu - nu/2)(p - nu/2) / nu +
+ * (iv - nv/2)(q - nv/2) / nv), independent of du and dv; its integer numerators are
+ * reduced modulo nu and nv (an exact identity) before the trigonometry.  W_total is the
+ * channel's summed weight; the image is 0 where it is 0.  The gridded data hold each
+ * measured baseline once, so the real part is the dirty image of a real sky.
+ * S [nv][nu][2], W [nv][nu]. */
+static double ora_pixel(int32_t nu, int32_t nv, const double* S, double wt, int32_t q, int32_t p) {
+    if (!(wt > 0.0)) return 0.0;
+    const int64_t cu = nu / 2, cv = nv / 2;
+    double acc = 0.0;
+    for (int32_t iv = 0; iv < nv; ++iv) {
+        const int64_t av = (((int64_t)(iv - cv) * (q - cv)) % nv + nv) % nv;
+        for (int32_t iu = 0; iu < nu; ++iu) {
+            const double sr = S[2 * ((size_t)iv * nu + iu)], si = S[2 * ((size_t)iv * nu + iu) + 1];
+            if (sr == 0.0 && si == 0.0) continue;
+            const int64_t au = (((int64_t)(iu - cu) * (p - cu)) % nu + nu) % nu;
+            const double ph = 2.0 * ORA_PI * ((double)au / (double)nu + (double)av / (double)nv);
+            acc += sr * cos(ph) - si * sin(ph);
+        }
+    }
+    return acc / wt;
+}
+
+/* Every pixel of every channel: S [nchan][nv][nu][2], W [nchan][nv][nu]; img and beam
+ * [nchan][nv][nu] (either may be NULL; the beam is the same inversion of W). */
+int ora_image(int32_t nu, int32_t nv, int32_t nchan, const double* S, const double* W, double* img, double* beam) {
+    if (nu < 1 || nv < 1 || nchan < 0) return -1;
+    const size_t plane = (size_t)nu * nv;
+    double* wre = (double*)malloc(sizeof(double) * 2 * plane);
+    if (!wre) return -3;
+    for (int32_t j = 0; j < nchan; ++j) {
+        const double* Sj = S + 2 * plane * j;
+        const double* Wj = W + plane * j;
+        double wt = 0.0;
+        for (size_t c = 0; c < plane; ++c) wt += Wj[c];
+        for (size_t c = 0; c < plane; ++c) { wre[2 * c] = Wj[c]; wre[2 * c + 1] = 0.0; }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int32_t q = 0; q < nv; ++q)
+            for (int32_t p = 0; p < nu; ++p) {
+                if (img) img[plane * j + (size_t)q * nu + p] = ora_pixel(nu, nv, Sj, wt, q, p);
+                if (beam) beam[plane * j + (size_t)q * nu + p] = ora_pixel(nu, nv, wre, wt, q, p);
+            }
+    }
+    free(wre);
+    return 0;
+}
+
+/* Selected pixels (q[i], p[i]) of one channel (S [nv][nu][2], W [nv][nu]). */
+int ora_image_pixels(int32_t nu, int32_t nv, const double* S, const double* W, int32_t n, const int32_t* q,
+                     const int32_t* p, double* out) {
+    if (nu < 1 || nv < 1 || n < 0) return -1;
+    double wt = 0.0;
+    for (size_t c = 0; c < (size_t)nu * nv; ++c) wt += W[c];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int32_t i = 0; i < n; ++i) out[i] = ora_pixel(nu, nv, S, wt, q[i], p[i]);
+    return 0;
+}
