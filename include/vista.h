@@ -266,6 +266,25 @@ int vista_rebin_window(const vista_rebin_desc* d, const vista_target* t, double*
 int vista_rebin_rows(const vista_rebin_desc* d, int32_t n_targets, const vista_target* t,
                      const vista_rebin_output* o, void* hip_stream, double* freq_lo, vista_timings* tim);
 
+/* ---- Dirty image of a stacked grid (the imaging step on the stacked product, Sec. 3.4) --
+ *
+ * For every rest channel j of a stacked grid (the outputs of vista_stack_finalize), the
+ * dirty image by an inverse 2-D FFT:
+ *   image[j][q][p] = Re sum_{iv, iu} S_j[iv][iu] exp(+2 pi i (u x_p + v y_q)) / W_j,
+ * u = (iu - nu/2) du, v = (iv - nv/2) dv, x_p = (p - nu/2) / (nu du), y_q = (q - nv/2) / (nv dv)
+ * (pixel spacing 1 / (n cell), pixel nu/2, nv/2 the stacking position), S = sum_wvis,
+ * W_j = the channel's summed weight (sum over the channel of sum_w, in FP64); a channel
+ * without weight images to 0.  The gridded data hold each measured baseline once, so the
+ * real part is the dirty image of a real sky.  beam (may be NULL): the same transform of
+ * sum_w (the dirty beam, 1 at the centre pixel).  Only nu, nv, nchan of g are read: nu and
+ * nv must be powers of two in 2..4096, nchan in 1..65535.  All arrays are device memory,
+ * [nchan][nv][nu]: sum_wvis complex64 (8-byte aligned), sum_w, image and beam float
+ * (4-byte aligned).  Stream-ordered on hip_stream; returns when the images are written.
+ * tim (may be NULL): device time of the imaging kernels in accum_ms.  Errors: ARG, NOMEM,
+ * HIP. */
+int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image, float* beam,
+                void* hip_stream, vista_timings* tim);
+
 /* Per (row, channel) indices the GPU computes for one target, for bit-exact checks:
  * iu, iv (the nearest cell before the bounds test, INT32_MIN when not representable),
  * j0 (first rest channel of the channel's overlap set, -1 if empty) and nj (its size).

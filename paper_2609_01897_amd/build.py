@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC_DIR = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libvista.so")
-SOURCES = ["vista_kernels.hip", "vista_accum.hip", "vista_sort.hip", "vista_rebin.hip", "vista_plan.cpp",
-           "vista_runtime.cpp"]
+SOURCES = ["vista_kernels.hip", "vista_accum.hip", "vista_sort.hip", "vista_rebin.hip", "vista_image.hip",
+           "vista_plan.cpp", "vista_runtime.cpp"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -208,6 +208,12 @@ hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint
 // Launch shapes the kernels are built for, in order (atomic: the packed kernel's list).
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
+// Dirty image of every channel of a stacked grid (vista_image.hip): nu, nv powers of two
+// in 2..4096; tmp holds image_temp_bytes(nu, nv, nchan), wsum nchan doubles; beam may be
+// null.
+size_t image_temp_bytes(int nu, int nv, int nchan);
+hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, float* beam, int nu, int nv,
+                        int nchan, float2* tmp, double* wsum, hipStream_t stream);
 // The per-row rebinning (vista_rebin.hip) over `nblocks` row blocks; every target of the
 // launch has `npol` polarisations (1, 2 or 4).
 hipError_t launch_rebin_rows(const RebinTarget* targets, const RebinBlock* blocks, int64_t nblocks, int npol,

@@ -1207,6 +1207,47 @@ int vista_rebin_rows(const vista_rebin_desc* d, int32_t n, const vista_target* t
     });
 }
 
+// -------------------------------------------------------------------- dirty image
+
+int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image, float* beam,
+                void* hip_stream, vista_timings* tim) {
+    if (!g) return fail(VISTA_E_ARG, "grid descriptor is NULL");
+    auto pow2 = [](int32_t n) { return n >= 2 && n <= 4096 && (n & (n - 1)) == 0; };
+    if (!pow2(g->nu) || !pow2(g->nv)) return fail(VISTA_E_ARG, "vista_image needs nu and nv powers of two in 2..4096");
+    if (g->nchan < 1 || g->nchan > 65535) return fail(VISTA_E_ARG, "vista_image needs nchan in 1..65535");
+    if (!sum_wvis || !sum_w || !image) return fail(VISTA_E_ARG, "sum_wvis, sum_w and image are required");
+    if (((uintptr_t)sum_wvis % 8) || ((uintptr_t)sum_w % 4) || ((uintptr_t)image % 4) || ((uintptr_t)beam % 4))
+        return fail(VISTA_E_ARG, "arrays are not aligned to their element size");
+    for (const void* ptr : {(const void*)sum_wvis, (const void*)sum_w, (const void*)image, (const void*)beam}) {
+        if (!ptr) continue;
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(VISTA_E_ARG, "vista_image needs device memory");
+        }
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    return guarded(nullptr, [&]() -> int {
+        Events ev;
+        DevMem mem(stream);
+        float2* tmp = (float2*)mem.alloc(image_temp_bytes(g->nu, g->nv, g->nchan));
+        double* wsum = mem.alloc_n<double>(g->nchan);
+        VISTA_HIP(hipEventRecord(ev.e[0], stream));
+        check_launch(launch_image(sum_wvis, sum_w, image, beam, g->nu, g->nv, g->nchan, tmp, wsum, stream), "image");
+        VISTA_HIP(hipEventRecord(ev.e[1], stream));
+        VISTA_HIP(hipStreamSynchronize(stream));
+        mem.release();
+        VISTA_HIP(hipStreamSynchronize(stream));
+        if (tim) {
+            memset(tim, 0, sizeof(*tim));
+            tim->accum_ms = ev.ms(0, 1);
+            tim->total_ms = tim->accum_ms;
+            tim->n_accum_launches = beam ? 5 : 3;
+        }
+        return VISTA_OK;
+    });
+}
+
 // ---------------------------------------------------------------------------- batch
 
 int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_stream, vista_batch** out) {

@@ -102,6 +102,8 @@ SYMBOLS = {
     "vista_debug_rotate": ([C.POINTER(GridDesc), C.POINTER(TargetDesc), C.c_void_p, C.c_void_p], C.c_int),
     "vista_debug_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "vista_batch_set_output": ([C.c_void_p, C.c_int32, C.POINTER(Output)], C.c_int),
+    "vista_image": ([C.POINTER(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.POINTER(Timings)], C.c_int),
     "vista_rebin_window": ([C.POINTER(RebinDesc), C.POINTER(TargetDesc), C.POINTER(C.c_double)], C.c_int),
     "vista_rebin_rows": ([C.POINTER(RebinDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.POINTER(Timings)], C.c_int),
@@ -427,3 +429,17 @@ def rebin_rows(targets, nout: int, dfreq: float, central_freq: float, outs=None,
     _check(lib().vista_rebin_rows(C.byref(d), n, C.cast(tds, C.c_void_p), C.cast(ods, C.c_void_p), s,
                                   C.cast(lo, C.c_void_p), C.byref(tim)))
     return outs, [lo[i] for i in range(n)], tim.as_dict()
+
+
+def image(grid: dict, sum_wvis, sum_w, beam: bool = False, out=None, stream=None):
+    """Dirty image of every rest channel of a stacked grid (``vista_image``): device tensors
+    sum_wvis complex64 and sum_w float32 [nchan, nv, nu]; returns (image, beam or None,
+    timings dict)."""
+    import torch
+    img = torch.empty(sum_w.shape, dtype=torch.float32, device=sum_w.device) if out is None else out
+    bm = torch.empty_like(img) if beam else None
+    tim = Timings()
+    s = current_stream() if stream is None else stream
+    _check(lib().vista_image(C.byref(grid_desc(grid)), _ptr(sum_wvis), _ptr(sum_w), _ptr(img), _ptr(bm), s,
+                             C.byref(tim)))
+    return img, bm, tim.as_dict()

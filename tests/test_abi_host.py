@@ -231,3 +231,22 @@ def test_rotation_fields_validated():
     lo = C.c_double()
     rd = vista.RebinDesc(8, g["dfreq"], cfg.line_rest)
     assert vista.lib().vista_rebin_window(C.byref(rd), C.byref(d), C.byref(lo)) == vista.VISTA_E_ARG
+
+
+def test_image_validation():
+    """Sizes that are not powers of two in 2..4096, missing arrays and host memory are
+    refused before any device work."""
+    g = dict(nu=64, nv=64, du=1.0, dv=1.0, nchan=2, freq_lo=1e9, dfreq=1e6)
+    S = np.zeros((2, 64, 64), np.complex64)
+    W = np.zeros((2, 64, 64), np.float32)
+    img = np.zeros((2, 64, 64), np.float32)
+    L = vista.lib()
+    for bad in (dict(g, nu=48), dict(g, nv=1), dict(g, nu=8192), dict(g, nchan=0)):
+        rc = L.vista_image(C.byref(vista.grid_desc(bad)), S.ctypes.data, W.ctypes.data, img.ctypes.data, None,
+                           None, None)
+        assert rc == vista.VISTA_E_ARG
+    rc = L.vista_image(C.byref(vista.grid_desc(g)), None, W.ctypes.data, img.ctypes.data, None, None, None)
+    assert rc == vista.VISTA_E_ARG
+    rc = L.vista_image(C.byref(vista.grid_desc(g)), S.ctypes.data, W.ctypes.data, img.ctypes.data, None, None,
+                       None)
+    assert rc == vista.VISTA_E_ARG and "device" in vista.lib().vista_last_error().decode()
