@@ -190,6 +190,13 @@ int vista_stack_timings(const vista_stack* s, vista_timings* t);
 /* Release everything the stack owns.  Always succeeds for a non-NULL handle. */
 int vista_stack_destroy(vista_stack* s);
 
+/* Stacks keep a per-thread launch workspace between calls -- row contexts, binning records,
+ * sort scratch and the work list, sized by the largest launch seen (about 80 B per row and
+ * 50 B per binning record), for at most two launch shapes -- so that consecutive stacks on
+ * one thread neither allocate nor free device memory.  This frees the calling thread's
+ * workspace (the next stack allocates it again).  It waits for the device.  Errors: HIP. */
+int vista_release_workspace(void);
+
 /* Batched form: n_stacks independent stacks (each with its own grid g[i]) run in one
  * persistent, hipGraph-replayed launch sequence per wave.  Targets are recorded by
  * vista_batch_add_target; vista_batch_run stacks them all.  When the inputs exceed

@@ -83,25 +83,34 @@ static void pool_setup_once() {
 }
 
 // Stream-ordered device buffers owned by one launch or handle.
+// Persistent buffers (a thread's cached launch workspace, which outlives any one stream)
+// are plain device allocations instead: every call that uses them synchronises its stream
+// before returning, so they are idle between calls, and freeing them waits for the device.
 class DevMem {
   public:
-    explicit DevMem(hipStream_t s) : s_(s) {}
+    explicit DevMem(hipStream_t s, bool persistent = false) : s_(s), persistent_(persistent) {}
     DevMem(const DevMem&) = delete;
     ~DevMem() { release(); }
+    void set_stream(hipStream_t s) { s_ = s; }
     void* alloc(size_t n) {
         if (n == 0) n = 16;
         Env e = read_env();
         if (e.fail_alloc) throw NoMem{"injected allocation failure"};
         if (e.mem_limit >= 0 && g_dev_bytes.load() + (int64_t)n > e.mem_limit)
             throw NoMem{"device memory limit reached"};
-        pool_setup_once();
         void* p = nullptr;
-        hipError_t r = hipMallocAsync(&p, n, s_);
+        hipError_t r;
+        if (persistent_) {
+            r = hipMalloc(&p, n);
+        } else {
+            pool_setup_once();
+            r = hipMallocAsync(&p, n, s_);
+        }
         if (r == hipErrorOutOfMemory) {
             (void)hipGetLastError();
             throw NoMem{"device allocation of " + std::to_string(n) + " bytes failed"};
         }
-        if (r != hipSuccess) throw HipFail{r, "hipMallocAsync"};
+        if (r != hipSuccess) throw HipFail{r, persistent_ ? "hipMalloc" : "hipMallocAsync"};
         g_dev_bytes += (int64_t)n;
         ptrs_.push_back({p, n});
         return p;
@@ -110,7 +119,8 @@ class DevMem {
     T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
     void release() {
         for (auto& q : ptrs_) {
-            (void)hipFreeAsync(q.first, s_);
+            if (persistent_) (void)hipFree(q.first);
+            else (void)hipFreeAsync(q.first, s_);
             g_dev_bytes -= (int64_t)q.second;
         }
         ptrs_.clear();
@@ -118,6 +128,7 @@ class DevMem {
 
   private:
     hipStream_t s_;
+    bool persistent_;
     std::vector<std::pair<void*, size_t>> ptrs_;
 };
 
@@ -429,8 +440,8 @@ struct Capacity {
 // hipGraph and replayed for every launch that fits the capacity.
 class Launcher {
   public:
-    Launcher(hipStream_t s, const Tuning& tu, uint32_t flags)
-        : s_(s), tu_(tu), mem_(s), recmem_(s) {
+    Launcher(hipStream_t s, const Tuning& tu, uint32_t flags, bool persistent = false)
+        : s_(s), tu_(tu), mem_(s, persistent), recmem_(s, persistent) {
         mode_ = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
         kahan_ = (flags & VISTA_F_KAHAN) ? 1 : 0;
         phase_fp32_ = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
@@ -438,6 +449,12 @@ class Launcher {
         if (!shape_ok(tu, flags)) throw HipFail{hipErrorInvalidValue, "unsupported launch shape (tile/jblock/waves)"};
     }
     ~Launcher() { drop_graph(); }
+    // Launch on another stream (a cached launcher between calls; no graph is captured then).
+    void set_stream(hipStream_t s) {
+        s_ = s;
+        mem_.set_stream(s);
+        recmem_.set_stream(s);
+    }
     int jsub() const { return jsub_; }
 
     // Grow the buffers to cover c (record buffers separately: they are sized last).
@@ -689,16 +706,92 @@ static void collect_stats(std::vector<StackJob>& jobs, const std::vector<unsigne
 
 // Stack every job in one eager pass (the plain form: one launch sequence).  All output
 // cells of every job are written.
+// A thread's launch workspaces: the launcher (its fixed and record buffers grow to the
+// largest launch seen and are then reused), events and a statistics buffer, per device,
+// launch shape and accumulation mode, so that consecutive stacks neither allocate nor free
+// device memory.  At most two are kept (the autotuner cycles through shapes); they are
+// freed by vista_release_workspace, or when evicted.
+struct Workspace {
+    int device = 0;
+    Tuning tu;
+    uint32_t mode_flags = 0;
+    std::unique_ptr<Launcher> ln;
+    std::unique_ptr<Events> ev;
+    std::unique_ptr<DevMem> stats_mem;
+    unsigned long long* stats = nullptr;
+    size_t stats_cap = 0;
+    unsigned long long* stats_for(size_t n) {
+        if (n > stats_cap) {
+            stats_mem->release();
+            stats_cap = std::max<size_t>(n, 64);
+            stats = stats_mem->alloc_n<unsigned long long>(stats_cap);
+        }
+        return stats;
+    }
+};
+static thread_local std::vector<std::unique_ptr<Workspace>> t_workspaces;
+constexpr size_t kMaxWorkspaces = 2;
+
+static Workspace& workspace_for(hipStream_t stream, const Tuning& tu, uint32_t flags) {
+    int dev = 0;
+    VISTA_HIP(hipGetDevice(&dev));
+    const uint32_t mf = flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN | VISTA_F_PHASE_FP32);
+    for (size_t i = 0; i < t_workspaces.size(); ++i) {
+        Workspace& w = *t_workspaces[i];
+        if (w.device == dev && w.mode_flags == mf && w.tu.tu == tu.tu && w.tu.tv == tu.tv && w.tu.jc == tu.jc &&
+            w.tu.waves == tu.waves && w.tu.wg_per_cu == tu.wg_per_cu) {
+            std::unique_ptr<Workspace> keep = std::move(t_workspaces[i]);     // most recent last
+            t_workspaces.erase(t_workspaces.begin() + i);
+            t_workspaces.push_back(std::move(keep));
+            t_workspaces.back()->ln->set_stream(stream);
+            return *t_workspaces.back();
+        }
+    }
+    if (t_workspaces.size() >= kMaxWorkspaces) t_workspaces.erase(t_workspaces.begin());
+    auto w = std::make_unique<Workspace>();
+    w->device = dev;
+    w->tu = tu;
+    w->mode_flags = mf;
+    w->ln = std::make_unique<Launcher>(stream, tu, flags, true);
+    w->ev = std::make_unique<Events>();
+    w->stats_mem = std::make_unique<DevMem>(stream, true);
+    t_workspaces.push_back(std::move(w));
+    return *t_workspaces.back();
+}
+
+// Drop the workspace of (tu, flags) after a failure: its buffers' contents are unknown.
+static void drop_workspace(const Workspace* w) {
+    for (size_t i = 0; i < t_workspaces.size(); ++i)
+        if (t_workspaces[i].get() == w) {
+            t_workspaces.erase(t_workspaces.begin() + i);
+            return;
+        }
+}
+
+static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning& tu, hipStream_t stream,
+                        vista_timings* tim);
+
 static void run_jobs(std::vector<StackJob>& jobs, const Tuning& tu, uint32_t flags, hipStream_t stream,
                      vista_timings* tim) {
-    DevMem mem(stream);
-    Events ev;
-    Launcher ln(stream, tu, flags);
+    Workspace& ws = workspace_for(stream, tu, flags);
+    try {
+        run_jobs_in(ws, jobs, tu, stream, tim);
+    } catch (...) {
+        drop_workspace(&ws);
+        throw;
+    }
+}
+
+static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning& tu, hipStream_t stream,
+                        vista_timings* tim) {
+    DevMem mem(stream);                   // staging of host-memory targets only
+    Events& ev = *ws.ev;
+    Launcher& ln = *ws.ln;
     for (size_t s = 0; s < jobs.size(); ++s) jobs[s].index = (int32_t)s;
     HostLaunch h = build_launch(jobs, tu, ln.jsub());
     VISTA_HIP(hipEventRecord(ev.e[0], stream));
     make_resident(h, mem, stream);
-    unsigned long long* d_stats = mem.alloc_n<unsigned long long>(8 * jobs.size());
+    unsigned long long* d_stats = ws.stats_for(8 * jobs.size());
     check_launch(launch_fill_u64(d_stats, 0ull, 8 * (int64_t)jobs.size(), stream), "fill");
     ln.reserve(Capacity::of(h));
     const int64_t nrec = ln.prepare(h, d_stats);
@@ -880,6 +973,13 @@ static int guarded(int* state, F&& f) {
 extern "C" {
 
 const char* vista_last_error(void) { return g_err.c_str(); }
+
+int vista_release_workspace(void) {
+    return guarded(nullptr, [&]() -> int {
+        t_workspaces.clear();
+        return VISTA_OK;
+    });
+}
 
 const char* vista_version(void) { return "vista-mi355x 0.1 (gfx950)"; }
 

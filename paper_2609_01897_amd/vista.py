@@ -107,6 +107,7 @@ SYMBOLS = {
     "vista_rebin_window": ([C.POINTER(RebinDesc), C.POINTER(TargetDesc), C.POINTER(C.c_double)], C.c_int),
     "vista_rebin_rows": ([C.POINTER(RebinDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.POINTER(Timings)], C.c_int),
+    "vista_release_workspace": ([], C.c_int),
     "vista_last_error": ([], C.c_char_p),
     "vista_version": ([], C.c_char_p),
 }
@@ -443,3 +444,8 @@ def image(grid: dict, sum_wvis, sum_w, beam: bool = False, out=None, stream=None
     _check(lib().vista_image(C.byref(grid_desc(grid)), _ptr(sum_wvis), _ptr(sum_w), _ptr(img), _ptr(bm), s,
                              C.byref(tim)))
     return img, bm, tim.as_dict()
+
+
+def release_workspace():
+    """Free the calling thread's cached launch workspace (``vista_release_workspace``)."""
+    _check(lib().vista_release_workspace())

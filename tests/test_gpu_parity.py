@@ -294,3 +294,30 @@ def test_copy_kernel_copies_every_vector(n16):
     vista.debug_copy(dst, src)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+def test_workspace_reuse_across_sizes_shapes_and_streams():
+    """Consecutive stacks on one thread reuse the cached launch workspace: a larger launch
+    after a smaller one (buffers grow), a smaller one after it, another launch shape (a
+    second workspace), another stream, and a release in between all give the oracle's
+    result."""
+    small_cfg, big_cfg = synth.config("tiny"), synth.config("small")
+    cases = []
+    for cfg in (small_cfg, big_cfg, small_cfg):
+        hs, ds = targets_on_gpu(cfg)
+        cases.append((synth.make_grid(cfg), hs, ds))
+    for g, hs, ds in cases:
+        out, st = gpu_stack(g, ds)
+        compare(oracle.stack(g, hs), out, st=st)
+    g, hs, ds = cases[1]
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, ds, tuning=dict(tile_u=16, tile_v=2, jblock=160, waves=16))
+    compare(o, out, st=st)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out, st = vista.stack(g, ds)
+    s.synchronize()
+    compare(o, {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+    vista.release_workspace()
+    out, st = gpu_stack(g, ds)
+    compare(o, out, st=st)
