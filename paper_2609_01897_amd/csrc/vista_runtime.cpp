@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <exception>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -142,23 +144,66 @@ static void check_launch(hipError_t e, const char* what) {
 
 struct HostTarget {
     vista_target t{};
+    const vista_grid_desc* g = nullptr;   // the grid it is planned on (owned by its handle)
+    bool planned = false;
     ChannelPlan plan;
     std::vector<double> freq, width;
     std::vector<unsigned char> staging;   // VISTA_MEM_HOST data: uvw | vis | weight | flag
     uint64_t n_samples = 0, n_outside_band = 0;
 };
 
-static void copy_target(HostTarget& h, const vista_grid_desc* g, const vista_target* t) {
+static void finish_plan(HostTarget& h) {
+    h.plan = plan_target(h.g, &h.t);
+    h.n_outside_band = (uint64_t)h.t.nrow * h.t.npol * (uint64_t)(h.t.nchan - h.plan.n_inband);
+    h.planned = true;
+}
+
+// Plan every target not yet planned, on up to 16 host threads (the channel tables of many
+// targets are independent).
+static void plan_all(const std::vector<HostTarget*>& hs) {
+    std::vector<HostTarget*> todo;
+    for (HostTarget* h : hs)
+        if (!h->planned) todo.push_back(h);
+    if (todo.empty()) return;
+    const size_t nth = std::min<size_t>({todo.size() / 4 + 1, 16, std::max(1u, std::thread::hardware_concurrency())});
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> err(nth);
+    auto work = [&](size_t w) {
+        try {
+            for (size_t i; (i = next.fetch_add(1)) < todo.size();) finish_plan(*todo[i]);
+        } catch (...) {
+            err[w] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> pool;
+    for (size_t w = 1; w < nth; ++w) pool.emplace_back(work, w);
+    work(0);
+    for (auto& th : pool) th.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+// Copy the target's description (and, for host memory, its data).  Planning waits for the
+// launch, where all targets are planned together, unless the target could exceed the
+// packed channel table's overlap-set limit: that is known at once, from its widest
+// rest-frame channel, and such a target is planned (and checked) now.
+static void copy_target(HostTarget& h, const vista_grid_desc* g, const vista_target* t, bool plan_now = false) {
     h.t = *t;
+    h.g = g;
     h.freq.assign(t->chan_freq, t->chan_freq + t->nchan);
     h.t.chan_freq = h.freq.data();
     if (t->chan_width) {
         h.width.assign(t->chan_width, t->chan_width + t->nchan);
         h.t.chan_width = h.width.data();
     }
-    h.plan = plan_target(g, &h.t);
+    if (!plan_now && !(g->flags & VISTA_F_SPECTRAL_NEAREST)) {
+        double wmax = 0.0;
+        for (int32_t k = 0; k < t->nchan; ++k)
+            wmax = std::max(wmax, channel_width(h.t.chan_freq, h.t.chan_width, t->nchan, k) * (1.0 + t->z));
+        plan_now = !(std::floor(wmax / g->dfreq) + 2.0 <= (double)kMaxNj);
+    }
+    if (plan_now) finish_plan(h);
     h.n_samples = (uint64_t)t->nrow * t->nchan * t->npol;
-    h.n_outside_band = (uint64_t)t->nrow * t->npol * (uint64_t)(t->nchan - h.plan.n_inband);
     if (t->mem == VISTA_MEM_HOST && t->nrow > 0) {
         size_t nr = (size_t)t->nrow, ns = nr * t->nchan * t->npol;
         size_t b_uvw = nr * 3 * sizeof(double), b_vis = ns * 8;
@@ -309,6 +354,11 @@ struct HostLaunch {
 };
 
 static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& tu, int jsub) {
+    {
+        std::vector<HostTarget*> all;
+        for (const StackJob& J : jobs) all.insert(all.end(), J.targets.begin(), J.targets.end());
+        plan_all(all);
+    }
     HostLaunch h;
     auto put = [&h](const void* p, size_t n) {
         size_t off = align256(h.arena.size());
@@ -1008,7 +1058,7 @@ int vista_stack_add_target(vista_stack* s, const vista_target* t) {
         auto h = std::make_unique<HostTarget>();
         copy_target(*h, &s->g, t);
         std::string w;
-        if (!check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
+        if (h->planned && !check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
         s->targets.push_back(std::move(h));
         return VISTA_OK;
     });
@@ -1092,7 +1142,7 @@ int vista_debug_indices(const vista_grid_desc* g, const vista_target* t, void* h
     hipStream_t stream = (hipStream_t)hip_stream;
     return guarded(nullptr, [&]() -> int {
         HostTarget h;
-        copy_target(h, g, t);
+        copy_target(h, g, t, true);
         DevMem mem(stream);
         size_t n = (size_t)t->nrow * t->nchan;
         const double* duvw = t->uvw;
@@ -1137,7 +1187,7 @@ int vista_debug_rotate(const vista_grid_desc* g, const vista_target* t, void* hi
     hipStream_t stream = (hipStream_t)hip_stream;
     return guarded(nullptr, [&]() -> int {
         HostTarget h;
-        copy_target(h, g, t);
+        copy_target(h, g, t, true);
         DevMem mem(stream);
         DevChan* dch = mem.alloc_n<DevChan>(t->nchan);
         VISTA_HIP(hipMemcpyAsync(dch, h.plan.chan.data(), t->nchan * sizeof(DevChan), hipMemcpyHostToDevice, stream));
@@ -1386,7 +1436,7 @@ int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t)
         auto h = std::make_unique<HostTarget>();
         copy_target(*h, &b->g[stack], t);
         std::string w;
-        if (!check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
+        if (h->planned && !check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
         b->targets[stack].push_back(std::move(h));
         return VISTA_OK;
     });

@@ -250,3 +250,20 @@ def test_image_validation():
     rc = L.vista_image(C.byref(vista.grid_desc(g)), S.ctypes.data, W.ctypes.data, img.ctypes.data, None, None,
                        None)
     assert rc == vista.VISTA_E_ARG and "device" in vista.lib().vista_last_error().decode()
+
+
+def test_too_fine_rest_grid_refused_at_add():
+    """A rest grid so fine that an input channel would overlap more than 255 rest channels
+    is refused when the target is added (planning of ordinary targets waits for the
+    launch)."""
+    cfg = synth.config("small")
+    t = synth.make_target(cfg, 0)
+    g = dict(synth.make_grid(cfg))
+    g["dfreq"] = g["dfreq"] / 2000
+    g["nchan"] = 200000
+    g["freq_lo"] = cfg.line_rest - 0.5 * g["nchan"] * g["dfreq"]
+    s = vista.Stack(g, stream=None)
+    with pytest.raises(vista.VistaError) as e:
+        s.add(t)
+    assert e.value.code == vista.VISTA_E_ARG and "255" in str(e.value)
+    s.close()
