@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "vista_device.h"
 
@@ -21,7 +22,22 @@ namespace vista {
 
 namespace {
 
-constexpr int kImgThreads = 256;
+constexpr int kSumThreads = 256;
+constexpr int kRowThreads = 256;
+constexpr int kColThreads = 1024;
+constexpr int kRowElems = 1024;     // complex elements of one row tile, unless a row is longer
+constexpr int kColElems = 4096;     // complex elements of one column tile
+constexpr int kMaxSide = 4096;      // largest grid side; a tile is at least one whole row or column
+constexpr int kColRegs = (kColElems > kMaxSide ? kColElems : kMaxSide) / kColThreads;
+
+// Workgroup barrier ordering LDS only.  Every exchange between threads here goes through
+// LDS, and a barrier that also orders global memory makes each wave wait for all of its
+// outstanding global loads, including the next tile's, which are meant to stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -34,6 +50,7 @@ __device__ float2* fft_inverse(float2* x, float2* y, int logn, int cnt) {
     int l = half, lm = 0;                   // l = n / 2^(s+1); m = 2^s = 1 << lm
     for (int s = 0; s < logn; ++s, l >>= 1, ++lm) {
         const int m = 1 << lm;
+        const float inv2l = 1.f / (float)(2 * l);        // exact: 2 l is a power of two
         for (int b = threadIdx.x; b < cnt * half; b += blockDim.x) {
             const int t = b >> (logn - 1), bb = b & (half - 1);
             const int j = bb >> lm, k = bb & (m - 1);
@@ -41,26 +58,45 @@ __device__ float2* fft_inverse(float2* x, float2* y, int logn, int cnt) {
             float2* ys = y + t * n;
             const float2 c0 = xs[k + j * m], c1 = xs[k + j * m + l * m];
             float sn, cs;
-            sincos_turns((float)j / (float)(2 * l), &sn, &cs);     // exp(+2 pi i j / (2 l))
+            sincos_turns((float)j * inv2l, &sn, &cs);              // exp(+2 pi i j / (2 l))
             ys[k + 2 * j * m] = make_float2(c0.x + c1.x, c0.y + c1.y);
             ys[k + 2 * j * m + m] = cmul(make_float2(c0.x - c1.x, c0.y - c1.y), make_float2(cs, sn));
         }
-        __syncthreads();
+        lds_barrier();
         float2* t = x; x = y; y = t;
     }
     return x;
 }
 
-// Summed weight of every channel, in FP64.
-__global__ void __launch_bounds__(kImgThreads) k_image_wsum(const float* __restrict__ w, int64_t plane,
+// Summed weight of every channel, in FP64.  VEC reads four weights per load (the plane is
+// a multiple of 4; VEC needs the base 16-byte aligned).
+template <bool VEC>
+__global__ void __launch_bounds__(kSumThreads) k_image_wsum(const float* __restrict__ w, int64_t plane,
                                                             double* __restrict__ wsum) {
-    __shared__ double part[kImgThreads];
+    __shared__ double part[kSumThreads];
     const VISTA_GLOBAL float* wj = gptr(w) + (size_t)blockIdx.x * plane;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < plane; i += blockDim.x) acc += (double)wj[i];
+    if (VEC) {
+        const VISTA_GLOBAL float4* w4 = (const VISTA_GLOBAL float4*)wj;
+        const int64_t n4 = plane >> 2;
+        double a1 = 0.0;
+        int64_t i = threadIdx.x;
+        for (; i + kSumThreads < n4; i += 2 * kSumThreads) {
+            const float4 p = w4[i], q = w4[i + kSumThreads];
+            acc += ((double)p.x + (double)p.y) + ((double)p.z + (double)p.w);
+            a1 += ((double)q.x + (double)q.y) + ((double)q.z + (double)q.w);
+        }
+        if (i < n4) {
+            const float4 p = w4[i];
+            acc += ((double)p.x + (double)p.y) + ((double)p.z + (double)p.w);
+        }
+        acc += a1;
+    } else {
+        for (int64_t i = threadIdx.x; i < plane; i += blockDim.x) acc += (double)wj[i];
+    }
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = kImgThreads / 2; o > 0; o >>= 1) {
+    for (int o = kSumThreads / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
         __syncthreads();
     }
@@ -70,7 +106,7 @@ __global__ void __launch_bounds__(kImgThreads) k_image_wsum(const float* __restr
 // Row pass: block (j, row block) transforms `rows` consecutive rows of channel j.  The
 // input is complex (S) or real (the weights, for the beam).
 template <bool REAL>
-__global__ void __launch_bounds__(kImgThreads) k_image_rows(const void* __restrict__ src, float2* __restrict__ tmp,
+__global__ void __launch_bounds__(kRowThreads) k_image_rows(const void* __restrict__ src, float2* __restrict__ tmp,
                                                             int lognu, int nv, int rows) {
     extern __shared__ float2 lds[];
     const int nu = 1 << lognu;
@@ -79,43 +115,80 @@ __global__ void __launch_bounds__(kImgThreads) k_image_rows(const void* __restri
     float2* x = lds;
     float2* y = lds + rows * nu;
     for (int i = threadIdx.x; i < rows * nu; i += blockDim.x) {
-        const int iv = iv0 + i / nu, iu = i & (nu - 1);
+        const int iv = iv0 + (i >> lognu), iu = i & (nu - 1);
         float2 v;
         if (REAL) v = make_float2(gptr((const float*)src)[base + i], 0.f);
         else v = gptr((const float2*)src)[base + i];
         const float sg = ((iu + iv) & 1) ? -1.f : 1.f;            // centring (input side)
         x[i] = make_float2(sg * v.x, sg * v.y);
     }
-    __syncthreads();
+    lds_barrier();
     const float2* r = fft_inverse(x, y, lognu, rows);
     for (int i = threadIdx.x; i < rows * nu; i += blockDim.x) tmp[base + i] = r[i];
 }
 
-// Column pass: block (j, column tile) transforms `cols` adjacent columns of channel j and
-// writes their real part, with the output centring and the channel's weight, to `out`.
-__global__ void __launch_bounds__(kImgThreads) k_image_cols(const float2* __restrict__ tmp,
+// The column pass is persistent: a block walks tiles tile, tile + gridDim.x, ... and loads
+// the next tile into registers before it transforms the current one, so that the loads
+// are in flight while the block works in LDS.
+
+// Column pass: tile t holds `cols` adjacent columns p0 = (t mod (nu / cols)) * cols, ...
+// of channel t / (nu / cols); the block writes their real part, with the output centring
+// and the channel's weight, to `out`.  FULL: every tile has exactly kColThreads * kColRegs
+// elements.
+template <bool FULL>
+__global__ void __launch_bounds__(kColThreads) k_image_cols(const float2* __restrict__ tmp,
                                                             const double* __restrict__ wsum, float* __restrict__ out,
-                                                            int lognu, int lognv, int cols, float sign) {
+                                                            int lognu, int lognv, int logcols, int ntiles, float sign) {
+    constexpr int E = kColRegs;
     extern __shared__ float2 lds[];
-    const int nu = 1 << lognu, nv = 1 << lognv;
-    const int j = blockIdx.y, p0 = blockIdx.x * cols;
-    const size_t plane = (size_t)nu * nv, base = (size_t)j * plane;
-    float2* x = lds;                       // column c at x + c * nv
-    float2* y = lds + cols * nv;
-    for (int i = threadIdx.x; i < cols * nv; i += blockDim.x) {
-        const int iv = i / cols, c = i - iv * cols;                // c fastest: contiguous loads
-        x[c * nv + iv] = gptr(tmp)[base + (size_t)iv * nu + p0 + c];
+    const int nu = 1 << lognu, nv = 1 << lognv, cols = 1 << logcols, per = cols * nv;
+    const int logtpc = lognu - logcols;                            // tiles per channel: nu / cols
+    const size_t plane = (size_t)nu * nv;
+    float2* x = lds;                                               // column c at x + c * nv
+    float2* y = lds + per;
+    float2 v[E];
+    auto fetch = [&](int tile) {
+        const size_t base = (size_t)(tile >> logtpc) * plane + ((size_t)(tile & ((1 << logtpc) - 1)) << logcols);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = threadIdx.x + e * kColThreads;           // c = i mod cols fastest: contiguous loads
+            if (FULL || i < per) v[e] = gptr(tmp)[base + (size_t)(i >> logcols) * nu + (i & (cols - 1))];
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = threadIdx.x + e * kColThreads;
+            if (FULL || i < per) x[(i & (cols - 1)) * nv + (i >> logcols)] = v[e];
+        }
+        lds_barrier();
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);
+        const float2* r = fft_inverse(x, y, lognv, cols);
+        const int j = tile >> logtpc, p0 = (tile & ((1 << logtpc) - 1)) << logcols;
+        const double wt = wsum[j];
+        const float inv = wt > 0.0 ? (float)(1.0 / wt) : 0.f;
+        const size_t base = (size_t)j * plane;
+        for (int i = threadIdx.x; i < per; i += blockDim.x) {
+            const int q = i >> logcols, c = i & (cols - 1);
+            const int p = p0 + c;
+            const float sg = ((p + q) & 1) ? -sign : sign;        // centring (output side)
+            ((VISTA_GLOBAL float*)out)[base + (size_t)q * nu + p] = sg * r[c * nv + q].x * inv;
+        }
+        lds_barrier();
     }
-    __syncthreads();
-    const float2* r = fft_inverse(x, y, lognv, cols);
-    const double wt = wsum[j];
-    const float inv = wt > 0.0 ? (float)(1.0 / wt) : 0.f;
-    for (int i = threadIdx.x; i < cols * nv; i += blockDim.x) {
-        const int q = i / cols, c = i - q * cols;
-        const int p = p0 + c;
-        const float sg = ((p + q) & 1) ? -sign : sign;            // centring (output side)
-        ((VISTA_GLOBAL float*)out)[base + (size_t)q * nu + p] = sg * r[c * nv + q].x * inv;
-    }
+}
+
+// Blocks of a persistent launch: as many as fit on the device at once, at most `ntiles`.
+template <typename K>
+int persistent_blocks(K kernel, int threads, size_t lds, int ntiles) {
+    int dev = 0, cu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+        cu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb <= 0) nb = 1;
+    return (int)std::min<int64_t>(ntiles, (int64_t)nb * cu);
 }
 
 int log2i(int n) {
@@ -132,21 +205,30 @@ hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, 
                         int nchan, float2* tmp, double* wsum, hipStream_t stream) {
     if (nchan <= 0) return hipSuccess;
     const int lognu = log2i(nu), lognv = log2i(nv);
-    if ((1 << lognu) != nu || (1 << lognv) != nv || nu < 2 || nv < 2 || nu > 4096 || nv > 4096)
+    if ((1 << lognu) != nu || (1 << lognv) != nv || nu < 2 || nv < 2 || nu > kMaxSide || nv > kMaxSide)
         return hipErrorInvalidValue;
-    const int rows = std::min(nv, std::max(1, 1024 / nu));
-    const int cols = std::min(nu, std::max(1, 4096 / nv));
+    const int rows = std::min(nv, std::max(1, kRowElems / nu));
+    const int cols = std::min(nu, std::max(1, kColElems / nv));
+    const int logcols = log2i(cols);
+    const int nct = (int)((int64_t)nchan * (nu / cols));
     const size_t lrow = 2 * (size_t)rows * nu * sizeof(float2), lcol = 2 * (size_t)cols * nv * sizeof(float2);
     const float sign = (nu == 2 ? -1.f : 1.f) * (nv == 2 ? -1.f : 1.f);
-    hipLaunchKernelGGL(k_image_wsum, dim3(nchan), dim3(kImgThreads), 0, stream, sum_w, (int64_t)nu * nv, wsum);
-    const dim3 grow(nv / rows, nchan), gcol(nu / cols, nchan);
-    hipLaunchKernelGGL(k_image_rows<false>, grow, dim3(kImgThreads), lrow, stream, sum_wvis, tmp, lognu, nv, rows);
-    hipLaunchKernelGGL(k_image_cols, gcol, dim3(kImgThreads), lcol, stream, tmp, wsum, image, lognu, lognv, cols,
+    if (((uintptr_t)sum_w & 15) == 0)
+        hipLaunchKernelGGL(k_image_wsum<true>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)nu * nv,
+                           wsum);
+    else
+        hipLaunchKernelGGL(k_image_wsum<false>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)nu * nv,
+                           wsum);
+    const bool cfull = cols * nv == kColThreads * kColRegs;
+    auto cols_k = cfull ? k_image_cols<true> : k_image_cols<false>;
+    const dim3 grow(nv / rows, nchan), gcol(persistent_blocks(cols_k, kColThreads, lcol, nct));
+    hipLaunchKernelGGL(k_image_rows<false>, grow, dim3(kRowThreads), lrow, stream, sum_wvis, tmp, lognu, nv, rows);
+    hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum, image, lognu, lognv, logcols, nct,
                        sign);
     if (beam) {
-        hipLaunchKernelGGL(k_image_rows<true>, grow, dim3(kImgThreads), lrow, stream, sum_w, tmp, lognu, nv, rows);
-        hipLaunchKernelGGL(k_image_cols, gcol, dim3(kImgThreads), lcol, stream, tmp, wsum, beam, lognu, lognv, cols,
-                           sign);
+        hipLaunchKernelGGL(k_image_rows<true>, grow, dim3(kRowThreads), lrow, stream, sum_w, tmp, lognu, nv, rows);
+        hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum, beam, lognu, lognv, logcols,
+                           nct, sign);
     }
     return hipGetLastError();
 }

@@ -3,7 +3,8 @@
 Every pixel within 1e-5 of the channel's image scale (sum |S_j| / W_j, the largest value a
 pixel can take) plus an absolute 1e-30 (noiseless line wings reach FP32's denormal range,
 which the device flushes to zero), the beam likewise; grids of every shape class the FFT handles (axes of 2,
-rectangular, up to 256 per side), a grid stacked by the library, and the bench's full-size
+rectangular, up to 256 per side, and sampled pixels of axes up to 4096), a grid stacked by the
+library, a weight array that is not 16-byte aligned, and the bench's full-size
 grid (512 x 512 x 960) on sampled pixels.
 """
 import numpy as np
@@ -92,3 +93,49 @@ def test_full_size_grid_sampled_pixels():
         wt = W.sum()
         scale = np.abs(S).sum() / wt if wt > 0 else 1.0
         assert np.max(np.abs(got - ref)) <= TOL * scale + ATOL
+
+
+def _sampled(S, W, img, beam, rng, npix):
+    nchan, nv, nu = S.shape
+    for j in range(nchan):
+        wt = W[j].sum()
+        q = rng.integers(0, nv, npix)
+        p = rng.integers(0, nu, npix)
+        q[0], p[0] = nv // 2, nu // 2
+        ref = oracle.image_pixels(S[j], W[j], q, p)
+        scale = np.abs(S[j]).sum() / wt
+        assert np.max(np.abs(img[j][q, p] - ref)) <= TOL * scale + ATOL
+        if beam is not None:
+            rb = oracle.image_pixels(W[j].astype(np.complex128), W[j], q, p)
+            assert np.max(np.abs(beam[j][q, p] - rb)) <= TOL
+
+
+@pytest.mark.parametrize("shape,nchan", [((4, 4096), 3), ((4096, 2), 3), ((2048, 8), 2), ((4096, 4096), 1)])
+def test_longest_axes_sampled_pixels(shape, nchan):
+    """Axes up to the 4096 limit, where one row or one column fills a whole tile."""
+    nv, nu = shape
+    rng = np.random.default_rng(nv + 7 * nu)
+    S = (rng.normal(size=(nchan, nv, nu)) + 1j * rng.normal(size=(nchan, nv, nu))).astype(np.complex64)
+    W = rng.uniform(0.0, 2.0, size=(nchan, nv, nu)).astype(np.float32)
+    g = dict(nu=nu, nv=nv, du=1.0, dv=1.0, nchan=nchan, freq_lo=1e9, dfreq=1e6)
+    img, beam, _ = vista.image(g, torch.from_numpy(S).cuda(), torch.from_numpy(W).cuda(), beam=True)
+    torch.cuda.synchronize()
+    _sampled(S.astype(np.complex128), W.astype(np.float64), img.cpu().numpy(), beam.cpu().numpy(), rng,
+             16 if nu * nv > 1 << 20 else 48)
+
+
+def test_weights_not_16_byte_aligned():
+    """A weight array that starts 4 bytes into its allocation takes the scalar summing path;
+    the image is the same as the oracle's."""
+    nchan, nv, nu = 3, 64, 32
+    rng = np.random.default_rng(5)
+    S = (rng.normal(size=(nchan, nv, nu)) + 1j * rng.normal(size=(nchan, nv, nu))).astype(np.complex64)
+    W = rng.uniform(0.0, 2.0, size=(nchan, nv, nu)).astype(np.float32)
+    buf = torch.zeros(W.size + 1, dtype=torch.float32, device="cuda")
+    w_dev = buf[1:].view(nchan, nv, nu)
+    w_dev.copy_(torch.from_numpy(W))
+    assert w_dev.data_ptr() % 16 != 0
+    g = dict(nu=nu, nv=nv, du=1.0, dv=1.0, nchan=nchan, freq_lo=1e9, dfreq=1e6)
+    img, beam, _ = vista.image(g, torch.from_numpy(S).cuda(), w_dev, beam=True)
+    torch.cuda.synchronize()
+    _check(S.astype(np.complex128), W.astype(np.float64), img.cpu().numpy(), beam.cpu().numpy())
