@@ -30,9 +30,25 @@ namespace {
 
 
 // First k in [lo, hi) with s * rint((c * a_k) * inv) >= A, or hi.  The key is
-// non-decreasing in k for the given orientation s.
+// non-decreasing in k for the given orientation s.  The continuous value s (c a_k) inv is
+// close to linear in k, so one interpolation step from the range's end points guesses the
+// answer g; the exact keys at g - 1 and g (two independent loads) confirm it or shrink the
+// range, and bisection finishes what is left.  The answer is the same as plain bisection.
 __device__ int32_t first_at_least(const DevChan* ch, int32_t lo, int32_t hi, double c, double inv,
                                   double s, double A) {
+    if (hi - lo > 2) {
+        const double x0 = s * ((c * ch[lo].a) * inv), x1 = s * ((c * ch[hi - 1].a) * inv);
+        const double f = (A - 0.5 - x0) / (x1 - x0);                 // rint reaches A at A - 1/2
+        int32_t g = lo;
+        if (f >= 1.0) g = hi;
+        else if (f > 0.0) g = lo + (int32_t)ceil(f * (double)(hi - 1 - lo));    // also NaN -> lo
+        g = min(max(g, lo), hi);
+        const bool below = g > lo && s * cell_coord(c, ch[g - 1].a, inv) < A;    // key(g - 1) < A
+        const bool at = g == hi || s * cell_coord(c, ch[g].a, inv) >= A;       // key(g) >= A
+        if ((below || g == lo) && at) return g;
+        if (!at) lo = g + 1;                   // key(g) < A: the answer is past g
+        else hi = g - 1;                       // key(g - 1) >= A: the answer is at most g - 1
+    }
     while (lo < hi) {
         int32_t mid = (lo + hi) >> 1;
         double key = s * cell_coord(c, ch[mid].a, inv);
