@@ -29,30 +29,41 @@ namespace {
 
 
 
+// Channel scales a_k as the searches read them: from LDS (the block's staged copy) or from
+// the target's channel table.
+struct ScalesLds {
+    const double* a;
+    __device__ double operator[](int32_t k) const { return a[k]; }
+};
+struct ScalesGlobal {
+    const DevChan* ch;
+    __device__ double operator[](int32_t k) const { return ch[k].a; }
+};
+
 // First k in [lo, hi) with s * rint((c * a_k) * inv) >= A, or hi.  The key is
 // non-decreasing in k for the given orientation s.  The continuous value s (c a_k) inv is
 // close to linear in k, so one interpolation step from the range's end points guesses the
 // answer g; the exact keys at g - 1 and g (two independent loads) confirm it or shrink the
 // range, and bisection finishes what is left.  The answer is the same as plain bisection.
-__device__ int32_t first_at_least(const DevChan* ch, int32_t lo, int32_t hi, double c, double inv,
-                                  double s, double A) {
+template <class A>
+__device__ int32_t first_at_least(const A& a, int32_t lo, int32_t hi, double c, double inv, double s, double key_min) {
     if (hi - lo > 2) {
-        const double x0 = s * ((c * ch[lo].a) * inv), x1 = s * ((c * ch[hi - 1].a) * inv);
-        const double f = (A - 0.5 - x0) / (x1 - x0);                 // rint reaches A at A - 1/2
+        const double x0 = s * ((c * a[lo]) * inv), x1 = s * ((c * a[hi - 1]) * inv);
+        const double f = (key_min - 0.5 - x0) / (x1 - x0);           // rint reaches key_min at key_min - 1/2
         int32_t g = lo;
         if (f >= 1.0) g = hi;
         else if (f > 0.0) g = lo + (int32_t)ceil(f * (double)(hi - 1 - lo));    // also NaN -> lo
         g = min(max(g, lo), hi);
-        const bool below = g > lo && s * cell_coord(c, ch[g - 1].a, inv) < A;    // key(g - 1) < A
-        const bool at = g == hi || s * cell_coord(c, ch[g].a, inv) >= A;       // key(g) >= A
+        const bool below = g > lo && s * cell_coord(c, a[g - 1], inv) < key_min;  // key(g - 1) < key_min
+        const bool at = g == hi || s * cell_coord(c, a[g], inv) >= key_min;     // key(g) >= key_min
         if ((below || g == lo) && at) return g;
-        if (!at) lo = g + 1;                   // key(g) < A: the answer is past g
-        else hi = g - 1;                       // key(g - 1) >= A: the answer is at most g - 1
+        if (!at) lo = g + 1;                   // key(g) < key_min: the answer is past g
+        else hi = g - 1;                       // key(g - 1) >= key_min: the answer is at most g - 1
     }
     while (lo < hi) {
         int32_t mid = (lo + hi) >> 1;
-        double key = s * cell_coord(c, ch[mid].a, inv);
-        if (key >= A) hi = mid; else lo = mid + 1;
+        double key = s * cell_coord(c, a[mid], inv);
+        if (key >= key_min) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
@@ -63,11 +74,12 @@ struct Track {
 };
 
 // In-grid interval of row (U, V) over channels [klo, khi).
-__device__ Track in_grid(const DevChan* ch, int32_t klo, int32_t khi, double U, double V,
-                         double inv_du, double inv_dv, int32_t nu, int32_t nv) {
+template <class A>
+__device__ Track in_grid(const A& a, int32_t klo, int32_t khi, double U, double V, double inv_du, double inv_dv,
+                         int32_t nu, int32_t nv) {
     Track t;
-    double u0 = cell_coord(U, ch[klo].a, inv_du), u1 = cell_coord(U, ch[khi - 1].a, inv_du);
-    double v0 = cell_coord(V, ch[klo].a, inv_dv), v1 = cell_coord(V, ch[khi - 1].a, inv_dv);
+    double u0 = cell_coord(U, a[klo], inv_du), u1 = cell_coord(U, a[khi - 1], inv_du);
+    double v0 = cell_coord(V, a[klo], inv_dv), v1 = cell_coord(V, a[khi - 1], inv_dv);
     t.su = (u1 >= u0) ? 1.0 : -1.0;
     t.sv = (v1 >= v0) ? 1.0 : -1.0;
     // inside: -(n/2) <= r < n - n/2.  With key = s r: s>0 -> [lo_b, hi_b);
@@ -76,10 +88,10 @@ __device__ Track in_grid(const DevChan* ch, int32_t klo, int32_t khi, double U, 
     double lob_v = -(double)(nv / 2), hib_v = (double)(nv - nv / 2);
     double Au = t.su > 0 ? lob_u : 1.0 - hib_u, Bu = t.su > 0 ? hib_u : 1.0 - lob_u;
     double Av = t.sv > 0 ? lob_v : 1.0 - hib_v, Bv = t.sv > 0 ? hib_v : 1.0 - lob_v;
-    int32_t a1 = first_at_least(ch, klo, khi, U, inv_du, t.su, Au);
-    int32_t b1 = first_at_least(ch, a1, khi, U, inv_du, t.su, Bu);
-    int32_t a2 = first_at_least(ch, klo, khi, V, inv_dv, t.sv, Av);
-    int32_t b2 = first_at_least(ch, a2, khi, V, inv_dv, t.sv, Bv);
+    int32_t a1 = first_at_least(a, klo, khi, U, inv_du, t.su, Au);
+    int32_t b1 = first_at_least(a, a1, khi, U, inv_du, t.su, Bu);
+    int32_t a2 = first_at_least(a, klo, khi, V, inv_dv, t.sv, Av);
+    int32_t b2 = first_at_least(a, a2, khi, V, inv_dv, t.sv, Bv);
     t.ga = max(a1, a2);
     t.gb = min(b1, b2);
     if (t.gb < t.ga) t.gb = t.ga;
@@ -87,10 +99,11 @@ __device__ Track in_grid(const DevChan* ch, int32_t klo, int32_t khi, double U, 
 }
 
 // End (exclusive) of the run of channels starting at k that stay in k's uv tile.
-__device__ int32_t tile_run_end(const DevChan* ch, int32_t k, int32_t gb, double U, double V,
-                                double inv_du, double inv_dv, int32_t nu, int32_t nv, int32_t TU,
-                                int32_t TV, const Track& tr, int32_t* tile_u, int32_t* tile_v) {
-    double ru = cell_coord(U, ch[k].a, inv_du), rv = cell_coord(V, ch[k].a, inv_dv);
+template <class A>
+__device__ int32_t tile_run_end(const A& a, int32_t k, int32_t gb, double U, double V, double inv_du,
+                                double inv_dv, int32_t nu, int32_t nv, int32_t TU, int32_t TV, const Track& tr,
+                                int32_t* tile_u, int32_t* tile_v) {
+    double ru = cell_coord(U, a[k], inv_du), rv = cell_coord(V, a[k], inv_dv);
     int32_t iu = (int32_t)ru + nu / 2, iv = (int32_t)rv + nv / 2;
     int32_t tu = iu / TU, tv = iv / TV;
     *tile_u = tu;
@@ -99,39 +112,87 @@ __device__ int32_t tile_run_end(const DevChan* ch, int32_t k, int32_t gb, double
     // -r >= -(t T - n/2) + 1.
     double Au = tr.su > 0 ? (double)((tu + 1) * TU - nu / 2) : (double)(-(tu * TU - nu / 2) + 1);
     double Av = tr.sv > 0 ? (double)((tv + 1) * TV - nv / 2) : (double)(-(tv * TV - nv / 2) + 1);
-    int32_t nu_k = first_at_least(ch, k + 1, gb, U, inv_du, tr.su, Au);
-    int32_t nv_k = first_at_least(ch, k + 1, gb, V, inv_dv, tr.sv, Av);
+    int32_t nu_k = first_at_least(a, k + 1, gb, U, inv_du, tr.su, Au);
+    int32_t nv_k = first_at_least(a, k + 1, gb, V, inv_dv, tr.sv, Av);
     return min(nu_k, nv_k);
 }
 
 
 // ----------------------------------------------------------------------------- binning
 
-__global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp,
-                                               uint32_t* __restrict__ seg_count,
-                                               const uint32_t* __restrict__ seg_off,
-                                               uint32_t* __restrict__ keys,
-                                               uint64_t* __restrict__ vals, int emit) {
+constexpr int kTrackThreads = 256;
+constexpr int kTrackScales = 2048;     // channel scales of one target staged in LDS (16 KB)
+
+// Records of row r of target T, whose uv cells come from (U, V): counted, or (EMIT)
+// written from position `base` on.  Returns the count; `outside` gets the row's in-band
+// samples that fall outside the grid.
+template <bool EMIT, class A>
+__device__ uint32_t track_row(const LaunchDesc& L, const DevTarget& T, const DevStack& S, const A& a, int64_t g,
+                              double U, double V, uint32_t base, uint32_t* __restrict__ keys,
+                              uint64_t* __restrict__ vals, unsigned long long* outside) {
+    const Track tr = in_grid(a, T.kin_lo, T.kin_hi, U, V, S.inv_du, S.inv_dv, S.nu, S.nv);
+    const int32_t inb_all = T.inband[T.kin_hi] - T.inband[T.kin_lo];
+    const int32_t inb_in = T.inband[tr.gb] - T.inband[tr.ga];
+    *outside = (unsigned long long)(inb_all - inb_in) * (unsigned long long)T.npol;
+    uint32_t n = 0;
+    int32_t k = tr.ga;
+    while (k < tr.gb) {
+        int32_t tu, tv;
+        const int32_t k1 = tile_run_end(a, k, tr.gb, U, V, S.inv_du, S.inv_dv, S.nu, S.nv, L.tu, L.tv, tr, &tu, &tv);
+        const int64_t unit0 = S.unit_base + ((int64_t)tv * S.tiles_u + tu) * S.nblocks;
+        for (int32_t b = 0; b < T.nblocks; ++b) {
+            const int32_t lo = max(k, T.blk[2 * b]), hi = min(k1, T.blk[2 * b + 1]);
+            if (lo >= hi) continue;
+            if (EMIT) {
+                keys[base + n] = (uint32_t)(unit0 + b);
+                vals[base + n] = ((uint64_t)g << 32) | ((uint64_t)lo << 16) | (uint64_t)hi;
+            }
+            ++n;
+        }
+        k = k1;
+    }
+    return n;
+}
+
+// Binning pass over the launch's rows, one thread per row: count (EMIT false, also writes
+// each row's context for the packed accumulation) or emit the records.  The channel scales
+// of the block's first target are staged in LDS when they fit, so the searches of its rows
+// (nearly always every row of the block) read LDS instead of the channel table.
+template <bool EMIT>
+__global__ void __launch_bounds__(kTrackThreads) k_track(const LaunchDesc* __restrict__ Lp,
+                                                         uint32_t* __restrict__ seg_count,
+                                                         const uint32_t* __restrict__ seg_off,
+                                                         uint32_t* __restrict__ keys,
+                                                         uint64_t* __restrict__ vals) {
+    __shared__ double s_scale[kTrackScales];
     const LaunchDesc& L = *Lp;
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
+    const int32_t t0 = g0 < L.nrows ? (int32_t)find_le_uniform(L.target_row_base, L.ntargets, g0) : -1;
+    const bool staged = t0 >= 0 && L.targets[t0].nchan <= kTrackScales;
+    if (staged) {
+        const DevChan* ch = L.targets[t0].chan;
+        for (int32_t k = threadIdx.x; k < L.targets[t0].nchan; k += blockDim.x) s_scale[k] = ch[k].a;
+    }
+    __syncthreads();
     unsigned long long outside = 0;
     int32_t stack_id = -1;
     if (g < L.nrows) {
-        int32_t ti = (int32_t)find_le(L.target_row_base, L.ntargets, g);
+        int32_t ti = t0;
+        if (g >= L.targets[t0].row_base + L.targets[t0].nrow) ti = (int32_t)find_le(L.target_row_base, L.ntargets, g);
         const DevTarget& T = L.targets[ti];
         const DevStack& S = L.stacks[T.stack];
         stack_id = T.stack;
-        int64_t r = g - T.row_base;
-        uint32_t n = 0;
-        if (!emit && L.rowctx) {
+        const int64_t r = g - T.row_base;
+        const double Um = T.uvw[3 * r], Vm = T.uvw[3 * r + 1], Wm = T.uvw[3 * r + 2];
+        if (!EMIT && L.rowctx) {
             // the row's context for the packed accumulation
-            const double U = T.uvw[3 * r], V = T.uvw[3 * r + 1], W = T.uvw[3 * r + 2];
             RowCtx c;
-            cell_uv(T, U, V, W, &c.U, &c.V);        // uv cells: the (rotated) baseline
+            cell_uv(T, Um, Vm, Wm, &c.U, &c.V);     // uv cells: the (rotated) baseline
             if (L.phase_fp32)
-                c.T = (double)((float)U * (float)T.l + (float)V * (float)T.m + (float)W * (float)T.nm1);
+                c.T = (double)((float)Um * (float)T.l + (float)Vm * (float)T.m + (float)Wm * (float)T.nm1);
             else
-                c.T = U * T.l + V * T.m + W * T.nm1;
+                c.T = Um * T.l + Vm * T.m + Wm * T.nm1;
             const size_t rs = (size_t)T.nchan * T.npol;     // samples per row
             c.w0 = T.weight_per_chan ? 0.f : T.weight[r * T.npol];
             c.w1 = (T.weight_per_chan || T.npol < 2) ? 0.f : T.weight[r * T.npol + 1];
@@ -142,35 +203,19 @@ __global__ void __launch_bounds__(256) k_track(const LaunchDesc* __restrict__ Lp
             c.info = (uint32_t)T.npol | ((uint32_t)(T.weight_per_chan != 0) << 8);
             L.rowctx[g] = c;
         }
+        uint32_t n = 0;
         if (T.kin_lo < T.kin_hi) {
             double U, V;
-            cell_uv(T, T.uvw[3 * r], T.uvw[3 * r + 1], T.uvw[3 * r + 2], &U, &V);
-            Track tr = in_grid(T.chan, T.kin_lo, T.kin_hi, U, V, S.inv_du, S.inv_dv, S.nu, S.nv);
-            int32_t inb_all = T.inband[T.kin_hi] - T.inband[T.kin_lo];
-            int32_t inb_in = T.inband[tr.gb] - T.inband[tr.ga];
-            outside = (unsigned long long)(inb_all - inb_in) * (unsigned long long)T.npol;
-            uint32_t base = emit ? seg_off[g] : 0;
-            int32_t k = tr.ga;
-            while (k < tr.gb) {
-                int32_t tu, tv;
-                int32_t k1 = tile_run_end(T.chan, k, tr.gb, U, V, S.inv_du, S.inv_dv, S.nu, S.nv, L.tu,
-                                          L.tv, tr, &tu, &tv);
-                int64_t unit0 = S.unit_base + ((int64_t)tv * S.tiles_u + tu) * S.nblocks;
-                for (int32_t b = 0; b < T.nblocks; ++b) {
-                    int32_t lo = max(k, T.blk[2 * b]), hi = min(k1, T.blk[2 * b + 1]);
-                    if (lo >= hi) continue;
-                    if (emit) {
-                        keys[base + n] = (uint32_t)(unit0 + b);
-                        vals[base + n] = ((uint64_t)g << 32) | ((uint64_t)lo << 16) | (uint64_t)hi;
-                    }
-                    ++n;
-                }
-                k = k1;
-            }
+            cell_uv(T, Um, Vm, Wm, &U, &V);
+            const uint32_t base = EMIT ? seg_off[g] : 0u;
+            if (staged && ti == t0)
+                n = track_row<EMIT>(L, T, S, ScalesLds{s_scale}, g, U, V, base, keys, vals, &outside);
+            else
+                n = track_row<EMIT>(L, T, S, ScalesGlobal{T.chan}, g, U, V, base, keys, vals, &outside);
         }
-        if (!emit) seg_count[g] = n;
+        if (!EMIT) seg_count[g] = n;
     }
-    if (!emit) {
+    if (!EMIT) {
         // outside-uv samples: one atomic per wave and stack run (waves rarely straddle
         // two stacks; lanes of another stack add their own share)
         int32_t first = __shfl(stack_id, 0, kWave);
@@ -726,9 +771,13 @@ __global__ void k_debug_rotate(const DevTarget* __restrict__ Tp, float2* out, in
 hipError_t launch_track(int64_t rows_cap, const LaunchDesc* dL, uint32_t* seg_count, const uint32_t* seg_off,
                         uint32_t* keys, uint64_t* vals, int emit, hipStream_t stream) {
     if (rows_cap <= 0) return hipSuccess;
-    int64_t blocks = (rows_cap + 255) / 256;
-    hipLaunchKernelGGL(k_track, dim3((unsigned)blocks), dim3(256), 0, stream, dL, seg_count, seg_off, keys, vals,
-                       emit);
+    int64_t blocks = (rows_cap + kTrackThreads - 1) / kTrackThreads;
+    if (emit)
+        hipLaunchKernelGGL(k_track<true>, dim3((unsigned)blocks), dim3(kTrackThreads), 0, stream, dL, seg_count,
+                           seg_off, keys, vals);
+    else
+        hipLaunchKernelGGL(k_track<false>, dim3((unsigned)blocks), dim3(kTrackThreads), 0, stream, dL, seg_count,
+                           seg_off, keys, vals);
     return hipGetLastError();
 }
 

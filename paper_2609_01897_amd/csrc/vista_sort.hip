@@ -7,7 +7,8 @@
 // Radix sort: 8-bit digits, least significant first.  Each pass is a stable counting
 // sort: per-block digit histograms -> exclusive scan of the digit-major histogram matrix
 // -> scatter with ranks that are stable inside the block (items are visited in index
-// order: slot, wave, lane; equal digits inside a wave are matched with ballots).
+// order: slot, wave, lane; equal digits inside a wave are matched with ballots), staged
+// in LDS so that each digit's run of the block is written contiguously.
 #include <hip/hip_runtime.h>
 
 #include "vista_internal.h"
@@ -116,26 +117,54 @@ __global__ void __launch_bounds__(kSortThreads) k_rs_hist(const uint32_t* __rest
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one tile: every record is ranked among the tile's records of its digit (in
+// index order: slot, wave, lane, so the sort is stable), placed at that rank in LDS, and
+// the tile is then written out from LDS digit run by digit run, so that consecutive
+// threads store to consecutive addresses.
 __global__ void __launch_bounds__(kSortThreads) k_rs_scatter(const uint32_t* __restrict__ kin, const uint64_t* __restrict__ vin,
                                                              const int64_t* __restrict__ n_dev, int64_t n_host, int shift,
+                                                             const uint32_t* __restrict__ hist,
                                                              const uint32_t* __restrict__ off, int64_t nblocks,
                                                              uint32_t* __restrict__ kout, uint64_t* __restrict__ vout) {
     constexpr int NW = kSortThreads / 64;
+    static_assert(kSortThreads == kRadix, "one thread per digit");
     __shared__ uint32_t run[kRadix];
     __shared__ uint32_t wcnt[NW][kRadix];
     __shared__ uint32_t wbase[NW][kRadix];
+    __shared__ uint32_t lstart[kRadix];    // start of each digit's run in the tile
+    __shared__ uint32_t gstart[kRadix];    // where that run goes in the output
+    __shared__ uint32_t wtot[NW];
+    __shared__ uint32_t sk[kSortTile];
+    __shared__ uint64_t sv[kSortTile];
     int64_t n = n_dev ? *n_dev : n_host;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    run[threadIdx.x] = 0;
-    for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
+    {
+        // the tile's digit counts (from the histogram pass), exclusive scan over digits
+        const int64_t hd = (int64_t)threadIdx.x * nblocks + blockIdx.x;
+        const uint32_t c = hist[hd];
+        gstart[threadIdx.x] = off[hd];
+        uint32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        run[threadIdx.x] = 0;
+        for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < wave; ++w) add += wtot[w];
+        lstart[threadIdx.x] = x - c + add;
+    }
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int s = 0; s < kSortItems; ++s) {
         int64_t e = base + (int64_t)s * kSortThreads + threadIdx.x;
         bool valid = e < n;
         uint32_t key = valid ? kin[e] : 0u;
+        uint64_t val = valid ? vin[e] : 0ull;
         uint32_t d = (key >> shift) & (kRadix - 1);
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
@@ -159,11 +188,19 @@ __global__ void __launch_bounds__(kSortThreads) k_rs_scatter(const uint32_t* __r
         }
         __syncthreads();
         if (valid) {
-            uint32_t pos = off[(int64_t)d * nblocks + blockIdx.x] + wbase[wave][d] + rank_w;
-            kout[pos] = key;
-            vout[pos] = vin[e];
+            const uint32_t p = lstart[d] + wbase[wave][d] + rank_w;
+            sk[p] = key;
+            sv[p] = val;
         }
         __syncthreads();
+    }
+    const int nvalid = (int)(n - base < (int64_t)kSortTile ? (n - base > 0 ? n - base : 0) : (int64_t)kSortTile);
+    for (int i = threadIdx.x; i < nvalid; i += kSortThreads) {
+        const uint32_t key = sk[i];
+        const uint32_t d = (key >> shift) & (kRadix - 1);
+        const uint32_t pos = gstart[d] + ((uint32_t)i - lstart[d]);
+        kout[pos] = key;
+        vout[pos] = sv[i];
     }
 }
 
@@ -227,8 +264,8 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint64_t* vals, const int64_t* n_dev
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, ka, n_dev, cap, shift, hist, nb);
         hipError_t e = scan_impl<uint32_t, uint32_t>(hist, nullptr, m, off, sums, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, ka, va, n_dev, cap, shift, off,
-                           nb, kb, vb);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, ka, va, n_dev, cap, shift, hist,
+                           off, nb, kb, vb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
