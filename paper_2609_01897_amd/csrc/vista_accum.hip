@@ -532,14 +532,22 @@ __global__ void k_record_lens(const uint64_t* __restrict__ recs, const int64_t* 
     }
 }
 
-// key: descending sample count (saturated), value: unit id
+// Work order of the units.  Units holding more than four times the mean sample count go
+// first, largest first (they bound the end of the launch); every other unit follows in unit
+// order (uv tile by tile, rest-channel block fastest), so that units which share rows, and
+// the cache lines where a row's records meet, run close together in time.
+// key: 0x7fffffff - samples for the large units, 0x80000000 for the rest; value: unit id
+// (the sort is stable).
 __global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_t* __restrict__ pre,
                             const int64_t* __restrict__ nunits_dev, uint32_t* __restrict__ keys,
                             uint64_t* __restrict__ vals) {
+    const int64_t nun = *nunits_dev;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < *nunits_dev) {
+    if (u < nun) {
         const uint64_t ns = pre[unit_off[u + 1]] - pre[unit_off[u]];
-        keys[u] = 0xffffffffu - (uint32_t)min(ns, (uint64_t)0xffffffffu);
+        const uint64_t tot = pre[unit_off[nun]] - pre[unit_off[0]];
+        const bool large = (double)ns * (double)nun > 4.0 * (double)tot;
+        keys[u] = large ? 0x7fffffffu - (uint32_t)min(ns, (uint64_t)0x7fffffffu) : 0x80000000u;
         vals[u] = (uint64_t)u;
     }
 }
