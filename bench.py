@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--targets", type=int, default=0, help="use only this many targets (0 = all)")
     ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32")
-    ap.add_argument("--cpu-targets", type=int, default=8, help="targets in the oracle's timed sample")
+    ap.add_argument("--cpu-targets", type=int, default=12, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed leg")
