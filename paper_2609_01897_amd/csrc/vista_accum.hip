@@ -532,22 +532,29 @@ __global__ void k_record_lens(const uint64_t* __restrict__ recs, const int64_t* 
     }
 }
 
-// Work order of the units.  Units holding more than four times the mean sample count go
-// first, largest first (they bound the end of the launch); every other unit follows in unit
-// order (uv tile by tile, rest-channel block fastest), so that units which share rows, and
-// the cache lines where a row's records meet, run close together in time.
-// key: 0x7fffffff - samples for the large units, 0x80000000 for the rest; value: unit id
-// (the sort is stable).
-__global__ void k_unit_keys(const uint32_t* __restrict__ unit_off, const uint64_t* __restrict__ pre,
-                            const int64_t* __restrict__ nunits_dev, uint32_t* __restrict__ keys,
-                            uint64_t* __restrict__ vals) {
+// Work order of the units (key ascending, stable, value: unit id).
+// - A launch of one stack: units holding more than four times the mean sample count first,
+//   largest first (they bound the end of the launch); every other unit after them in unit
+//   order (uv tile by tile, rest-channel block fastest), so that units which share rows,
+//   and the cache lines where a row's records meet, run close together in time.
+//   key: 0x7fffffff - samples for the large units, 0x80000000 for the rest.
+// - A launch of several stacks: every unit by decreasing sample count.  Such stacks differ
+//   in size by orders of magnitude, most of their units are small, and balancing the end of
+//   the launch with the smallest units matters more than locality.  key: ~samples.
+__global__ void k_unit_keys(const LaunchDesc* __restrict__ Lp, const uint32_t* __restrict__ unit_off,
+                            const uint64_t* __restrict__ pre, const int64_t* __restrict__ nunits_dev,
+                            uint32_t* __restrict__ keys, uint64_t* __restrict__ vals) {
     const int64_t nun = *nunits_dev;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u < nun) {
         const uint64_t ns = pre[unit_off[u + 1]] - pre[unit_off[u]];
-        const uint64_t tot = pre[unit_off[nun]] - pre[unit_off[0]];
-        const bool large = (double)ns * (double)nun > 4.0 * (double)tot;
-        keys[u] = large ? 0x7fffffffu - (uint32_t)min(ns, (uint64_t)0x7fffffffu) : 0x80000000u;
+        if (Lp->nstacks > 1) {
+            keys[u] = 0xffffffffu - (uint32_t)min(ns, (uint64_t)0xffffffffu);
+        } else {
+            const uint64_t tot = pre[unit_off[nun]] - pre[unit_off[0]];
+            const bool large = (double)ns * (double)nun > 4.0 * (double)tot;
+            keys[u] = large ? 0x7fffffffu - (uint32_t)min(ns, (uint64_t)0x7fffffffu) : 0x80000000u;
+        }
         vals[u] = (uint64_t)u;
     }
 }
@@ -562,11 +569,12 @@ hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, i
     return exclusive_scan_u32_to_u64(lens, nrec_dev, nrec_cap, pre, sums, stream);
 }
 
-hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, const int64_t* nunits_dev,
-                             int64_t nunits_cap, uint32_t* keys, uint64_t* vals, void* sort_temp, hipStream_t stream) {
+hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, const uint64_t* pre,
+                             const int64_t* nunits_dev, int64_t nunits_cap, uint32_t* keys, uint64_t* vals,
+                             void* sort_temp, hipStream_t stream) {
     if (nunits_cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unit_keys, dim3((unsigned)((nunits_cap + 255) / 256)), dim3(256), 0, stream, unit_off, pre,
-                       nunits_dev, keys, vals);
+    hipLaunchKernelGGL(k_unit_keys, dim3((unsigned)((nunits_cap + 255) / 256)), dim3(256), 0, stream, dL, unit_off,
+                       pre, nunits_dev, keys, vals);
     return radix_sort_pairs(keys, vals, nunits_dev, nunits_cap, 32, sort_temp, stream);
 }
 

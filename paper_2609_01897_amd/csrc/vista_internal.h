@@ -162,10 +162,13 @@ hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_
 // sorted records before i (pre[nrec] = total); lens is nrec u32 of scratch.
 hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, int64_t nrec_cap, uint32_t* lens,
                                 uint64_t* pre, uint64_t* sums, hipStream_t stream);
-// Work list of the packed accumulation: units sorted by descending channel-sample count
-// (keys/vals: nunits entries each, sorted in place; vals end as the unit ids).
-hipError_t launch_unit_order(const uint32_t* unit_off, const uint64_t* pre, const int64_t* nunits_dev,
-                             int64_t nunits_cap, uint32_t* keys, uint64_t* vals, void* sort_temp, hipStream_t stream);
+// Work list of the packed accumulation (keys/vals: nunits entries each, sorted in place;
+// vals end as the unit ids).  One stack in the launch (dL->nstacks): units above four times
+// the mean channel-sample count first, largest first, then the rest in unit order; several
+// stacks: all units by descending channel-sample count.
+hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, const uint64_t* pre,
+                             const int64_t* nunits_dev, int64_t nunits_cap, uint32_t* keys, uint64_t* vals,
+                             void* sort_temp, hipStream_t stream);
 // The packed accumulation (atomic mode): `grid` workgroups of `waves` wavefronts pull units
 // from *counter (zeroed first) in the order of `order` (u64 unit ids, L.nunits of them).
 hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,

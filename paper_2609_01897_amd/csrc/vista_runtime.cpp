@@ -625,7 +625,7 @@ class Launcher {
         check_launch(radix_sort_pairs(keys_, vals_, nrec_dev(), cap_.recs, bits, stmp_, s_), "sort");
         check_launch(launch_unit_offsets(keys_, nrec_dev(), cap_.recs, nunits_dev(), unit_off_, s_), "unit offsets");
         check_launch(launch_record_prefix(vals_, nrec_dev(), cap_.recs, lens_, pre_, psums_, s_), "record prefix");
-        check_launch(launch_unit_order(unit_off_, pre_, nunits_dev(), cap_.units, okeys_, order_, otmp_, s_),
+        check_launch(launch_unit_order(d_L_, unit_off_, pre_, nunits_dev(), cap_.units, okeys_, order_, otmp_, s_),
                      "unit order");
         check_launch(launch_fill_u32(counter_, 0u, 1, s_), "fill");
         if (ev) VISTA_HIP(hipEventRecord(ev->e[1], s_));
