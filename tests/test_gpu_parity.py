@@ -50,6 +50,20 @@ def test_debug_indices_bit_exact():
         assert np.array_equal(gi["nj"], oi["nj"])
 
 
+def test_long_channel_axes():
+    """Targets of 2500 and 4100 channels next to a short one.  Binning stages a block's
+    channel scales in LDS only up to 2048 channels, so these rows search the channel table
+    in global memory instead."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    hs = [synth.make_target(cfg, 0, nchan=2500, n_int=8), synth.make_target(cfg, 1, nchan=4100, n_int=6),
+          synth.make_target(cfg, 2)]
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs])
+    err = compare(o, out, st=st)
+    print(err)
+
+
 def test_boundary_samples_bit_exact():
     """Samples placed exactly on cell edges and one ulp either side of them."""
     cfg = synth.config("small")
