@@ -7,7 +7,7 @@
 // For power-of-two sizes the centring factors split off: multiply the input by
 // (-1)^(iu + iv), take the unnormalised inverse FFT, multiply the output by (-1)^(p + q)
 // and by a constant (-1 per axis of length 2, else 1).  The 2-D transform is done as row
-// transforms then column transforms, each a radix-2 Stockham (self-sorting) FFT in LDS;
+// transforms then column transforms, each a Stockham (self-sorting) FFT in LDS;
 // the column pass stages a tile of adjacent columns so that its loads and stores are
 // contiguous runs.  Nothing here is a matrix product: the work is a few passes over the
 // grid in HBM.
@@ -43,24 +43,54 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
 // `cnt` inverse transforms (exp(+2 pi i ...)) of length n = 2^logn, transform t at
-// x + t * n, ping-ponging between x and y; returns the buffer holding the result.
+// x + t * n, ping-ponging between x and y; returns the buffer holding the result.  Stockham
+// (self-sorting) stages of radix 4, after one radix-2 stage when logn is odd.  A stage of
+// radix r, with m the product of the radices before it and l = n / (r m), maps the inputs
+// c_p = x[k + j m + p l m] (p < r) to y[k + (r j + q) m] = w^(j q) sum_p c_p e^(2 pi i p q / r),
+// w = e^(2 pi i / (r l)), for j < l and k < m.
 __device__ float2* fft_inverse(float2* x, float2* y, int logn, int cnt) {
-    const int n = 1 << logn, half = n >> 1;
-    int l = half, lm = 0;                   // l = n / 2^(s+1); m = 2^s = 1 << lm
-    for (int s = 0; s < logn; ++s, l >>= 1, ++lm) {
-        const int m = 1 << lm;
-        const float inv2l = 1.f / (float)(2 * l);        // exact: 2 l is a power of two
+    const int n = 1 << logn;
+    int lm = 0;                               // m = 2^lm
+    if (logn & 1) {                           // radix 2: m = 1, l = n / 2
+        const int half = n >> 1;
+        const float inv = 1.f / (float)n;      // turns j / (2 l), exact: n is a power of two
         for (int b = threadIdx.x; b < cnt * half; b += blockDim.x) {
-            const int t = b >> (logn - 1), bb = b & (half - 1);
-            const int j = bb >> lm, k = bb & (m - 1);
+            const int t = b >> (logn - 1), j = b & (half - 1);
             const float2* xs = x + t * n;
             float2* ys = y + t * n;
-            const float2 c0 = xs[k + j * m], c1 = xs[k + j * m + l * m];
+            const float2 c0 = xs[j], c1 = xs[j + half];
             float sn, cs;
-            sincos_turns((float)j * inv2l, &sn, &cs);              // exp(+2 pi i j / (2 l))
-            ys[k + 2 * j * m] = make_float2(c0.x + c1.x, c0.y + c1.y);
-            ys[k + 2 * j * m + m] = cmul(make_float2(c0.x - c1.x, c0.y - c1.y), make_float2(cs, sn));
+            sincos_turns((float)j * inv, &sn, &cs);
+            ys[2 * j] = cadd(c0, c1);
+            ys[2 * j + 1] = cmul(csub(c0, c1), make_float2(cs, sn));
+        }
+        lds_barrier();
+        float2* t = x; x = y; y = t;
+        lm = 1;
+    }
+    const int q4 = n >> 2;                    // l m of a radix-4 stage
+    for (; lm < logn; lm += 2) {
+        const int m = 1 << lm;
+        const float inv4l = 1.f / (float)(n >> lm);    // 1 / (4 l), exact
+        for (int b = threadIdx.x; b < cnt * q4; b += blockDim.x) {
+            const int t = b >> (logn - 2), bb = b & (q4 - 1);
+            const int j = bb >> lm, k = bb & (m - 1);
+            const float2* xs = x + t * n + k + j * m;
+            const float2 c0 = xs[0], c1 = xs[q4], c2 = xs[2 * q4], c3 = xs[3 * q4];
+            const float2 a = cadd(c0, c2), bq = csub(c0, c2), c = cadd(c1, c3);
+            const float2 e = csub(c1, c3), d = make_float2(-e.y, e.x);      // i (c1 - c3)
+            float sn, cs;
+            sincos_turns((float)j * inv4l, &sn, &cs);
+            const float2 w1 = make_float2(cs, sn), w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+            float2* ys = y + t * n + k + 4 * j * m;
+            ys[0] = cadd(a, c);
+            ys[m] = cmul(cadd(bq, d), w1);
+            ys[2 * m] = cmul(csub(a, c), w2);
+            ys[3 * m] = cmul(csub(bq, d), w3);
         }
         lds_barrier();
         float2* t = x; x = y; y = t;
