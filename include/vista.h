@@ -193,8 +193,10 @@ int vista_stack_destroy(vista_stack* s);
 /* Stacks keep a per-thread launch workspace between calls -- row contexts, binning records,
  * sort scratch and the work list, sized by the largest launch seen (about 80 B per row and
  * 50 B per binning record), for at most two launch shapes -- so that consecutive stacks on
- * one thread neither allocate nor free device memory.  This frees the calling thread's
- * workspace (the next stack allocates it again).  It waits for the device.  Errors: HIP. */
+ * one thread neither allocate nor free device memory.  Every launch (stacks and batches)
+ * also keeps the host buffers of its channel tables on the calling thread (about 40 B per
+ * channel of the largest launch).  This frees both for the calling thread (the next launch
+ * allocates them again).  It waits for the device.  Errors: HIP. */
 int vista_release_workspace(void);
 
 /* Batched form: n_stacks independent stacks (each with its own grid g[i]) run in one

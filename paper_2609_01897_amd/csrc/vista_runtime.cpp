@@ -339,7 +339,29 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Host side of one launch: the descriptors and tables of its stacks and targets, packed
 // for one upload.  Target data pointers (uvw, vis, weight, flag) are set by the caller.
+// Host buffers of the launch tables, kept per thread between launches: tables of many
+// targets run to tens of MB, and fresh allocations of that size come from the system
+// zero-filled and fault in page by page on every launch.
+struct HostScratch {
+    std::vector<unsigned char> arena;         // spare arena, handed to the next launch
+    std::vector<DevChan> chan;
+    std::vector<float> f1, fval;
+    std::vector<int32_t> foff;
+};
+static thread_local HostScratch t_host;
+
 struct HostLaunch {
+    HostLaunch() = default;
+    HostLaunch(HostLaunch&&) = default;
+    HostLaunch& operator=(HostLaunch&&) = default;
+    HostLaunch(const HostLaunch&) = delete;
+    HostLaunch& operator=(const HostLaunch&) = delete;
+    ~HostLaunch() {
+        if (arena.capacity() > t_host.arena.capacity()) {
+            arena.clear();
+            t_host.arena.swap(arena);
+        }
+    }
     std::vector<DevTarget> dts;
     std::vector<DevStack> dss;
     std::vector<int64_t> row_base, tile_base, unit_base;
@@ -360,16 +382,24 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
         plan_all(all);
     }
     HostLaunch h;
+    h.arena.swap(t_host.arena);
+    h.arena.clear();
     auto put = [&h](const void* p, size_t n) {
         size_t off = align256(h.arena.size());
-        h.arena.resize(off + n);
-        if (n) memcpy(h.arena.data() + off, p, n);
+        h.arena.resize(off);
+        const unsigned char* b = (const unsigned char*)p;
+        if (n) h.arena.insert(h.arena.end(), b, b + n);
         return off;
     };
     // launch-wide channel tables: target i's entries start at its chan0
-    std::vector<DevChan> chan_all;
-    std::vector<float> f1_all, fval_all;
-    std::vector<int32_t> foff_all;
+    std::vector<DevChan>& chan_all = t_host.chan;
+    std::vector<float>& f1_all = t_host.f1;
+    std::vector<float>& fval_all = t_host.fval;
+    std::vector<int32_t>& foff_all = t_host.foff;
+    chan_all.clear();
+    f1_all.clear();
+    fval_all.clear();
+    foff_all.clear();
     int64_t tiles = 0;
     h.dss.resize(jobs.size());
     for (size_t s = 0; s < jobs.size(); ++s) {
@@ -1027,6 +1057,7 @@ const char* vista_last_error(void) { return g_err.c_str(); }
 int vista_release_workspace(void) {
     return guarded(nullptr, [&]() -> int {
         t_workspaces.clear();
+        t_host = HostScratch();
         return VISTA_OK;
     });
 }
