@@ -426,8 +426,8 @@ def main():
                          "hardware byte counters), and print its bytes and time")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes "
-              "for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the design notes "
+              "describe how the work would shard)", file=sys.stderr)
         sys.exit(2)
 
     import torch
