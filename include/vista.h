@@ -167,9 +167,12 @@ typedef struct vista_batch vista_batch;
  * when the stack is finalized.  Errors: VISTA_E_ARG (NULL pointer, bad grid), NOMEM. */
 int vista_stack_create(const vista_grid_desc* g, void* hip_stream, vista_stack** out);
 
-/* Add one target.  Host planning runs here (rest-frame edges, Eq. 3-4 overlap table,
- * a_k = nu_k / c); device work is deferred to vista_stack_finalize, which stacks all
- * targets in one pass.  VISTA_MEM_HOST data are copied to library staging before the
+/* Add one target.  The arguments are validated and the channel axis copied here; the host
+ * planning (rest-frame edges, Eq. 3-4 overlap table, a_k = nu_k / c) runs at finalize,
+ * for all targets at once on several threads, except for a target whose widest rest-frame
+ * channel could overlap more rest channels than the overlap table holds: that one is
+ * planned and checked here.  Device work is deferred to vista_stack_finalize, which stacks
+ * all targets in one pass.  VISTA_MEM_HOST data are copied to library staging before the
  * call returns; VISTA_MEM_HOST_PINNED and VISTA_MEM_DEVICE data must stay valid and
  * unchanged until finalize returns.  Errors: ARG (see vista_target), STATE (after
  * finalize or poisoned), NOMEM, HIP. */
