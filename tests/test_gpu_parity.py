@@ -311,10 +311,10 @@ def test_copy_kernel_copies_every_vector(n16):
 
 
 def test_workspace_reuse_across_sizes_shapes_and_streams():
-    """Consecutive stacks on one thread reuse the cached launch workspace: a larger launch
-    after a smaller one (buffers grow), a smaller one after it, another launch shape (a
-    second workspace), another stream, and a release in between all give the oracle's
-    result."""
+    """Consecutive stacks on one thread reuse the cached launch workspace (device buffers,
+    and the host buffers the channel tables are built in): a larger launch after a smaller
+    one (buffers grow), a smaller one after it, another launch shape (a second workspace),
+    another stream, and a release in between all give the oracle's result."""
     small_cfg, big_cfg = synth.config("tiny"), synth.config("small")
     cases = []
     for cfg in (small_cfg, big_cfg, small_cfg):
