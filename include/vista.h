@@ -168,10 +168,10 @@ typedef struct vista_batch vista_batch;
 int vista_stack_create(const vista_grid_desc* g, void* hip_stream, vista_stack** out);
 
 /* Add one target.  The arguments are validated and the channel axis copied here; the host
- * planning (rest-frame edges, Eq. 3-4 overlap table, a_k = nu_k / c) runs at finalize,
- * for all targets at once on several threads, except for a target whose widest rest-frame
- * channel could overlap more rest channels than the overlap table holds: that one is
- * planned and checked here.  Device work is deferred to vista_stack_finalize, which stacks
+ * planning (rest-frame edges, Eq. 3-4 overlap table, a_k = nu_k / c) is handed to a pool
+ * of library threads and runs while the caller adds more targets (finalize waits for it and
+ * reports its errors), except for a target whose widest rest-frame channel could overlap
+ * more rest channels than the overlap table holds: that one is planned and checked here.  Device work is deferred to vista_stack_finalize, which stacks
  * all targets in one pass.  VISTA_MEM_HOST data are copied to library staging before the
  * call returns; VISTA_MEM_HOST_PINNED and VISTA_MEM_DEVICE data must stay valid and
  * unchanged until finalize returns.  Errors: ARG (see vista_target), STATE (after

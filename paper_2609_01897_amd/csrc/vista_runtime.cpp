@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <exception>
 #include <thread>
 #include <cmath>
@@ -18,6 +20,8 @@
 #include <numeric>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "vista.h"
 #include "vista_internal.h"
@@ -150,6 +154,15 @@ struct HostTarget {
     std::vector<double> freq, width;
     std::vector<unsigned char> staging;   // VISTA_MEM_HOST data: uvw | vis | weight | flag
     uint64_t n_samples = 0, n_outside_band = 0;
+    // planning handed to the planning pool when the target was added
+    std::mutex pm;
+    std::condition_variable pcv;
+    int pstate = 0;                       // 0 not handed over, 1 queued or running, 2 done
+    std::exception_ptr perr;
+    ~HostTarget() {
+        std::unique_lock<std::mutex> lk(pm);
+        pcv.wait(lk, [this] { return pstate != 1; });
+    }
 };
 
 static void finish_plan(HostTarget& h) {
@@ -158,9 +171,97 @@ static void finish_plan(HostTarget& h) {
     h.planned = true;
 }
 
+// Host threads that plan the targets handed over by add_target, so that planning runs while
+// the caller goes on adding targets.  Created on first use and never destroyed (its threads
+// wait for work until the process ends); a forked child, which has none of them, builds its
+// own.
+class PlanPool {
+public:
+    // The pool, or nullptr when no thread could be started (callers then plan at launch).
+    static PlanPool* get() {
+        static std::mutex m;
+        static PlanPool* pool = nullptr;
+        std::lock_guard<std::mutex> lk(m);
+        if (!pool || pool->pid_ != getpid()) {
+            PlanPool* p = new PlanPool();
+            if (!p->start()) return nullptr;            // nothing waits on it: left alone
+            pool = p;
+        }
+        return pool;
+    }
+    void submit(HostTarget* h) {
+        {
+            std::lock_guard<std::mutex> lk(h->pm);
+            h->pstate = 1;
+        }
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            q_.push_back(h);
+        }
+        cv_.notify_one();
+    }
+
+private:
+    PlanPool() : pid_(getpid()) {}
+    bool start() {
+        const unsigned n = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+        unsigned started = 0;
+        try {
+            for (; started < n; ++started) std::thread([this] { loop(); }).detach();
+        } catch (...) {
+        }
+        return started > 0;
+    }
+    void loop() {
+        for (;;) {
+            HostTarget* h;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [this] { return !q_.empty(); });
+                h = q_.front();
+                q_.pop_front();
+            }
+            std::exception_ptr e;
+            try {
+                finish_plan(*h);
+            } catch (...) {
+                e = std::current_exception();
+            }
+            // notified under the lock: the waiter may destroy *h as soon as it is released
+            std::lock_guard<std::mutex> lk(h->pm);
+            h->perr = e;
+            h->pstate = 2;
+            h->pcv.notify_all();
+        }
+    }
+    pid_t pid_;
+    std::mutex m_;
+    std::condition_variable cv_;
+    std::deque<HostTarget*> q_;
+};
+
+// Hand an added target's planning to the pool (planned at launch when there is none).
+static void plan_in_background(HostTarget* h) {
+    if (h->planned) return;
+    if (PlanPool* p = PlanPool::get()) p->submit(h);
+}
+
+// Wait for a target handed to the pool; a planning error is rethrown here, once.
+static void wait_plan(HostTarget& h) {
+    std::unique_lock<std::mutex> lk(h.pm);
+    h.pcv.wait(lk, [&h] { return h.pstate != 1; });
+    if (h.perr) {
+        std::exception_ptr e = h.perr;
+        h.perr = nullptr;
+        h.pstate = 0;
+        std::rethrow_exception(e);
+    }
+}
+
 // Plan every target not yet planned, on up to 16 host threads (the channel tables of many
 // targets are independent).
 static void plan_all(const std::vector<HostTarget*>& hs) {
+    for (HostTarget* h : hs) wait_plan(*h);        // those handed to the pool at add time
     std::vector<HostTarget*> todo;
     for (HostTarget* h : hs)
         if (!h->planned) todo.push_back(h);
@@ -1090,6 +1191,8 @@ int vista_stack_add_target(vista_stack* s, const vista_target* t) {
         copy_target(*h, &s->g, t);
         std::string w;
         if (h->planned && !check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
+        s->targets.reserve(s->targets.size() + 1);
+        plan_in_background(h.get());
         s->targets.push_back(std::move(h));
         return VISTA_OK;
     });
@@ -1468,6 +1571,8 @@ int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t)
         copy_target(*h, &b->g[stack], t);
         std::string w;
         if (h->planned && !check_plan(h->plan, &w)) return fail(VISTA_E_ARG, w);
+        b->targets[stack].reserve(b->targets[stack].size() + 1);
+        plan_in_background(h.get());
         b->targets[stack].push_back(std::move(h));
         return VISTA_OK;
     });
