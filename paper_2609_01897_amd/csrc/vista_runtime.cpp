@@ -445,9 +445,6 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // zero-filled and fault in page by page on every launch.
 struct HostScratch {
     std::vector<unsigned char> arena;         // spare arena, handed to the next launch
-    std::vector<DevChan> chan;
-    std::vector<float> f1, fval;
-    std::vector<int32_t> foff;
 };
 static thread_local HostScratch t_host;
 
@@ -458,10 +455,7 @@ struct HostLaunch {
     HostLaunch(const HostLaunch&) = delete;
     HostLaunch& operator=(const HostLaunch&) = delete;
     ~HostLaunch() {
-        if (arena.capacity() > t_host.arena.capacity()) {
-            arena.clear();
-            t_host.arena.swap(arena);
-        }
+        if (arena.capacity() > t_host.arena.capacity()) t_host.arena.swap(arena);
     }
     std::vector<DevTarget> dts;
     std::vector<DevStack> dss;
@@ -483,24 +477,43 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
         plan_all(all);
     }
     HostLaunch h;
-    h.arena.swap(t_host.arena);
-    h.arena.clear();
-    auto put = [&h](const void* p, size_t n) {
-        size_t off = align256(h.arena.size());
-        h.arena.resize(off);
-        const unsigned char* b = (const unsigned char*)p;
-        if (n) h.arena.insert(h.arena.end(), b, b + n);
-        return off;
+    // The arena: the launch-wide channel tables (target i's entries start at its chan0),
+    // then each target's block and in-band tables, every table 256-byte aligned.  Sized
+    // first, then written in place.  The buffer is recycled, so only its growth is
+    // zero-filled; padding between tables is never read.
+    int64_t nch = 0, nfv = 0;
+    size_t small = 0;
+    for (const StackJob& J : jobs) {
+        const int64_t nb = (J.g->nchan + tu.jc - 1) / tu.jc, nsb = (J.g->nchan + jsub - 1) / jsub;
+        for (const HostTarget* ht : J.targets) {
+            if (ht->t.nrow == 0) continue;
+            nch += (int64_t)ht->plan.chan.size();
+            nfv += (int64_t)ht->plan.fval.size();
+            small += align256(2 * nb * sizeof(int32_t)) + align256((ht->plan.inband.size()) * sizeof(int32_t));
+            if (jsub != tu.jc) small += align256(2 * nsb * sizeof(int32_t));
+        }
+    }
+    if (nch >= 0x7fffffffLL || nfv >= 0x7fffffffLL) throw HipFail{hipErrorInvalidValue, "too many channels in one launch"};
+    size_t cur = 0;
+    auto take = [&cur](size_t n) {
+        const size_t o = cur;
+        cur = align256(cur + n);
+        return o;
     };
-    // launch-wide channel tables: target i's entries start at its chan0
-    std::vector<DevChan>& chan_all = t_host.chan;
-    std::vector<float>& f1_all = t_host.f1;
-    std::vector<float>& fval_all = t_host.fval;
-    std::vector<int32_t>& foff_all = t_host.foff;
-    chan_all.clear();
-    f1_all.clear();
-    fval_all.clear();
-    foff_all.clear();
+    h.o_chan = take((size_t)nch * sizeof(DevChan));
+    h.o_f1 = take((size_t)nch * sizeof(float));
+    h.o_foff = take((size_t)nch * sizeof(int32_t));
+    h.o_fval = take((size_t)nfv * sizeof(float));
+    h.arena.swap(t_host.arena);
+    h.arena.resize(std::max<size_t>(cur + small, 256));
+    unsigned char* const A = h.arena.data();
+    auto put = [&](const void* p, size_t n) {
+        const size_t o = take(n);
+        if (o + n > h.arena.size()) throw HipFail{hipErrorInvalidValue, "launch table sizes disagree"};
+        if (n) memcpy(A + o, p, n);
+        return o;
+    };
+    int64_t chan0 = 0, fval0 = 0;
     int64_t tiles = 0;
     h.dss.resize(jobs.size());
     for (size_t s = 0; s < jobs.size(); ++s) {
@@ -548,15 +561,18 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
             T.l = ht->plan.frame.l; T.m = ht->plan.frame.m; T.nm1 = ht->plan.nm1;
             T.rotate = ht->plan.frame.rotate;
             for (int q = 0; q < 6; ++q) T.rot[q] = ht->plan.frame.R[q];
-            T.chan0 = (int32_t)chan_all.size();
-            chan_all.insert(chan_all.end(), ht->plan.chan.begin(), ht->plan.chan.end());
-            f1_all.insert(f1_all.end(), ht->plan.f1.begin(), ht->plan.f1.end());
-            for (int32_t f : ht->plan.foff) foff_all.push_back(f + (int32_t)fval_all.size());
-            fval_all.insert(fval_all.end(), ht->plan.fval.begin(), ht->plan.fval.end());
+            T.chan0 = (int32_t)chan0;
+            const size_t nc = ht->plan.chan.size();
+            memcpy(A + h.o_chan + chan0 * sizeof(DevChan), ht->plan.chan.data(), nc * sizeof(DevChan));
+            memcpy(A + h.o_f1 + chan0 * sizeof(float), ht->plan.f1.data(), nc * sizeof(float));
+            int32_t* foff = (int32_t*)(A + h.o_foff) + chan0;
+            for (size_t k = 0; k < nc; ++k) foff[k] = ht->plan.foff[k] + (int32_t)fval0;
+            if (!ht->plan.fval.empty())
+                memcpy(A + h.o_fval + fval0 * sizeof(float), ht->plan.fval.data(), ht->plan.fval.size() * sizeof(float));
+            chan0 += (int64_t)nc;
+            fval0 += (int64_t)ht->plan.fval.size();
             if (!ht->t.flag)
                 h.zero_flag_bytes = std::max<int64_t>(h.zero_flag_bytes, (int64_t)ht->t.nchan * ht->t.npol);
-            if (chan_all.size() >= 0x7fffffffu || fval_all.size() >= 0x7fffffffu)
-                throw HipFail{hipErrorInvalidValue, "too many channels in one launch"};
             if (T.npol != 2 || T.weight_per_chan) h.npol_all = 0;   // the specialised path: 2 pols, row weights
             HostLaunch::Offs o;
             std::vector<int32_t> blk = block_ranges(ht->plan, g->nchan, tu.jc);
@@ -581,10 +597,7 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
     h.unit_base.push_back(h.nunits);
     if (h.rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
     if (h.nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
-    h.o_chan = put(chan_all.data(), chan_all.size() * sizeof(DevChan));
-    h.o_f1 = put(f1_all.data(), f1_all.size() * sizeof(float));
-    h.o_foff = put(foff_all.data(), foff_all.size() * sizeof(int32_t));
-    h.o_fval = put(fval_all.data(), fval_all.size() * sizeof(float));
+    h.arena.resize(std::max<size_t>(cur, 256));
     return h;
 }
 
