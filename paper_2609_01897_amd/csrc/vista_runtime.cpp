@@ -204,7 +204,9 @@ public:
 private:
     PlanPool() : pid_(getpid()) {}
     bool start() {
-        const unsigned n = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+        // half the cores, at most 8: planning keeps up with the caller's adds, and the
+        // caller keeps a core of its own
+        const unsigned n = std::min(8u, std::max(1u, std::thread::hardware_concurrency() / 2));
         unsigned started = 0;
         try {
             for (; started < n; ++started) std::thread([this] { loop(); }).detach();
