@@ -267,3 +267,47 @@ def test_too_fine_rest_grid_refused_at_add():
         s.add(t)
     assert e.value.code == vista.VISTA_E_ARG and "255" in str(e.value)
     s.close()
+
+
+
+def _stack_and_drop(g, targets):
+    s = vista.Stack(g)
+    try:
+        for t in targets:
+            s.add(t)
+    finally:
+        s.close()
+
+
+def test_background_planning_survives_drop_and_fork():
+    """Targets are planned on library threads from add time on.  Dropping a stack right
+    after its adds waits for that planning; a forked child, which has none of the parent's
+    threads, plans on a pool of its own.  (The inputs are drawn before the fork: the child
+    runs only the library.)"""
+    import os
+    import signal
+    import time
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    targets = [synth.make_target(cfg, i) for i in range(6)]
+    for _ in range(3):
+        _stack_and_drop(g, targets)
+    pid = os.fork()
+    if pid == 0:
+        code = 1
+        try:
+            _stack_and_drop(g, targets)
+            code = 0
+        finally:
+            os._exit(code)
+    deadline = time.time() + 60
+    while True:
+        done, status = os.waitpid(pid, os.WNOHANG)
+        if done:
+            break
+        if time.time() > deadline:
+            os.kill(pid, signal.SIGKILL)
+            os.waitpid(pid, 0)
+            pytest.fail("the forked child did not finish its adds")
+        time.sleep(0.05)
+    assert os.WIFEXITED(status) and os.WEXITSTATUS(status) == 0
