@@ -335,3 +335,41 @@ def test_workspace_reuse_across_sizes_shapes_and_streams():
     vista.release_workspace()
     out, st = gpu_stack(g, ds)
     compare(o, out, st=st)
+
+
+def test_two_threads_stack_at_once():
+    """Different handles on different host threads, each on a stream of its own, at the
+    same time (each thread keeps its own workspace; the planning pool is shared): both
+    results equal the oracle's, several times over."""
+    import threading
+    jobs = []
+    for name in ("small", "c1"):
+        cfg = synth.config(name)
+        hs, ds = targets_on_gpu(cfg)
+        g = synth.make_grid(cfg)
+        jobs.append((g, hs, ds, oracle.stack(g, hs)))
+    results = [[None] * 3 for _ in jobs]
+    errors = []
+
+    def work(i):
+        g, hs, ds, o = jobs[i]
+        try:
+            s = torch.cuda.Stream()
+            for rep in range(3):
+                with torch.cuda.stream(s):
+                    out, st = vista.stack(g, ds)
+                s.synchronize()
+                results[i][rep] = ({k: v.cpu().numpy() for k, v in out.items()}, st)
+        except Exception as e:          # reported by the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(jobs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=240)
+    assert not any(t.is_alive() for t in th), "a stacking thread did not finish"
+    assert not errors, errors
+    for (g, hs, ds, o), res in zip(jobs, results):
+        for out, st in res:
+            compare(o, out, st=st)
