@@ -123,7 +123,6 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
                                            Acc* s_im, Acc* s_w, uint32_t* s_n,
                                            const float* c_re, const float* c_im, const float* c_w) {
     const int32_t nu = S.nu, nv = S.nv;
-    const size_t plane = (size_t)S.nchan * nv * nu;
     VISTA_GLOBAL float2* const o_vis = (VISTA_GLOBAL float2*)S.out_vis;
     VISTA_GLOBAL float* const o_w = (VISTA_GLOBAL float*)S.out_w;
     VISTA_GLOBAL uint32_t* const o_cnt = (VISTA_GLOBAL uint32_t*)S.out_cnt;
@@ -134,6 +133,10 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
     VISTA_GLOBAL uint32_t* const st_n = (VISTA_GLOBAL uint32_t*)S.st_n;
     unsigned long long* const stats = S.stats;
     const int carry = S.carry, kahan = L.kahan, last = S.last;
+    // the unit's block of the carried state: unit (tile, b) of this stack, TU x TV x jc cells
+    const size_t splane = (size_t)S.st_plane;
+    const size_t sbase = ((size_t)((tv0 / TV) * S.tiles_u + tu0 / TU) * (size_t)S.nblocks + (size_t)(jb0 / L.jc)) *
+                         (size_t)(TU * TV * L.jc);
     const int ncv = (jb1 - jb0) * TV * TU;
     for (int i = threadIdx.x; i < ncv; i += blockDim.x) {
         const int lu = i % TU;
@@ -157,29 +160,30 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
         }
         if (carry) {
             // merge into the state carried across passes
+            const size_t os = sbase + (size_t)i;        // the unit's state block, contiguous in i
             double vals3[3] = {dre, dim, dw};
             for (int q = 0; q < 3; ++q) {
                 const float x = (float)vals3[q];
-                float sv = st_s[q * plane + o];
+                float sv = st_s[q * splane + os];
                 if (kahan) {
-                    float cc = st_c[q * plane + o];
+                    float cc = st_c[q * splane + os];
                     const float xl = (float)(vals3[q] - (double)x);   // the part lost to FP32
                     float y = x - cc;
                     float t = sv + y;
                     cc = (t - sv) - y;
                     sv = t;
                     y = xl - cc; t = sv + y; cc = (t - sv) - y; sv = t;
-                    st_c[q * plane + o] = cc;
+                    st_c[q * splane + os] = cc;
                     vals3[q] = (double)sv - (double)cc;
                 } else {
                     sv = sv + x;
                     vals3[q] = sv;
                 }
-                st_s[q * plane + o] = sv;
+                st_s[q * splane + os] = sv;
             }
-            const uint64_t nn = (uint64_t)st_n[o] + n;
+            const uint64_t nn = (uint64_t)st_n[os] + n;
             if (nn > 0xffffffffull) atomicOr(&stats[7], 1ull);
-            st_n[o] = (uint32_t)nn;
+            st_n[os] = (uint32_t)nn;
             if (!last) continue;
             dre = vals3[0]; dim = vals3[1]; dw = vals3[2]; n = (uint32_t)nn;
         }

@@ -83,10 +83,13 @@ struct DevStack {
     double* out_w64;
     unsigned long long* stats;  // [8]: samples, flagged, bad weight, outside uv,
                                 //      outside band, used, contrib, overflow flag
-    // grid state carried across the waves of a streamed batch (nullptr otherwise)
-    float* st_s;              // [3][nchan][nv][nu]: re, im, w
-    float* st_c;              // [3][nchan][nv][nu]: Kahan compensations
-    uint32_t* st_n;           // [nchan][nv][nu]
+    // grid state carried across the waves of a streamed batch (nullptr otherwise), laid
+    // out unit by unit: unit u = tile * nblocks + b holds its tu x tv x jc cells at
+    // [u][jl][lv][lu], so that a unit reads and writes its state as one contiguous block
+    float* st_s;              // [3][st_plane]: re, im, w
+    float* st_c;              // [3][st_plane]: Kahan compensations
+    uint32_t* st_n;           // [st_plane]
+    int64_t st_plane;         // tiles_u * tiles_v * nblocks * tu * tv * jc
     int32_t carry;            // 1: merge this launch's sums into the carried state
     int32_t last;             // with carry: this is the stack's last wave, write outputs
 };

@@ -472,6 +472,14 @@ struct HostLaunch {
     int npol_all = 2;
 };
 
+// Cells of one plane of a stack's carried state: every (tile, block) unit's full
+// tu x tv x jc block, edge units included.
+static int64_t carried_state_cells(const vista_grid_desc& g, const Tuning& tu) {
+    const int64_t tiles = (int64_t)((g.nu + tu.tu - 1) / tu.tu) * ((g.nv + tu.tv - 1) / tu.tv);
+    const int64_t nblocks = (g.nchan + tu.jc - 1) / tu.jc;
+    return tiles * nblocks * tu.tu * tu.tv * tu.jc;
+}
+
 static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& tu, int jsub) {
     {
         std::vector<HostTarget*> all;
@@ -539,6 +547,7 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
         S.st_s = jobs[s].st_s;
         S.st_c = jobs[s].st_c;
         S.st_n = jobs[s].st_n;
+        S.st_plane = carried_state_cells(*g, tu);
         S.carry = jobs[s].carry;
         S.last = jobs[s].last;
         h.stats_index.push_back(jobs[s].index);
@@ -1715,8 +1724,7 @@ int vista_batch_run(vista_batch* b) {
         std::vector<uint32_t*> cs_n(ns, nullptr);
         for (size_t s = 0; s < ns; ++s) {
             if (nwaves[s] < 2) continue;
-            const vista_grid_desc& g = b->g[s];
-            const int64_t nc = (int64_t)g.nu * g.nv * g.nchan;
+            const int64_t nc = carried_state_cells(b->g[s], b->tune);
             cs_s[s] = b->keep->alloc_n<float>(3 * nc);
             cs_n[s] = b->keep->alloc_n<uint32_t>(nc);
             if (kahan) cs_c[s] = b->keep->alloc_n<float>(3 * nc);
@@ -1736,8 +1744,7 @@ int vista_batch_run(vista_batch* b) {
         VISTA_HIP(hipStreamWaitEvent(g.s, e_in, 0));
         for (size_t s = 0; s < ns; ++s) {
             if (!cs_s[s]) continue;
-            const vista_grid_desc& gd = b->g[s];
-            const int64_t nc = (int64_t)gd.nu * gd.nv * gd.nchan;
+            const int64_t nc = carried_state_cells(b->g[s], b->tune);
             check_launch(launch_fill_u32((uint32_t*)cs_s[s], 0u, 3 * nc, st), "fill");
             check_launch(launch_fill_u32(cs_n[s], 0u, nc, st), "fill");
             if (cs_c[s]) check_launch(launch_fill_u32((uint32_t*)cs_c[s], 0u, 3 * nc, st), "fill");
