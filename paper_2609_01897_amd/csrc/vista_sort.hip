@@ -26,20 +26,25 @@ constexpr int kSortTile = kSortThreads * kSortItems;   // records per block
 constexpr int kRadix = 256;
 
 __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t x, uint64_t* sh, uint64_t* total) {
-    // sh: kScanThreads entries
-    const int t = threadIdx.x;
-    sh[t] = x;
-    __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-        uint64_t y = t >= o ? sh[t - o] : 0;
-        __syncthreads();
-        sh[t] += y;
-        __syncthreads();
+    // sh: at least kScanThreads / 64 entries.  Inclusive scan in each wavefront by shuffles,
+    // then the wavefront totals through LDS.
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint64_t inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
     }
-    uint64_t incl = sh[t];
-    *total = sh[kScanThreads - 1];
+    if (lane == 63) sh[w] = inc;
     __syncthreads();
-    return incl - x;
+    uint64_t before = 0, all = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        const uint64_t s = sh[k];
+        if (k < w) before += s;
+        all += s;
+    }
+    *total = all;
+    __syncthreads();                      // sh is free again when this returns
+    return before + inc - x;
 }
 
 // Per-block totals of in[0, n).
@@ -74,28 +79,40 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint64_t* __restrict
     if (threadIdx.x == 0) sums[nb] = carry;
 }
 
-// out[e] = sums[block] + exclusive prefix inside the block; out[n] = total.
+// out[e] = sums[block] + exclusive prefix inside the block; out[n] = total.  The tile goes
+// through LDS both ways, so that global loads and stores are coalesced while each thread
+// scans kScanItems consecutive items (element e of the tile at LDS index e + e / 16, which
+// keeps a thread's consecutive items off one bank).
 template <class T, class U>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T* __restrict__ in, const int64_t* __restrict__ n_dev,
                                                               int64_t n_host, const uint64_t* __restrict__ sums,
                                                               int64_t nb, U* __restrict__ out) {
     __shared__ uint64_t sh[kScanThreads];
-    int64_t n = n_dev ? *n_dev : n_host;
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
-    // blocked arrangement inside the block: thread t owns items [t*I, t*I + I)
+    __shared__ uint64_t tile[kScanTile + kScanTile / 16];
+    const int64_t n = n_dev ? *n_dev : n_host;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    auto at = [](int e) { return e + (e >> 4); };
+    for (int i = 0; i < kScanItems; ++i) {
+        const int e = i * kScanThreads + (int)threadIdx.x;
+        tile[at(e)] = base + e < n ? (uint64_t)in[base + e] : 0;
+    }
+    __syncthreads();
     uint64_t v[kScanItems];
     uint64_t acc = 0;
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t e = base + (int64_t)threadIdx.x * kScanItems + i;
-        v[i] = e < n ? (uint64_t)in[e] : 0;
+        v[i] = tile[at((int)threadIdx.x * kScanItems + i)];
         acc += v[i];
     }
     uint64_t tot;
     uint64_t ex = block_exclusive_u64(acc, sh, &tot) + sums[blockIdx.x];
     for (int i = 0; i < kScanItems; ++i) {
-        int64_t e = base + (int64_t)threadIdx.x * kScanItems + i;
-        if (e < n) out[e] = (U)ex;
+        tile[at((int)threadIdx.x * kScanItems + i)] = ex;
         ex += v[i];
+    }
+    __syncthreads();
+    for (int i = 0; i < kScanItems; ++i) {
+        const int e = i * kScanThreads + (int)threadIdx.x;
+        if (base + e < n) out[base + e] = (U)tile[at(e)];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (U)sums[nb];
 }
