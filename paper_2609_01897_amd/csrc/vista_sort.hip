@@ -6,9 +6,9 @@
 //
 // Radix sort: 8-bit digits, least significant first.  Each pass is a stable counting
 // sort: per-block digit histograms -> exclusive scan of the digit-major histogram matrix
-// -> scatter with ranks that are stable inside the block (items are visited in index
-// order: slot, wave, lane; equal digits inside a wave are matched with ballots), staged
-// in LDS so that each digit's run of the block is written contiguously.
+// -> scatter with ranks that are stable inside the block (each wavefront ranks a contiguous
+// slice of the block; equal digits inside a wavefront's slot are matched with ballots),
+// staged in LDS so that each digit's run of the block is written contiguously.
 #include <hip/hip_runtime.h>
 
 #include "vista_internal.h"
@@ -134,26 +134,27 @@ __global__ void __launch_bounds__(kSortThreads) k_rs_hist(const uint32_t* __rest
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter of one tile: every record is ranked among the tile's records of its digit (in
-// index order: slot, wave, lane, so the sort is stable), placed at that rank in LDS, and
-// the tile is then written out from LDS digit run by digit run, so that consecutive
-// threads store to consecutive addresses.
+// Scatter of one tile: every record is ranked among the tile's records of its digit, placed
+// at that rank in LDS, and the tile is then written out from LDS digit run by digit run, so
+// that consecutive threads store to consecutive addresses.  Wavefront w takes the tile's
+// w-th slice of kSortItems * 64 records (slot by slot, lanes in order) and ranks them with
+// counters of its own, so the slots need no workgroup barrier; the slices' counts are
+// combined per digit once.  Ranks follow the tile's index order: the sort is stable.
 __global__ void __launch_bounds__(kSortThreads) k_rs_scatter(const uint32_t* __restrict__ kin, const uint64_t* __restrict__ vin,
                                                              const int64_t* __restrict__ n_dev, int64_t n_host, int shift,
                                                              const uint32_t* __restrict__ hist,
                                                              const uint32_t* __restrict__ off, int64_t nblocks,
                                                              uint32_t* __restrict__ kout, uint64_t* __restrict__ vout) {
     constexpr int NW = kSortThreads / 64;
+    constexpr int kSlice = kSortItems * 64;   // records of one wavefront's slice
     static_assert(kSortThreads == kRadix, "one thread per digit");
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t wcnt[NW][kRadix];
-    __shared__ uint32_t wbase[NW][kRadix];
-    __shared__ uint32_t lstart[kRadix];    // start of each digit's run in the tile
-    __shared__ uint32_t gstart[kRadix];    // where that run goes in the output
+    __shared__ uint32_t wcnt[NW][kRadix];      // per slice: running count, then the slice's base
+    __shared__ uint32_t lstart[kRadix];        // start of each digit's run in the tile
+    __shared__ uint32_t gstart[kRadix];        // where that run goes in the output
     __shared__ uint32_t wtot[NW];
     __shared__ uint32_t sk[kSortTile];
     __shared__ uint64_t sv[kSortTile];
-    int64_t n = n_dev ? *n_dev : n_host;
+    const int64_t n = n_dev ? *n_dev : n_host;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     {
@@ -167,7 +168,6 @@ __global__ void __launch_bounds__(kSortThreads) k_rs_scatter(const uint32_t* __r
             if (lane >= o) x += y;
         }
         if (lane == 63) wtot[wave] = x;
-        run[threadIdx.x] = 0;
         for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
         __syncthreads();
         uint32_t add = 0;
@@ -176,47 +176,55 @@ __global__ void __launch_bounds__(kSortThreads) k_rs_scatter(const uint32_t* __r
     }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t sbase = base + (int64_t)wave * kSlice;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kSortItems], rank[kSortItems];
+    uint64_t val[kSortItems];
     for (int s = 0; s < kSortItems; ++s) {
-        int64_t e = base + (int64_t)s * kSortThreads + threadIdx.x;
-        bool valid = e < n;
-        uint32_t key = valid ? kin[e] : 0u;
-        uint64_t val = valid ? vin[e] : 0ull;
-        uint32_t d = (key >> shift) & (kRadix - 1);
-        // lanes of this wave holding the same digit
+        const int64_t e = sbase + (int64_t)s * 64 + lane;
+        const bool valid = e < n;
+        key[s] = valid ? kin[e] : 0u;
+        val[s] = valid ? vin[e] : 0ull;
+    }
+    for (int s = 0; s < kSortItems; ++s) {
+        const bool valid = sbase + (int64_t)s * 64 + lane < n;
+        const uint32_t d = (key[s] >> shift) & (kRadix - 1);
+        // lanes of this slot holding the same digit
         uint64_t peers = __ballot(valid);
         for (int bit = 0; bit < 8; ++bit) {
-            uint64_t b = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? b : ~b;
+            const uint64_t bb = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bb : ~bb;
         }
-        uint32_t rank_w = (uint32_t)__popcll(peers & lt);
-        if (valid && (peers & lt) == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            int dd = threadIdx.x;
-            uint32_t r = run[dd];
-            for (int w = 0; w < NW; ++w) {
-                uint32_t c = wcnt[w][dd];
-                wbase[w][dd] = r;
-                r += c;
-                wcnt[w][dd] = 0;
-            }
-            run[dd] = r;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t p = lstart[d] + wbase[wave][d] + rank_w;
-            sk[p] = key;
-            sv[p] = val;
-        }
-        __syncthreads();
+        const uint32_t before = wcnt[wave][d];                  // this slice's count so far
+        rank[s] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    {
+        // slice bases per digit: the counts of the slices before
+        const int dd = threadIdx.x;
+        uint32_t r = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = wcnt[w][dd];
+            wcnt[w][dd] = r;
+            r += c;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < kSortItems; ++s) {
+        if (sbase + (int64_t)s * 64 + lane >= n) continue;
+        const uint32_t d = (key[s] >> shift) & (kRadix - 1);
+        const uint32_t p = lstart[d] + wcnt[wave][d] + rank[s];
+        sk[p] = key[s];
+        sv[p] = val[s];
+    }
+    __syncthreads();
     const int nvalid = (int)(n - base < (int64_t)kSortTile ? (n - base > 0 ? n - base : 0) : (int64_t)kSortTile);
     for (int i = threadIdx.x; i < nvalid; i += kSortThreads) {
-        const uint32_t key = sk[i];
-        const uint32_t d = (key >> shift) & (kRadix - 1);
+        const uint32_t k = sk[i];
+        const uint32_t d = (k >> shift) & (kRadix - 1);
         const uint32_t pos = gstart[d] + ((uint32_t)i - lstart[d]);
-        kout[pos] = key;
+        kout[pos] = k;
         vout[pos] = sv[i];
     }
 }
