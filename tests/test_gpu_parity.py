@@ -149,6 +149,26 @@ def test_edge_layouts(variant, mode):
     compare(o, out, st=st)
 
 
+@pytest.mark.parametrize("axis", ["u", "v"])
+@pytest.mark.parametrize("mode", ["atomic", "deterministic_kahan"])
+def test_maximum_grid_side(axis, mode):
+    """One grid side at its limit of 65535 cells (a ragged last tile of 8192 or 16384 along
+    it), the other 3 cells wide: each row's track crosses hundreds of cells and tiles of the
+    long axis, and every sample lands inside the grid."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    fine, coarse = g["du"] * g["nu"] / 65535, g["du"] * g["nu"]
+    if axis == "u":
+        g = dict(g, nu=65535, nv=3, du=fine, dv=coarse)
+    else:
+        g = dict(g, nu=3, nv=65535, du=coarse, dv=fine)
+    hs, ds = targets_on_gpu(cfg)
+    o = oracle.stack(g, hs)
+    assert o["stats"]["n_outside_uv"] == 0
+    out, st = gpu_stack(g, ds, flags=MODES[mode])
+    compare(o, out, st=st)
+
+
 def test_empty_and_single_channel_targets():
     cfg = synth.config("small")
     g = synth.make_grid(cfg)
