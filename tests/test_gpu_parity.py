@@ -64,6 +64,19 @@ def test_long_channel_axes():
     print(err)
 
 
+@pytest.mark.parametrize("mode", ["atomic", "deterministic"])
+def test_channel_axis_at_its_limit(mode):
+    """A target of 65535 channels, the most one target may have (a record's channel bounds
+    then reach 65535), next to a short one; thousands of its channels overlap each rest
+    channel."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    hs = [synth.make_target(cfg, 1, nchan=65535, n_int=2), synth.make_target(cfg, 2)]
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=MODES[mode])
+    compare(o, out, st=st)
+
+
 def test_boundary_samples_bit_exact():
     """Samples placed exactly on cell edges and one ulp either side of them."""
     cfg = synth.config("small")
