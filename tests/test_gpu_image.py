@@ -3,7 +3,7 @@
 Every pixel within 1e-5 of the channel's image scale (sum |S_j| / W_j, the largest value a
 pixel can take) plus an absolute 1e-30 (noiseless line wings reach FP32's denormal range,
 which the device flushes to zero), the beam likewise; grids of every shape class the FFT handles (axes of 2,
-rectangular, up to 256 per side, and sampled pixels of axes up to 4096), a grid stacked by the
+rectangular, up to 256 per side, and sampled pixels of axes up to 4096), 65535 channels, a grid stacked by the
 library, a weight array that is not 16-byte aligned, and the bench's full-size
 grid (512 x 512 x 960) on sampled pixels.
 """
@@ -37,6 +37,20 @@ def _check(S, W, img, beam=None):
         if beam is not None:
             assert np.max(np.abs(beam[j] - rb[j])) <= TOL
     return ref
+
+
+def test_channel_count_at_its_limit():
+    """65535 channels of a 4 x 8 grid, the most one call takes (the row pass puts the
+    channels on the second dimension of its launch grid), with an empty channel."""
+    rng = np.random.default_rng(65535)
+    nchan, nv, nu = 65535, 4, 8
+    S = (rng.normal(size=(nchan, nv, nu)) + 1j * rng.normal(size=(nchan, nv, nu))).astype(np.complex64)
+    W = rng.uniform(0.0, 2.0, size=(nchan, nv, nu)).astype(np.float32)
+    W[nchan // 2] = 0.0
+    g = dict(nu=nu, nv=nv, du=1.0, dv=1.0, nchan=nchan, freq_lo=1e9, dfreq=1e6)
+    img, beam, _ = vista.image(g, torch.from_numpy(S).cuda(), torch.from_numpy(W).cuda(), beam=True)
+    torch.cuda.synchronize()
+    _check(S.astype(np.complex128), W.astype(np.float64), img.cpu().numpy(), beam.cpu().numpy())
 
 
 @pytest.mark.parametrize("shape", [(2, 2), (2, 8), (16, 4), (32, 32), (64, 128), (256, 256)])
