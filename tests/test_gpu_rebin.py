@@ -6,7 +6,8 @@ same row and polarisation (Eq. 3 averages a few inputs, so that is the scale of 
 output); the Eq. 3 normalisers within 1e-6.  Cases span several workgroups with ragged
 tails (window widths above, below and not a multiple of a workgroup), every polarisation
 count, descending and irregular channel axes, windows that fit, overhang an edge of the
-band or exceed it, and the bench's full-size shape on sampled rows.
+band or exceed it, a target at the 65535-channel limit, and the bench's full-size shape on
+sampled rows.
 """
 import dataclasses
 
@@ -87,6 +88,21 @@ def test_rebin_matches_oracle(variant, window):
         ora = oracle.rebin_rows(h, lo_ora, dfreq, nout)
         _compare(h, out, lo, ora, lo_ora)
         assert (ora["flag"] == 0).any()
+
+
+@pytest.mark.parametrize("window", ["line", "fine"])
+def test_rebin_channel_axis_at_its_limit(window):
+    """A target of 65535 channels, the most one target may have: each output channel
+    averages hundreds ("fine") or thousands ("line") of input channels."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    h = synth.make_target(cfg, 1, nchan=65535, n_int=2)
+    nout, dfreq = {"line": (40, g["dfreq"]), "fine": (300, g["dfreq"] / 10)}[window]
+    outs, los, _ = _run([h], nout, dfreq, cfg.line_rest)
+    lo_ora = oracle.rebin_window(h, cfg.line_rest, dfreq, nout)
+    ora = oracle.rebin_rows(h, lo_ora, dfreq, nout)
+    print(window, _compare(h, outs[0], los[0], ora, lo_ora))
+    assert (ora["flag"] == 0).any()
 
 
 def test_rebin_mixed_polarisations_and_empty_target():
