@@ -332,6 +332,30 @@ def test_batch_equals_plain():
     b.close()
 
 
+def test_batch_of_many_small_stacks():
+    """150 stacks in one launch, each one target on a grid of its own size (5 to 24 cells a
+    side, 3 to 12 rest channels): the stack of every row and unit is looked up among many,
+    and the work list orders units of many stacks by size."""
+    cfg = synth.config("tiny")
+    base = synth.make_grid(cfg)
+    rng = np.random.default_rng(150)
+    grids, hs_all = [], []
+    for s in range(150):
+        nu, nv, nch = int(rng.integers(5, 25)), int(rng.integers(5, 25)), int(rng.integers(3, 13))
+        grids.append(dict(base, nu=nu, nv=nv, du=base["du"] * base["nu"] / nu, dv=base["dv"] * base["nv"] / nv,
+                          nchan=nch, dfreq=base["dfreq"] * base["nchan"] / nch))
+        hs_all.append([synth.make_target(cfg, s % cfg.n_targets)])
+    b = vista.Batch(grids)
+    for s, hs in enumerate(hs_all):
+        b.add(s, hs[0].to("cuda"))
+    b.run()
+    for s, g in enumerate(grids):
+        out = vista.alloc_outputs(g)
+        st = b.finalize(s, out)
+        compare(oracle.stack(g, hs_all[s]), {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+    b.close()
+
+
 @pytest.mark.parametrize("n16", [1, 1000, 256 * 256 * 256 * 4 + 5])
 def test_copy_kernel_copies_every_vector(n16):
     """The plain copy kernel (bandwidth measurement, counter calibration): every 16-byte
