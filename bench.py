@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--targets", type=int, default=0, help="use only this many targets (0 = all)")
-    ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32")
+    ap.add_argument("--flags", default="", help="comma list: kahan,deterministic,phase_fp32,plain_fp32")
     ap.add_argument("--cpu-targets", type=int, default=12, help="targets in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
@@ -447,7 +447,7 @@ def main():
     flags = 0
     for f in filter(None, args.flags.split(",")):
         flags |= {"kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC,
-                  "phase_fp32": vista.F_PHASE_FP32}[f]
+                  "phase_fp32": vista.F_PHASE_FP32, "plain_fp32": vista.F_PLAIN_FP32}[f]
     tuning = None
     if args.tuning:
         a = [int(x) for x in args.tuning.split(",")]

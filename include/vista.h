@@ -56,9 +56,15 @@ enum {
                                            results from run to run (slower) */
     VISTA_F_SPECTRAL_NEAREST = 1u << 2, /* each input channel goes whole to the rest
                                            channel holding nu_obs (1+z) */
-    VISTA_F_PHASE_FP32 = 1u << 3        /* ablation: form u_lambda and the phase turns in
+    VISTA_F_PHASE_FP32 = 1u << 3,       /* ablation: form u_lambda and the phase turns in
                                            FP32 with full-range sincos (cell indices still
                                            come from FP64) */
+    VISTA_F_PLAIN_FP32 = 1u << 4        /* the plain, uncompensated FP32 form: per-tile sums
+                                           are FP32 LDS atomic adds (16 B of LDS per cell,
+                                           so larger tiles), each addition rounded to FP32.
+                                           Error grows with the contributions per cell
+                                           (about sqrt(n) * 6e-8 relative).  Not combinable
+                                           with VISTA_F_KAHAN or VISTA_F_DETERMINISTIC. */
 };
 
 /* The common stack grid.

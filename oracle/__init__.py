@@ -36,7 +36,7 @@ class _Target(C.Structure):
                 ("l", C.c_double), ("m", C.c_double), ("z", C.c_double),
                 ("weight_per_chan", C.c_int32), ("kbeg", C.c_int32), ("kend", C.c_int32),
                 ("rotate", C.c_int32), ("ra0", C.c_double), ("dec0", C.c_double), ("ra1", C.c_double),
-                ("dec1", C.c_double)]
+                ("dec1", C.c_double), ("kdata", C.c_int32), ("kstride", C.c_int32)]
 
 
 def lib():
@@ -75,7 +75,7 @@ def _host(t) -> dict:
     out["uvw"] = np.ascontiguousarray(d["uvw"], dtype=np.float64)
     vis = np.asarray(d["vis"])
     if np.iscomplexobj(vis):
-        vis = np.ascontiguousarray(vis.astype(np.complex64)).view(np.float32)
+        vis = np.ascontiguousarray(vis.astype(np.complex64, copy=False)).view(np.float32)
     out["vis"] = np.ascontiguousarray(vis, dtype=np.float32)
     out["weight"] = np.ascontiguousarray(d["weight"], dtype=np.float32)
     out["flag"] = None if d.get("flag") is None else np.ascontiguousarray(d["flag"], dtype=np.uint8)
@@ -84,6 +84,9 @@ def _host(t) -> dict:
     out["chan_width"] = None if cw is None else np.ascontiguousarray(cw, dtype=np.float64)
     out["kbeg"] = int(d.get("kbeg", 0))
     out["kend"] = int(d.get("kend", out["chan_freq"].shape[0]))
+    # the data arrays may hold more channels than [kbeg, kend): [kdata, kdata + kstride)
+    out["kdata"] = int(d.get("kdata", out["kbeg"]))
+    out["kstride"] = int(d.get("kstride", 0))
     return out
 
 
@@ -96,7 +99,7 @@ def _target(h: dict) -> _Target:
                    ptr(h["chan_freq"]), ptr(h["chan_width"]), float(h["l"]), float(h["m"]),
                    float(h["z"]), int(bool(h.get("weight_per_chan", False))), h["kbeg"], h["kend"],
                    int(bool(h.get("rotate_uvw", False))), float(h.get("ra0", 0.0)), float(h.get("dec0", 0.0)),
-                   float(h.get("ra1", 0.0)), float(h.get("dec1", 0.0)))
+                   float(h.get("ra1", 0.0)), float(h.get("dec1", 0.0)), h["kdata"], h["kstride"])
 
 
 def stack(grid: dict, targets, jlo: int = 0, jhi: int | None = None, stats: bool = True,

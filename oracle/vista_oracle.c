@@ -65,18 +65,28 @@ typedef struct {
     int64_t nrow;
     int32_t nchan, npol;
     const double* uvw;        /* [nrow][3] metres */
-    const float* vis;         /* [nrow][kend-kbeg][npol][2] (re, im) */
-    const float* weight;      /* [nrow][npol], or [nrow][kend-kbeg][npol] if weight_per_chan */
-    const uint8_t* flag;      /* [nrow][kend-kbeg][npol] or NULL */
+    const float* vis;         /* [nrow][nk][npol][2] (re, im) */
+    const float* weight;      /* [nrow][npol], or [nrow][nk][npol] if weight_per_chan */
+    const uint8_t* flag;      /* [nrow][nk][npol] or NULL */
     const double* chan_freq;  /* [nchan], all channels */
     const double* chan_width; /* [nchan] or NULL */
     double l, m, z;
     int32_t weight_per_chan;
-    int32_t kbeg, kend;       /* the data arrays hold channels [kbeg, kend) */
+    int32_t kbeg, kend;       /* the channels [kbeg, kend) are the ones used */
     int32_t rotate;           /* 1: Eq. 1's rotation from (ra0, dec0) to (ra1, dec1) [rad];
                                  l, m are then taken from the angles */
     double ra0, dec0, ra1, dec1;
+    int32_t kdata, kstride;   /* the data arrays hold channels [kdata, kdata + kstride) of
+                                 each row, nk = kstride; kstride == 0: they hold exactly
+                                 [kbeg, kend) (kdata = kbeg, nk = kend - kbeg) */
 } ora_target;
+
+/* Position of sample (r, k, p) in the data arrays (indexing only). */
+static size_t ora_elem(const ora_target* t, int64_t r, int32_t k, int32_t p) {
+    const int32_t k0 = t->kstride > 0 ? t->kdata : t->kbeg;
+    const int32_t nk = t->kstride > 0 ? t->kstride : t->kend - t->kbeg;
+    return ((size_t)r * (size_t)nk + (size_t)(k - k0)) * (size_t)t->npol + (size_t)p;
+}
 
 /* Per-channel rest-frame table of one target: a_k = nu_k / c and the contributing set
  * J_k = {(j, f_kj)} stored as a CSR list. */
@@ -246,9 +256,8 @@ static void ora_phasor(const double* uvw_row, double a, double l, double m, doub
     *s = sin(ph);
 }
 
-static double ora_weight(const ora_target* t, int64_t r, int32_t kk, int32_t p) {
-    int32_t nk = t->kend - t->kbeg;
-    if (t->weight_per_chan) return (double)t->weight[((size_t)r * nk + kk) * t->npol + p];
+static double ora_weight(const ora_target* t, int64_t r, int32_t k, int32_t p) {
+    if (t->weight_per_chan) return (double)t->weight[ora_elem(t, r, k, p)];
     return (double)t->weight[(size_t)r * t->npol + p];
 }
 
@@ -262,6 +271,9 @@ int ora_check(const ora_grid* g, int32_t ntgt, const ora_target* tg) {
         const ora_target* t = &tg[i];
         if (t->nrow < 0 || t->nchan < 1 || (t->npol != 1 && t->npol != 2 && t->npol != 4)) return -1;
         if (t->kbeg < 0 || t->kend > t->nchan || t->kbeg > t->kend) return -1;
+        if (t->kstride < 0) return -1;
+        if (t->kstride > 0 && (t->kdata < 0 || t->kdata > t->kbeg || t->kend > t->kdata + t->kstride ||
+                               t->kdata + t->kstride > t->nchan)) return -1;
         if (t->nchan == 1 && !t->chan_width) return -1;
         if (!(t->z > -1.0 && isfinite(t->z))) return -1;
         if (t->rotate != 0 && t->rotate != 1) return -1;
@@ -324,7 +336,6 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
             const ora_table* tb = &tabs[i];
             ora_frame fr;
             ora_make_frame(t, &fr);
-            int32_t nk = t->kend - t->kbeg;
             for (int64_t r = 0; r < t->nrow; ++r) {
                 const double* uvw = t->uvw + 3 * r;
                 double ur[3];
@@ -338,11 +349,10 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
                     if (!ora_cell(g, ur, tb->a[k], &iu, &iv)) continue;
                     double pc, ps;
                     ora_phasor(uvw, tb->a[k], fr.l, fr.m, fr.nm1, &pc, &ps);
-                    int32_t kk = k - t->kbeg;
                     for (int32_t p = 0; p < t->npol; ++p) {
-                        size_t e = ((size_t)r * nk + kk) * t->npol + p;
+                        size_t e = ora_elem(t, r, k, p);
                         if (t->flag && t->flag[e]) continue;
-                        double wt = ora_weight(t, r, kk, p);
+                        double wt = ora_weight(t, r, k, p);
                         if (!(wt > 0.0 && isfinite(wt))) continue;
                         double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
                         double xr = vr * pc - vi * ps;      /* V' = V * (pc + i ps) */
@@ -370,7 +380,6 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
             const ora_table* tb = &tabs[i];
             ora_frame fr;
             ora_make_frame(t, &fr);
-            int32_t nk = t->kend - t->kbeg;
             for (int64_t r = 0; r < t->nrow; ++r) {
                 double ur[3];
                 ora_rot(&fr, t->uvw + 3 * r, ur);
@@ -378,14 +387,13 @@ int ora_stack(const ora_grid* g, int32_t ntgt, const ora_target* tg, int32_t jlo
                     int32_t nj = tb->start[k + 1] - tb->start[k];
                     int64_t iu, iv;
                     int inside = nj > 0 ? ora_cell(g, ur, tb->a[k], &iu, &iv) : 0;
-                    int32_t kk = k - t->kbeg;
                     for (int32_t p = 0; p < t->npol; ++p) {
-                        size_t e = ((size_t)r * nk + kk) * t->npol + p;
+                        size_t e = ora_elem(t, r, k, p);
                         stats[0]++;
                         if (nj == 0) { stats[4]++; continue; }
                         if (!inside) { stats[3]++; continue; }
                         if (t->flag && t->flag[e]) { stats[1]++; continue; }
-                        double wt = ora_weight(t, r, kk, p);
+                        double wt = ora_weight(t, r, k, p);
                         if (!(wt > 0.0 && isfinite(wt))) { stats[2]++; continue; }
                         stats[5]++;
                         stats[6] += (uint64_t)nj;
@@ -442,7 +450,8 @@ int ora_rotate(const ora_target* t, double* out) {
             ora_phasor(t->uvw + 3 * r, t->chan_freq[k] / ORA_C, fr.l, fr.m, fr.nm1, &pc, &ps);
             for (int32_t p = 0; p < t->npol; ++p) {
                 size_t e = ((size_t)r * nk + (k - t->kbeg)) * t->npol + p;
-                double vr = (double)t->vis[2 * e], vi = (double)t->vis[2 * e + 1];
+                size_t d = ora_elem(t, r, k, p);
+                double vr = (double)t->vis[2 * d], vi = (double)t->vis[2 * d + 1];
                 out[2 * e] = vr * pc - vi * ps;
                 out[2 * e + 1] = vr * ps + vi * pc;
             }

@@ -3,8 +3,10 @@
 // The binning pass leaves the records of every (uv tile, rest-channel block) unit
 // contiguous; a record is a run [k_lo, k_hi) of channels of one row.  Concatenated, the
 // unit's records form one stream of (row, channel) samples, and pre[] gives each record's
-// start in it.  A workgroup owns one unit at a time: its cells live in LDS (FP64 sums and a
+// start in it.  A workgroup owns one unit at a time: its cells live in LDS (three sums and a
 // u32 count per cell), so every cell of the grid is written exactly once, from one place.
+// The sums are FP64 (28 B of LDS per cell), or, in the plain FP32 form, FP32 (16 B per
+// cell, so units hold 1.75 times as many cells); both are native LDS atomic adds.
 // The unit's stream is split into equal sample ranges, one per wavefront, and a wavefront
 // walks its range in chunks of 128 consecutive samples, two adjacent ones per lane (records
 // are padded to whole pairs), whatever records they come from: no lane idles at record
@@ -195,7 +197,7 @@ struct WaveStats {
 
 __device__ __forceinline__ uint64_t popc_ballot(bool p) { return (uint64_t)__popcll(__ballot(p)); }
 
-template <int TU, int TV, int JC, int NPOL>
+template <int TU, int TV, int JC, int NPOL, class Acc>
 __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __restrict__ Lp,
                                                           const uint64_t* __restrict__ order,
                                                           uint32_t* __restrict__ counter,
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
     constexpr int JP = JC + 1;            // padded channel stride of a cell
     constexpr int NC = TU * TV * JP;
     constexpr uint32_t kChunk = 2 * kWave;
-    __shared__ double s_re[NC], s_im[NC], s_w[NC];
+    __shared__ Acc s_re[NC], s_im[NC], s_w[NC];
     __shared__ uint32_t s_n[NC];
     __shared__ uint32_t s_unit;
     __shared__ unsigned long long s_contrib;
@@ -225,7 +227,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 
     // LDS starts zeroed; afterwards each unit's flush zeroes the cells it wrote
     for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-        s_re[i] = 0.0; s_im[i] = 0.0; s_w[i] = 0.0; s_n[i] = 0u;
+        s_re[i] = Acc(0); s_im[i] = Acc(0); s_w[i] = Acc(0); s_n[i] = 0u;
     }
     // the next unit is claimed while the current one is processed
     if (threadIdx.x == 0) {
@@ -412,13 +414,14 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     u_contrib += popc_ballot(add0 && use_p[p]) + popc_ballot(add1 && use_p[p]);
                 if (!live_add) return;
                 const int cell = (lv * TU + lu) * JP - jb0;
-                const double dr = (double)pr, di = (double)pi, dq = (double)q;
+                // FP64: the products of FP32 values are exact; FP32: one rounding each
+                const Acc dr = (Acc)pr, di = (Acc)pi, dq = (Acc)q;
 #pragma unroll
                 for (int qq = 0; qq < 2; ++qq) {
                     if (qq == 0 ? add0 : add1) {
-                        const double f = (double)(qq == 0 ? x.f0 : x.f1);
+                        const Acc f = (Acc)(qq == 0 ? x.f0 : x.f1);
                         const int cc = cell + j0 + qq;
-                        atomicAdd(&s_re[cc], f * dr);          // exact products of FP32 values
+                        atomicAdd(&s_re[cc], f * dr);
                         atomicAdd(&s_im[cc], f * di);
                         atomicAdd(&s_w[cc], f * dq);
                         atomicAdd(&s_n[cc], n);
@@ -430,7 +433,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     for (int qq = 2; qq < (int)nj; ++qq) {
                         const int32_t j = j0 + qq;
                         if (j < jb0 || j >= jb1) continue;
-                        const double f = (double)gptr(L.fval_all)[fo + qq];
+                        const Acc f = (Acc)gptr(L.fval_all)[fo + qq];
                         const int cc = cell + j;
                         atomicAdd(&s_re[cc], f * dr);
                         atomicAdd(&s_im[cc], f * di);
@@ -513,8 +516,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
             s_contrib = 0ull;
             s_unit = next;
         }
-        flush_unit<TU, TV, JP, double, false, true>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, nullptr,
-                                                    nullptr, nullptr);
+        flush_unit<TU, TV, JP, Acc, false, true>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, nullptr,
+                                                 nullptr, nullptr);
         __syncthreads();
     }
     ws.flush(L, lane);
@@ -578,6 +581,7 @@ hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, con
     return radix_sort_pairs(keys, vals, nunits_dev, nunits_cap, 32, sort_temp, stream);
 }
 
+// Launch shapes (tile_u, tile_v, jblock) of the FP64-sum form (28 B of LDS per cell) ...
 #define VISTA_PACKED_SHAPES(X) \
     X(8, 8, 64)                \
     X(16, 4, 64)               \
@@ -595,58 +599,103 @@ hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, con
     X(8, 2, 320)               \
     X(8, 4, 160)
 
-int accum_packed_shape_list(int* tu, int* tv, int* jc, int cap) {
+// ... and of the plain FP32 form (16 B per cell): units up to 1.75 times larger, and
+// smaller ones that let two workgroups share a compute unit.
+#define VISTA_PACKED_SHAPES_F32(X) \
+    X(8, 4, 288)                   \
+    X(16, 4, 144)                  \
+    X(8, 8, 144)                   \
+    X(16, 2, 288)                  \
+    X(4, 4, 576)                   \
+    X(8, 2, 576)                   \
+    X(16, 8, 64)                   \
+    X(8, 4, 128)                   \
+    X(8, 4, 144)                   \
+    X(16, 4, 64)
+
+static size_t packed_lds_bytes(int tu, int tv, int jc, int acc32) {
+    return (size_t)tu * tv * (jc + 1) * (acc32 ? 16 : 28) + 16;
+}
+
+int accum_packed_shape_list(int acc32, int* tu, int* tv, int* jc, int cap) {
     int n = 0;
 #define X(a, b, c)            \
     if (n < cap) {            \
         tu[n] = a; tv[n] = b; jc[n] = c; \
     }                         \
     ++n;
-    VISTA_PACKED_SHAPES(X)
+    if (acc32) {
+        VISTA_PACKED_SHAPES_F32(X)
+    } else {
+        VISTA_PACKED_SHAPES(X)
+    }
 #undef X
     return n;
 }
 
-bool accum_packed_shape_supported(int tu, int tv, int jc, int waves) {
+size_t accum_packed_lds_bytes(int tu, int tv, int jc, int acc32) { return packed_lds_bytes(tu, tv, jc, acc32); }
+
+bool accum_packed_shape_supported(int tu, int tv, int jc, int waves, int acc32) {
     if (waves < 1 || waves > 16) return false;
 #define X(a, b, c) \
-    if (tu == a && tv == b && jc == c) return (size_t)a * b * (c + 1) * 28 + 4 <= 160 * 1024;
-    VISTA_PACKED_SHAPES(X)
+    if (tu == a && tv == b && jc == c) return packed_lds_bytes(a, b, c, acc32) <= 160 * 1024;
+    if (acc32) {
+        VISTA_PACKED_SHAPES_F32(X)
+    } else {
+        VISTA_PACKED_SHAPES(X)
+    }
 #undef X
     return false;
 }
 
 hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
                                const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
-                               int npol, hipStream_t stream) {
-    if (waves < 1 || waves > 16) return hipErrorInvalidValue;
-#define X(a, b, c)                                                                                              \
+                               int npol, int acc32, hipStream_t stream) {
+    if (!accum_packed_shape_supported(L.tu, L.tv, L.jc, waves, acc32)) return hipErrorInvalidValue;
+#define X_ACC(a, b, c, ACC)                                                                                     \
     if (L.tu == a && L.tv == b && L.jc == c) {                                                                  \
         if (npol == 2)                                                                                          \
-            hipLaunchKernelGGL((k_accum_packed<a, b, c, 2>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
-                               order, counter, unit_off, recs, pre);                                    \
+            hipLaunchKernelGGL((k_accum_packed<a, b, c, 2, ACC>), dim3(grid), dim3(waves * kWave), 0, stream,  \
+                               dL, order, counter, unit_off, recs, pre);                                        \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_accum_packed<a, b, c, 0>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
-                               order, counter, unit_off, recs, pre);                                    \
+            hipLaunchKernelGGL((k_accum_packed<a, b, c, 0, ACC>), dim3(grid), dim3(waves * kWave), 0, stream,  \
+                               dL, order, counter, unit_off, recs, pre);                                        \
         return hipGetLastError();                                                                               \
     }
-    VISTA_PACKED_SHAPES(X)
-#undef X
+#define X64(a, b, c) X_ACC(a, b, c, double)
+#define X32(a, b, c) X_ACC(a, b, c, float)
+    if (acc32) {
+        VISTA_PACKED_SHAPES_F32(X32)
+    } else {
+        VISTA_PACKED_SHAPES(X64)
+    }
+#undef X64
+#undef X32
+#undef X_ACC
     return hipErrorInvalidValue;
 }
 
-int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol) {
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32) {
+    if (!accum_packed_shape_supported(tu, tv, jc, waves, acc32)) return 0;
     int nb = 0;
-#define X(a, b, c)                                                                                               \
+#define X_ACC(a, b, c, ACC)                                                                                       \
     if (tu == a && tv == b && jc == c) {                                                                         \
-        hipError_t e = npol == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_packed<a, b, c, 2>, \
-                                                                               waves * kWave, 0)                 \
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_packed<a, b, c, 0>, \
-                                                                               waves * kWave, 0);                \
+        hipError_t e = npol == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
+                                       &nb, k_accum_packed<a, b, c, 2, ACC>, waves * kWave, 0)                    \
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
+                                       &nb, k_accum_packed<a, b, c, 0, ACC>, waves * kWave, 0);                   \
         return e == hipSuccess ? nb : 0;                                                                         \
     }
-    VISTA_PACKED_SHAPES(X)
-#undef X
+#define X64(a, b, c) X_ACC(a, b, c, double)
+#define X32(a, b, c) X_ACC(a, b, c, float)
+    if (acc32) {
+        VISTA_PACKED_SHAPES_F32(X32)
+    } else {
+        VISTA_PACKED_SHAPES(X64)
+    }
+#undef X64
+#undef X32
+#undef X_ACC
     return 0;
 }
 

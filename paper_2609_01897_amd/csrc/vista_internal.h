@@ -174,11 +174,14 @@ hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, con
                              void* sort_temp, hipStream_t stream);
 // The packed accumulation (atomic mode): `grid` workgroups of `waves` wavefronts pull units
 // from *counter (zeroed first) in the order of `order` (u64 unit ids, L.nunits of them).
+// acc32: per-tile sums in FP32 (the plain FP32 form) instead of FP64.
 hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
                                const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
-                               int npol, hipStream_t stream);
-int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol);
-bool accum_packed_shape_supported(int tu, int tv, int jc, int waves);
+                               int npol, int acc32, hipStream_t stream);
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32);
+bool accum_packed_shape_supported(int tu, int tv, int jc, int waves, int acc32);
+int accum_packed_shape_list(int acc32, int* tu, int* tv, int* jc, int cap);
+size_t accum_packed_lds_bytes(int tu, int tv, int jc, int acc32);
 // The accumulation over the work list `order` (global unit ids); `grid` workgroups of
 // `waves` wavefronts pull list entries from *counter (zeroed first).
 // npol == 2 when every target of the launch has two polarisations (specialised path).
@@ -211,7 +214,7 @@ hipError_t launch_debug_rotate(const DevTarget* t, float2* out, int64_t nrow, in
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 // *flag |= 1 when a and b differ anywhere in [0, n) (the caller zeroes *flag).
 hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint32_t* flag, hipStream_t stream);
-// Launch shapes the kernels are built for, in order (atomic: the packed kernel's list).
+// Launch shapes the ordered kernel is built for, in order.
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 // Dirty image of every channel of a stacked grid (vista_image.hip): nu, nv powers of two

@@ -858,10 +858,8 @@ static int occ_one(int waves) {
     return nb;
 }
 
-int accum_packed_shape_list(int* tu, int* tv, int* jc, int cap);
-
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap) {
-    if (mode == kModeAtomic) return accum_packed_shape_list(tu, tv, jc, cap);
+    if (mode == kModeAtomic) return accum_packed_shape_list(0, tu, tv, jc, cap);
     int n = 0;
 #define X(a, b, c)            \
     if (n < cap) {            \
@@ -889,12 +887,9 @@ bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kaha
 
 // npol: 2 for launches whose targets all have two polarisations (the specialised path),
 // anything else selects the generic path.
+// (The atomic mode runs the packed kernel; callers pass ordered launches only.)
 #define VISTA_DISPATCH(a, b, c, CALL)                                                    \
     if (L.tu == a && L.tv == b && L.jc == c) {                                           \
-        if (L.mode == kModeAtomic) {                                                     \
-            if (npol == 2) return CALL(a, b, c, kModeAtomic, false, 2);                  \
-            return CALL(a, b, c, kModeAtomic, false, 0);                                 \
-        }                                                                                \
         if (L.kahan) {                                                                   \
             if (npol == 2) return CALL(a, b, c, kModeOrdered, true, 2);                  \
             return CALL(a, b, c, kModeOrdered, true, 0);                                 \
@@ -906,7 +901,8 @@ bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kaha
 hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order,
                              uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, int grid,
                              int waves, int npol, hipStream_t stream) {
-    if (!accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan)) return hipErrorInvalidValue;
+    if (L.mode != kModeOrdered || !accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan))
+        return hipErrorInvalidValue;
 #define CALL(a, b, c, m, k, p) launch_one<a, b, c, m, k, p>(dL, order, counter, unit_off, recs, grid, waves, stream)
 #define X(a, b, c) VISTA_DISPATCH(a, b, c, CALL)
     VISTA_SHAPES(X)
@@ -916,7 +912,7 @@ hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const ui
 }
 
 int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int npol) {
-    if (!accum_shape_supported(tu, tv, jc, waves, mode, kahan)) return 0;
+    if (mode != kModeOrdered || !accum_shape_supported(tu, tv, jc, waves, mode, kahan)) return 0;
     LaunchDesc L;
     L.tu = tu; L.tv = tv; L.jc = jc; L.mode = mode; L.kahan = kahan;
 #define CALL(a, b, c, m, k, p) occ_one<a, b, c, m, k, p>(waves)

@@ -70,8 +70,12 @@ bool check_grid(const vista_grid_desc* g, std::string* why) {
     if (!(g->dfreq > 0 && isfinite(g->dfreq))) { *why = "grid dfreq must be finite and > 0"; return false; }
     if (!isfinite(g->freq_lo)) { *why = "grid freq_lo must be finite"; return false; }
     if (g->flags & ~(uint32_t)(VISTA_F_KAHAN | VISTA_F_DETERMINISTIC | VISTA_F_SPECTRAL_NEAREST |
-                               VISTA_F_PHASE_FP32)) {
+                               VISTA_F_PHASE_FP32 | VISTA_F_PLAIN_FP32)) {
         *why = "unknown grid flag bits";
+        return false;
+    }
+    if ((g->flags & VISTA_F_PLAIN_FP32) && (g->flags & (VISTA_F_KAHAN | VISTA_F_DETERMINISTIC))) {
+        *why = "VISTA_F_PLAIN_FP32 (uncompensated FP32 tiles) excludes VISTA_F_KAHAN and VISTA_F_DETERMINISTIC";
         return false;
     }
     if ((double)g->nu * g->nv * g->nchan > 4.0e11) { *why = "grid has too many cells"; return false; }

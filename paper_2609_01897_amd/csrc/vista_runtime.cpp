@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdarg>
 #include <condition_variable>
 #include <deque>
 #include <exception>
@@ -76,6 +77,27 @@ static Env read_env() {
 
 static std::atomic<int64_t> g_dev_bytes{0};
 
+// ------------------------------------------------------------------------- logging
+
+// VISTA_LOG=0..3 sets how much the library writes to stderr: 0 nothing (the default);
+// 1 one line per stack launch and batch run (records, units, device times); 2 also the
+// autotuner's candidates and the batch's wave plan; 3 also each launch's host build.
+static int log_level() {
+    const char* s = getenv("VISTA_LOG");
+    return s ? atoi(s) : 0;
+}
+
+static void vlog(int level, const char* fmt, ...) {
+    if (log_level() < level) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[vista] %s\n", buf);
+    fflush(stderr);
+}
+
 static void pool_setup_once() {
     static std::once_flag once;
     std::call_once(once, [] {
@@ -138,11 +160,16 @@ class DevMem {
     std::vector<std::pair<void*, size_t>> ptrs_;
 };
 
-static void check_launch(hipError_t e, const char* what) {
+// Enqueue a kernel launch and check it.  An injected launch failure is raised before the
+// kernel is enqueued, so nothing is left running on memory the unwinding frees.
+template <class F>
+static void check_launch_f(F&& launch, const char* what) {
     if (read_env().fail_launch) throw HipFail{hipErrorLaunchFailure, std::string("injected launch failure: ") + what};
+    const hipError_t e = launch();
     if (e == hipErrorInvalidValue) throw HipFail{e, std::string("unsupported launch shape: ") + what};
     if (e != hipSuccess) throw HipFail{e, what};
 }
+#define check_launch(expr, what) check_launch_f([&]() { return (expr); }, what)
 
 // ------------------------------------------------------------------------ handles
 
@@ -333,13 +360,15 @@ struct Tuning {
 static bool shape_ok(const Tuning& t, uint32_t flags) {
     if (flags & VISTA_F_DETERMINISTIC)
         return accum_shape_supported(t.tu, t.tv, t.jc, t.waves, kModeOrdered, (flags & VISTA_F_KAHAN) ? 1 : 0);
-    return accum_packed_shape_supported(t.tu, t.tv, t.jc, t.waves);
+    return accum_packed_shape_supported(t.tu, t.tv, t.jc, t.waves, (flags & VISTA_F_PLAIN_FP32) ? 1 : 0);
 }
 
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
     if (flags & VISTA_F_DETERMINISTIC) {
         t.tu = 8; t.tv = 4; t.jc = 128; t.waves = 8;   // ordered: 16-channel slices per wave
+    } else if (flags & VISTA_F_PLAIN_FP32) {
+        t.tu = 8; t.tv = 4; t.jc = 288; t.waves = 16;  // FP32 tiles: 1.75 times the cells
     }
     return t;
 }
@@ -649,6 +678,7 @@ class Launcher {
         : s_(s), tu_(tu), mem_(s, persistent), recmem_(s, persistent) {
         mode_ = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
         kahan_ = (flags & VISTA_F_KAHAN) ? 1 : 0;
+        acc32_ = (flags & VISTA_F_PLAIN_FP32) ? 1 : 0;
         phase_fp32_ = (flags & VISTA_F_PHASE_FP32) ? 1 : 0;
         jsub_ = mode_ == kModeOrdered ? tu.jc / tu.waves : tu.jc;
         if (!shape_ok(tu, flags)) throw HipFail{hipErrorInvalidValue, "unsupported launch shape (tile/jblock/waves)"};
@@ -787,13 +817,13 @@ class Launcher {
         int per_cu = tu_.wg_per_cu;
         if (per_cu <= 0)
             per_cu = mode_ == kModeAtomic
-                         ? accum_packed_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, npol_)
+                         ? accum_packed_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, npol_, acc32_)
                          : accum_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, mode_, kahan_, npol_);
         if (per_cu < 1) per_cu = 1;
         const int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, cap_.units));
         if (mode_ == kModeAtomic)
             check_launch(launch_accum_packed(L_, d_L_, order_, counter_, unit_off_, vals_, pre_, (int)grid, tu_.waves,
-                                             npol_, s_),
+                                             npol_, acc32_, s_),
                          "accumulate");
         else
             check_launch(launch_accum_impl(L_, d_L_, order_, counter_, unit_off_, vals_, (int)grid, tu_.waves, npol_,
@@ -839,7 +869,7 @@ class Launcher {
 
     hipStream_t s_;
     Tuning tu_;
-    int mode_ = kModeAtomic, kahan_ = 0, phase_fp32_ = 0, jsub_ = 0, npol_ = 2;
+    int mode_ = kModeAtomic, kahan_ = 0, acc32_ = 0, phase_fp32_ = 0, jsub_ = 0, npol_ = 2;
     DevMem mem_, recmem_;
     Capacity cap_;
     bool fixed_ = false, recs_ok_ = false;
@@ -940,7 +970,7 @@ constexpr size_t kMaxWorkspaces = 2;
 static Workspace& workspace_for(hipStream_t stream, const Tuning& tu, uint32_t flags) {
     int dev = 0;
     VISTA_HIP(hipGetDevice(&dev));
-    const uint32_t mf = flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN | VISTA_F_PHASE_FP32);
+    const uint32_t mf = flags & (VISTA_F_DETERMINISTIC | VISTA_F_KAHAN | VISTA_F_PHASE_FP32 | VISTA_F_PLAIN_FP32);
     for (size_t i = 0; i < t_workspaces.size(); ++i) {
         Workspace& w = *t_workspaces[i];
         if (w.device == dev && w.mode_flags == mf && w.tu.tu == tu.tu && w.tu.tv == tu.tv && w.tu.jc == tu.jc &&
@@ -1009,6 +1039,10 @@ static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning
     VISTA_HIP(hipEventRecord(ev.e[3], stream));
     VISTA_HIP(hipStreamSynchronize(stream));
     collect_stats(jobs, st);
+    vlog(1, "stack launch: %zu stack(s), %zu target(s), %lld rows, %lld records, %lld units, shape %dx%dx%d/%d; "
+            "binning %.3f ms, accumulation %.3f ms, total %.3f ms",
+         jobs.size(), h.dts.size(), (long long)h.rows, (long long)nrec, (long long)h.nunits, tu.tu, tu.tv, tu.jc,
+         tu.waves, ev.ms(0, 1), ev.ms(1, 2), ev.ms(0, 3));
     if (tim) {
         tim->bin_ms = ev.ms(0, 1);
         tim->accum_ms = ev.ms(1, 2);
@@ -1030,15 +1064,20 @@ static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning
 static std::vector<Tuning> tuning_candidates(uint32_t flags) {
     const int mode = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
     const int kahan = (flags & VISTA_F_KAHAN) ? 1 : 0;
+    const int acc32 = (flags & VISTA_F_PLAIN_FP32) ? 1 : 0;
     int tu[64], tv[64], jc[64];
-    const int n = std::min(accum_shape_list(mode, tu, tv, jc, 64), 64);
+    const int n = std::min(mode == kModeAtomic ? accum_packed_shape_list(acc32, tu, tv, jc, 64)
+                                               : accum_shape_list(mode, tu, tv, jc, 64),
+                           64);
     std::vector<Tuning> out{default_tuning(flags)};
     for (int i = 0; i < n; ++i)
         for (int waves : {16, 8}) {
             Tuning t;
             t.tu = tu[i]; t.tv = tv[i]; t.jc = jc[i]; t.waves = waves;
             if (!shape_ok(t, flags)) continue;
-            if (waves == 8 && accum_lds_bytes(t.tu, t.tv, t.jc, mode, kahan) > 80 * 1024) continue;
+            const size_t lds = mode == kModeAtomic ? accum_packed_lds_bytes(t.tu, t.tv, t.jc, acc32)
+                                                   : accum_lds_bytes(t.tu, t.tv, t.jc, mode, kahan);
+            if (waves == 8 && lds > 80 * 1024) continue;
             if (t.tu == out[0].tu && t.tv == out[0].tv && t.jc == out[0].jc && t.waves == out[0].waves) continue;
             out.push_back(t);
         }
@@ -1085,6 +1124,8 @@ static Tuning autotune_jobs(std::vector<StackJob>& jobs, uint32_t flags, hipStre
             VISTA_HIP(hipStreamSynchronize(stream));
             same = h == 0;
         }
+        vlog(2, "autotune candidate %dx%dx%d/%d: %.3f ms%s", cand[c].tu, cand[c].tv, cand[c].jc, cand[c].waves, t,
+             same ? "" : " (counts differ from the default shape: rejected)");
         if (same && t < best_t) {
             best_t = t;
             best = cand[c];
@@ -1093,6 +1134,118 @@ static Tuning autotune_jobs(std::vector<StackJob>& jobs, uint32_t flags, hipStre
     VISTA_HIP(hipStreamSynchronize(stream));
     if (best_ms) *best_ms = best_t;
     return best;
+}
+
+// ------------------------------------------------------------------ tuning cache
+
+// VISTA_TUNE_CACHE names a file of JSON lines, one per tuned workload:
+//   {"key": "<16 hex digits>", "tile_u": 8, "tile_v": 4, "jblock": 160, "waves": 16, "ms": 31.2,
+//    "workload": "<the signature hashed into key>"}
+// The signature holds the device's architecture and compute units, the accumulation flags,
+// every stack's grid shape and its targets' count, rows, channels and samples.  An autotune
+// call whose key is in the file takes that shape without timing anything (if the shape is
+// still built and valid for the flags); otherwise it times the candidates and appends the
+// winner.  Lines that do not parse are ignored.
+static std::string tune_signature(const std::vector<StackJob>& jobs, uint32_t flags) {
+    std::string sig;
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+        sig += std::string(p.gcnArchName) + "/" + std::to_string(p.multiProcessorCount);
+    sig += " flags=" + std::to_string(flags & (VISTA_F_KAHAN | VISTA_F_DETERMINISTIC | VISTA_F_PHASE_FP32 |
+                                               VISTA_F_PLAIN_FP32 | VISTA_F_SPECTRAL_NEAREST));
+    for (const StackJob& J : jobs) {
+        int64_t rows = 0, chans = 0, samples = 0;
+        int npol_mask = 0;
+        for (const HostTarget* h : J.targets) {
+            rows += h->t.nrow;
+            chans += h->t.nchan;
+            samples += h->t.nrow * (int64_t)h->t.nchan * h->t.npol;
+            npol_mask |= 1 << h->t.npol | (h->t.weight_per_chan ? 32 : 0);
+        }
+        sig += " " + std::to_string(J.g->nu) + "x" + std::to_string(J.g->nv) + "x" + std::to_string(J.g->nchan) + ":" +
+               std::to_string(J.targets.size()) + "/" + std::to_string(rows) + "/" + std::to_string(chans) + "/" +
+               std::to_string(samples) + "/" + std::to_string(npol_mask);
+    }
+    return sig;
+}
+
+static std::string tune_key(const std::string& sig) {
+    uint64_t h = 1469598103934665603ull;            // FNV-1a, 64 bit
+    for (unsigned char c : sig) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    char buf[17];
+    snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+    return buf;
+}
+
+static bool tune_cache_lookup(const std::string& key, uint32_t flags, Tuning* out) {
+    const char* path = getenv("VISTA_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, want.c_str())) continue;
+        auto field = [&](const char* name, int* v) {
+            const char* q = strstr(line, name);
+            if (!q) return false;
+            q += strlen(name);
+            while (*q == ' ' || *q == ':') ++q;
+            char* end = nullptr;
+            const long x = strtol(q, &end, 10);
+            if (end == q || x < 1 || x > 100000) return false;
+            *v = (int)x;
+            return true;
+        };
+        Tuning t;
+        if (field("\"tile_u\"", &t.tu) && field("\"tile_v\"", &t.tv) && field("\"jblock\"", &t.jc) &&
+            field("\"waves\"", &t.waves) && shape_ok(t, flags)) {
+            *out = t;                                  // the last valid line for the key wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void tune_cache_store(const std::string& key, const std::string& sig, const Tuning& t, double ms) {
+    const char* path = getenv("VISTA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) {
+        vlog(1, "tuning cache %s cannot be opened for appending", path);
+        return;
+    }
+    fprintf(f, "{\"key\": \"%s\", \"tile_u\": %d, \"tile_v\": %d, \"jblock\": %d, \"waves\": %d, \"ms\": %.4f, "
+               "\"workload\": \"%s\"}\n",
+            key.c_str(), t.tu, t.tv, t.jc, t.waves, ms, sig.c_str());
+    fclose(f);
+}
+
+// The autotuner behind the cache; `prepare` (scratch outputs for the timed runs) is called
+// only when the shape must be timed.
+template <class F>
+static Tuning autotune_cached(std::vector<StackJob>& jobs, uint32_t flags, hipStream_t stream, bool* from_cache,
+                              F&& prepare) {
+    const std::string sig = tune_signature(jobs, flags);
+    const std::string key = tune_key(sig);
+    Tuning t;
+    if (tune_cache_lookup(key, flags, &t)) {
+        vlog(2, "autotune: shape %dx%dx%d/%d from the tuning cache (key %s)", t.tu, t.tv, t.jc, t.waves, key.c_str());
+        *from_cache = true;
+        return t;
+    }
+    prepare();
+    double ms = 0;
+    t = autotune_jobs(jobs, flags, stream, 2, &ms);
+    tune_cache_store(key, sig, t, ms);
+    *from_cache = false;
+    return t;
 }
 
 // Scratch outputs (sum_wvis, sum_w, count) of one job, for autotuning.
@@ -1562,11 +1715,12 @@ int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_str
     if (!out) return fail(VISTA_E_ARG, "out is NULL");
     if (n_stacks < 1 || !g) return fail(VISTA_E_ARG, "need n_stacks >= 1 grids");
     std::string why;
-    const uint32_t mode_bits = VISTA_F_KAHAN | VISTA_F_DETERMINISTIC | VISTA_F_PHASE_FP32;
+    const uint32_t mode_bits = VISTA_F_KAHAN | VISTA_F_DETERMINISTIC | VISTA_F_PHASE_FP32 | VISTA_F_PLAIN_FP32;
     for (int32_t i = 0; i < n_stacks; ++i) {
         if (!check_grid(&g[i], &why)) return fail(VISTA_E_ARG, "stack " + std::to_string(i) + ": " + why);
         if ((g[i].flags & mode_bits) != (g[0].flags & mode_bits))
-            return fail(VISTA_E_ARG, "all stacks of a batch need the same KAHAN/DETERMINISTIC/PHASE_FP32 flags");
+            return fail(VISTA_E_ARG,
+                        "all stacks of a batch need the same KAHAN/DETERMINISTIC/PHASE_FP32/PLAIN_FP32 flags");
     }
     try {
         auto* b = new vista_batch();
@@ -1705,6 +1859,7 @@ int vista_batch_run(vista_batch* b) {
                 wbytes.back() += nb;
             }
         const size_t nw = waves.size();
+        vlog(2, "batch plan: %zu stack(s), %zu wave(s), stream budget %lld bytes", ns, nw, (long long)budget);
         // a stack takes part in the waves holding its targets (a stack without targets in
         // the first, so that its cells are written)
         std::vector<std::vector<char>> member(nw, std::vector<char>(ns, 0));
@@ -1871,6 +2026,9 @@ int vista_batch_run(vista_batch* b) {
         T.n_units = cap.units;
         T.n_accum_launches = (int32_t)nw;
         T.n_waves = (int32_t)nw;
+        vlog(1, "batch run: %zu stack(s), %zu wave(s), %lld records; binning %.3f ms, accumulation %.3f ms, "
+                "input copies %.3f ms, total %.3f ms",
+             ns, nw, (long long)nrec_total, T.bin_ms, T.accum_ms, T.h2d_ms, T.total_ms);
         b->state = 1;
         return VISTA_OK;
     });
@@ -1945,8 +2103,8 @@ int vista_stack_autotune(vista_stack* s, vista_tuning* best) {
         std::vector<StackJob> jobs(1);
         jobs[0].g = &s->g;
         for (auto& h : s->targets) jobs[0].targets.push_back(h.get());
-        scratch_outputs(jobs[0], mem);
-        const Tuning t = autotune_jobs(jobs, s->g.flags, s->stream, 2, nullptr);
+        bool cached = false;
+        const Tuning t = autotune_cached(jobs, s->g.flags, s->stream, &cached, [&] { scratch_outputs(jobs[0], mem); });
         mem.release();
         VISTA_HIP(hipStreamSynchronize(s->stream));
         s->tune = t;
@@ -1969,9 +2127,11 @@ int vista_batch_autotune(vista_batch* b, vista_tuning* best) {
         for (size_t s = 0; s < jobs.size(); ++s) {
             jobs[s].g = &b->g[s];
             for (auto& h : b->targets[s]) jobs[s].targets.push_back(h.get());
-            scratch_outputs(jobs[s], mem);
         }
-        const Tuning t = autotune_jobs(jobs, b->g[0].flags, b->stream, 2, nullptr);
+        bool cached = false;
+        const Tuning t = autotune_cached(jobs, b->g[0].flags, b->stream, &cached, [&] {
+            for (auto& J : jobs) scratch_outputs(J, mem);
+        });
         mem.release();
         VISTA_HIP(hipStreamSynchronize(b->stream));
         b->tune = t;

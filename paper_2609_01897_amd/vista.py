@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libvista.so")
 
 VISTA_OK, VISTA_E_ARG, VISTA_E_STATE, VISTA_E_NOMEM, VISTA_E_HIP, VISTA_E_RANGE = 0, -1, -2, -3, -4, -5
 MEM_HOST, MEM_HOST_PINNED, MEM_DEVICE = 0, 1, 2
-F_KAHAN, F_DETERMINISTIC, F_SPECTRAL_NEAREST, F_PHASE_FP32 = 1, 2, 4, 8
+F_KAHAN, F_DETERMINISTIC, F_SPECTRAL_NEAREST, F_PHASE_FP32, F_PLAIN_FP32 = 1, 2, 4, 8, 16
 STAT_NAMES = ("n_samples", "n_flagged", "n_bad_weight", "n_outside_uv", "n_outside_band", "n_used",
               "n_contrib")
 _ERR = {VISTA_E_ARG: "VISTA_E_ARG", VISTA_E_STATE: "VISTA_E_STATE", VISTA_E_NOMEM: "VISTA_E_NOMEM",

@@ -8,6 +8,7 @@ gridding).  Random numbers are drawn here and handed to both sides as inputs.
 """
 from .configs import CONFIGS, config, grid_for
 from .generate import Target, batch_stack_sizes, make_target, make_targets, make_grid, radec_of_offset
+from .pool import make_pool, pool_targets
 
 __all__ = ["CONFIGS", "config", "grid_for", "Target", "batch_stack_sizes", "make_target", "make_targets",
-           "make_grid", "radec_of_offset"]
+           "make_grid", "radec_of_offset", "make_pool", "pool_targets"]

@@ -311,3 +311,16 @@ def test_background_planning_survives_drop_and_fork():
             pytest.fail("the forked child did not finish its adds")
         time.sleep(0.05)
     assert os.WIFEXITED(status) and os.WEXITSTATUS(status) == 0
+
+
+def test_injected_launch_failure_is_raised_before_the_launch(monkeypatch):
+    """VISTA_FAULT_INJECT=launch fails the next kernel launch from the host, before the
+    kernel is enqueued: the call returns VISTA_E_HIP with the injected message."""
+    monkeypatch.setenv("VISTA_FAULT_INJECT", "launch")
+    src = np.zeros(64, np.uint8)
+    dst = np.zeros(64, np.uint8)
+    L = vista.lib()
+    rc = L.vista_debug_copy(dst.ctypes.data, src.ctypes.data, 64, None)
+    assert rc == vista.VISTA_E_HIP
+    assert "injected launch failure" in L.vista_last_error().decode()
+    monkeypatch.delenv("VISTA_FAULT_INJECT")

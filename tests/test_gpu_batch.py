@@ -172,3 +172,66 @@ def test_batch_autotune_keeps_results():
         st = b.finalize(s, out)
         compare(oracle.stack(g, hs[s]), {k: v.cpu().numpy() for k, v in out.items()}, st=st)
     b.close()
+
+
+def test_injected_launch_failure_poisons_and_recovers(monkeypatch):
+    """A launch failure forced from the host (raised before its kernel is enqueued) fails
+    finalize with VISTA_E_HIP and poisons the handle; destroy succeeds, and a fresh stack on
+    the same thread then runs normally and matches the oracle."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    hs = synth.make_targets(cfg, n=2)
+    ds = [t.to("cuda") for t in hs]
+    monkeypatch.setenv("VISTA_FAULT_INJECT", "launch")
+    s = vista.Stack(g)
+    for t in ds:
+        s.add(t)
+    with pytest.raises(vista.VistaError) as e:
+        s.finalize(vista.alloc_outputs(g))
+    assert e.value.code == vista.VISTA_E_HIP and "injected" in str(e.value)
+    with pytest.raises(vista.VistaError) as e:
+        s.add(ds[0])
+    assert e.value.code == vista.VISTA_E_STATE
+    s.close()
+    monkeypatch.delenv("VISTA_FAULT_INJECT")
+    torch.cuda.synchronize()
+    out, st = vista.stack(g, ds)
+    torch.cuda.synchronize()
+    compare(oracle.stack(g, hs), {k: v.cpu().numpy() for k, v in out.items()}, st=st)
+
+
+def test_tuning_cache_is_written_and_read(tmp_path, monkeypatch):
+    """With VISTA_TUNE_CACHE set, the first autotune of a workload appends its winner to the
+    file; a later autotune of the same workload takes the file's shape without timing (here
+    a line appended by hand, so the choice shows), and the result still matches."""
+    import json
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("VISTA_TUNE_CACHE", str(path))
+    cfg = synth.config("small")
+    hs = synth.make_targets(cfg)
+    ds = [t.to("cuda") for t in hs]
+    g = synth.make_grid(cfg)
+
+    def tuned():
+        s = vista.Stack(g)
+        for t in ds:
+            s.add(t)
+        return s, s.autotune()
+
+    s, best = tuned()
+    s.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["tile_u"] == best["tile_u"] and lines[0]["jblock"] == best["jblock"]
+    forced = dict(lines[0], tile_u=4, tile_v=2, jblock=512, waves=16)
+    if (best["tile_u"], best["tile_v"], best["jblock"]) == (4, 2, 512):
+        forced.update(tile_u=8, tile_v=8, jblock=64)
+    with open(path, "a") as f:
+        f.write(json.dumps(forced) + "\n")
+    s, again = tuned()
+    assert (again["tile_u"], again["tile_v"], again["jblock"], again["waves"]) == (
+        forced["tile_u"], forced["tile_v"], forced["jblock"], forced["waves"])
+    assert len(path.read_text().splitlines()) == 2          # nothing timed, nothing appended
+    out = vista.alloc_outputs(g)
+    st = s.finalize(out)
+    s.close()
+    compare(oracle.stack(g, hs), {k: v.cpu().numpy() for k, v in out.items()}, st=st)

@@ -21,7 +21,7 @@ from paper_2609_01897_amd import vista  # noqa: E402
 from tests.gpu_util import compare, gpu_stack, targets_on_gpu  # noqa: E402
 
 MODES = {"atomic": 0, "deterministic": vista.F_DETERMINISTIC, "kahan": vista.F_KAHAN,
-         "deterministic_kahan": vista.F_DETERMINISTIC | vista.F_KAHAN}
+         "deterministic_kahan": vista.F_DETERMINISTIC | vista.F_KAHAN, "plain_fp32": vista.F_PLAIN_FP32}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -135,7 +135,7 @@ def test_phase_fp32_ablation_loses_cycles():
 
 @pytest.mark.parametrize("variant", ["descending", "jitter_width", "perchan_badw", "nearest", "odd_small_grid",
                                      "npol1", "npol4", "no_flags"])
-@pytest.mark.parametrize("mode", ["atomic", "deterministic_kahan"])
+@pytest.mark.parametrize("mode", ["atomic", "deterministic_kahan", "plain_fp32"])
 def test_edge_layouts(variant, mode):
     cfg = synth.config("small")
     kw = {}
@@ -250,24 +250,52 @@ PACKED_SHAPES = [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128)
                  (4, 2, 512), (4, 4, 128), (8, 4, 64), (8, 2, 128), (4, 2, 256), (16, 2, 160), (8, 2, 320),
                  (8, 4, 160)]
 ORDERED_SHAPES = PACKED_SHAPES[:8]
+PACKED_SHAPES_F32 = [(8, 4, 288), (16, 4, 144), (8, 8, 144), (16, 2, 288), (4, 4, 576), (8, 2, 576), (16, 8, 64),
+                     (8, 4, 128), (8, 4, 144), (16, 4, 64)]
 
 
-@pytest.mark.parametrize("shape", PACKED_SHAPES)
-def test_every_tile_shape_matches(shape):
-    """The autotuner's candidates change only speed: counts identical, sums in tolerance
-    (plain and compensated; the ordered kernel on the shapes it is built for)."""
+@pytest.fixture(scope="module")
+def small_case():
     cfg = synth.config("small")
     hs, ds = targets_on_gpu(cfg)
     g = synth.make_grid(cfg)
-    o = oracle.stack(g, hs)
-    tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=4)
+    return g, ds, oracle.stack(g, hs)
+
+
+@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("shape", PACKED_SHAPES)
+def test_every_tile_shape_matches(shape, waves, small_case):
+    """The autotuner's candidates change only speed: counts identical, sums in tolerance
+    (plain and compensated; the ordered kernel on the shapes it is built for), with 4
+    wavefronts per workgroup and with the 16 whose per-wavefront stream split the
+    benchmark runs."""
+    g, ds, o = small_case
+    tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
     out, st = gpu_stack(g, ds, tuning=tu)
     compare(o, out, st=st)
     out, st = gpu_stack(g, ds, flags=vista.F_KAHAN, tuning=tu)
     compare(o, out, st=st)
-    if shape in ORDERED_SHAPES:
+    if shape in ORDERED_SHAPES and waves == 4:
         out, st = gpu_stack(g, ds, flags=vista.F_DETERMINISTIC | vista.F_KAHAN, tuning=tu)
         compare(o, out, st=st)
+
+
+@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("shape", PACKED_SHAPES_F32)
+def test_every_fp32_tile_shape_matches(shape, waves, small_case):
+    """The plain FP32 form's shapes (FP32 per-tile sums, 16 B of LDS per cell)."""
+    g, ds, o = small_case
+    tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
+    out, st = gpu_stack(g, ds, flags=vista.F_PLAIN_FP32, tuning=tu)
+    compare(o, out, st=st)
+
+
+def test_plain_fp32_rejects_compensated_flags():
+    g = synth.make_grid("small")
+    for extra in (vista.F_KAHAN, vista.F_DETERMINISTIC):
+        with pytest.raises(vista.VistaError) as e:
+            vista.Stack(g, flags=vista.F_PLAIN_FP32 | extra)
+        assert e.value.code == vista.VISTA_E_ARG
 
 
 def test_deterministic_mode_is_bit_identical():

@@ -277,6 +277,24 @@ def test_channel_slices_add_up():
         assert sum(p["stats"][k] for p in parts) == full["stats"][k]
 
 
+
+@pytest.mark.parametrize("perchan", [False, True])
+def test_strided_channel_view_equals_copied_slice(perchan):
+    """A channel range read in place from the full data arrays (kdata = 0, kstride = nchan)
+    gives the same bits as the same range copied out (an indexing change only)."""
+    cfg = synth.config("small")
+    t = synth.make_target(cfg, 2, weight_per_chan=perchan, bad_weight_frac=0.05 if perchan else 0.0)
+    g = synth.make_grid(cfg)
+    k0, k1 = 23, t.nchan - 31
+    copied = oracle.stack(g, [t.channel_slice(k0, k1)])
+    view = dict(t.numpy(), kbeg=k0, kend=k1, kdata=0, kstride=t.nchan)
+    strided = oracle.stack(g, [view])
+    for k in ("S", "W", "A", "N"):
+        assert np.array_equal(strided[k], copied[k])
+    assert strided["stats"] == copied["stats"]
+    with pytest.raises(ValueError):
+        oracle.stack(g, [dict(view, kdata=k0 + 1)])      # the view must hold [kbeg, kend)
+
 def _stacked_line(cfg, n_targets=4):
     ts = synth.make_targets(cfg, n=n_targets, noiseless=True)
     g = synth.make_grid(cfg)
