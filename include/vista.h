@@ -169,34 +169,50 @@ typedef struct {
 typedef struct vista_stack vista_stack;
 typedef struct vista_batch vista_batch;
 
-/* Create a stack on `hip_stream` (the current device).  The grid state is allocated
- * when the stack is finalized.  Errors: VISTA_E_ARG (NULL pointer, bad grid), NOMEM. */
+/* Create one stack: the common (u, v, nu_rest) grid every target is added into -- the
+ * stacked product of the method (Sec. 2 and Sec. 3.1: targets shifted to their own
+ * positions, rest-framed and combined on one grid of Delta nu_new channels).  g is copied;
+ * hip_stream (a hipStream_t of the current device, NULL = the null stream) orders every
+ * device operation of the stack.  Nothing is allocated on the device until finalize.
+ * *out receives the handle, owned by the caller until vista_stack_destroy.
+ * Errors: ARG (NULL pointer, invalid grid or flags), NOMEM (host). */
 int vista_stack_create(const vista_grid_desc* g, void* hip_stream, vista_stack** out);
 
-/* Add one target.  The arguments are validated and the channel axis copied here; the host
- * planning (rest-frame edges, Eq. 3-4 overlap table, a_k = nu_k / c) is handed to a pool
- * of library threads and runs while the caller adds more targets (finalize waits for it and
- * reports its errors), except for a target whose widest rest-frame channel could overlap
- * more rest channels than the overlap table holds: that one is planned and checked here.  Device work is deferred to vista_stack_finalize, which stacks
- * all targets in one pass.  VISTA_MEM_HOST data are copied to library staging before the
- * call returns; VISTA_MEM_HOST_PINNED and VISTA_MEM_DEVICE data must stay valid and
- * unchanged until finalize returns.  Errors: ARG (see vista_target), STATE (after
- * finalize or poisoned), NOMEM, HIP. */
+/* Add one target (one dataset selection, Sec. 3.1: its rows' uvw, visibilities, weights and
+ * flags, its channel frequencies, its offset (l, m) and redshift z).  The arguments are
+ * validated and the channel axis copied here; the host planning (rest-frame edges,
+ * Eq. 3-4 overlap table, a_k = nu_k / c) is handed to a pool of library threads and runs
+ * while the caller adds more targets (finalize waits for it and reports its errors),
+ * except for a target whose widest rest-frame channel could overlap more rest channels
+ * than the overlap table holds: that one is planned and checked here.  Device work is
+ * deferred to vista_stack_finalize, which stacks all targets in one pass.  VISTA_MEM_HOST
+ * data are copied to library staging before the call returns; VISTA_MEM_HOST_PINNED and
+ * VISTA_MEM_DEVICE data must stay valid and unchanged until finalize returns (the library
+ * keeps only pointers).  Errors: ARG (see vista_target; the stack is unchanged), STATE
+ * (after finalize or poisoned), NOMEM, HIP. */
 int vista_stack_add_target(vista_stack* s, const vista_target* t);
 
-/* Select the launch shape (NULL = defaults).  Only before finalize. */
+/* Select the launch shape (NULL = defaults).  Only before finalize.  Errors: ARG (a shape
+ * the kernels are not built for, or that does not fit the flags), STATE. */
 int vista_stack_set_tuning(vista_stack* s, const vista_tuning* tu);
 
-/* Stack every added target, write the outputs, synchronise the stream and return the
- * classification in *st (may be NULL).  Every output cell is written.  A stack is
- * finalized once; later add/finalize calls return VISTA_E_STATE.  Errors: ARG, STATE,
- * NOMEM, HIP, RANGE (a count above 2^32-1; outputs are then undefined). */
+/* Stack every added target: Eq. 2's shift of each sample to its target's position, the
+ * rest frame of Sec. 3.1 with uvw in wavelengths at the sample's own frequency, and the
+ * Eq. 3-4 overlap-weighted accumulation of every (row, channel, polarisation) into the
+ * grid's sum(w f V'), sum(w f) and counts.  Writes every cell of the outputs o (device,
+ * pinned or pageable host memory, dense [nchan][nv][nu]; any field NULL to skip it; NULL o
+ * for statistics only), synchronises the stack's stream and returns the classification in
+ * *st (may be NULL).  The library owns the grid state and scratch (freed or cached for the
+ * thread before return).  A stack is finalized once; later add/finalize calls return
+ * VISTA_E_STATE.  Errors: ARG (misaligned or unknown-memory outputs), STATE, NOMEM, HIP
+ * (the handle is then poisoned), RANGE (a count above 2^32-1; outputs are then undefined). */
 int vista_stack_finalize(vista_stack* s, const vista_output* o, vista_stats* st);
 
-/* Timings of the finalize of this stack (zeros before it). */
+/* Timings of the finalize of this stack (zeros before it).  Errors: ARG. */
 int vista_stack_timings(const vista_stack* s, vista_timings* t);
 
-/* Release everything the stack owns.  Always succeeds for a non-NULL handle. */
+/* Release everything the stack owns (waiting for its planning threads).  Always succeeds
+ * for a non-NULL handle, poisoned ones included.  Errors: ARG (NULL). */
 int vista_stack_destroy(vista_stack* s);
 
 /* Stacks keep a per-thread launch workspace between calls -- row contexts, binning records,
@@ -208,26 +224,48 @@ int vista_stack_destroy(vista_stack* s);
  * allocates them again).  It waits for the device.  Errors: HIP. */
 int vista_release_workspace(void);
 
-/* Batched form: n_stacks independent stacks (each with its own grid g[i]) run in one
- * persistent, hipGraph-replayed launch sequence per wave.  Targets are recorded by
- * vista_batch_add_target; vista_batch_run stacks them all.  When the inputs exceed
- * device memory (VISTA_MEM_HOST_PINNED targets beyond the device budget), they are
- * streamed in waves through double-buffered device staging on a copy stream, and the
- * grid state is carried across waves (compensated when VISTA_F_KAHAN). */
+/* ---- Batched form (Sec. 3.3: N_batch datasets packed into contiguous device buffers and
+ * processed per launch, while the host reads the next ones) ---------------------------
+ *
+ * n_stacks independent stacks (each with its own grid g[i]; every stack of a batch has
+ * the same KAHAN, DETERMINISTIC, PHASE_FP32 and PLAIN_FP32 flags) run in one persistent
+ * launch sequence per wave, captured once as a hipGraph and replayed.  Targets are recorded
+ * by vista_batch_add_target (as vista_stack_add_target, into stack `stack`);
+ * vista_batch_run stacks them all.  Targets in host memory are streamed in waves of at most
+ * the stream budget through two device staging buffers on a copy stream, double-buffered
+ * against compute (Sec. 3.2's read/compute overlap); device-resident targets run in the
+ * first wave.  A stack whose targets span several waves carries its grid state across
+ * them in FP32, merged with compensated (Kahan) additions when VISTA_F_KAHAN.
+ * Ownership as for stacks: pinned and device inputs stay valid until vista_batch_run
+ * returns; registered device outputs are written in place; otherwise the batch keeps the
+ * results on the device until vista_batch_finalize copies them out.
+ * Errors: create -- ARG (count, grids, mixed flags), NOMEM; add -- as stack add, and ARG for
+ * a stack index out of range; run -- STATE (run twice or poisoned), NOMEM (a target larger
+ * than the stream budget, device memory), HIP (poisons); finalize -- ARG, STATE (before the
+ * run), HIP, RANGE. */
 int vista_batch_create(int32_t n_stacks, const vista_grid_desc* g, void* hip_stream, vista_batch** out);
 int vista_batch_add_target(vista_batch* b, int32_t stack, const vista_target* t);
+/* Launch shape of the batch (NULL = defaults).  Only before the run.  Errors: ARG, STATE. */
 int vista_batch_set_tuning(vista_batch* b, const vista_tuning* tu);
-/* Device memory the batch may use for streamed input staging (bytes; 0 = default). */
+/* Device memory per staging buffer for streamed inputs (bytes; 0 = an eighth of the free
+ * device memory).  Errors: ARG (negative). */
 int vista_batch_set_stream_budget(vista_batch* b, int64_t bytes);
 /* Register the outputs of one stack before vista_batch_run: VISTA_MEM_DEVICE outputs
  * are then written by the run itself (no copy at finalize), and only the outputs given
  * are produced.  Other memory kinds are filled at finalize.  Errors: ARG, STATE. */
 int vista_batch_set_output(vista_batch* b, int32_t stack, const vista_output* o);
+/* Stack every stack's targets (as vista_stack_finalize does for one), all waves; returns
+ * when the results are complete on the device and the caller's stream is ordered after
+ * them.  Errors: see above. */
 int vista_batch_run(vista_batch* b);
 /* Copy one stack's results into o (may be NULL when its outputs were registered) and
  * return its classification in *st (may be NULL).  Errors: ARG, STATE, HIP, RANGE. */
 int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, vista_stats* st);
+/* Timings of the run (bin_ms and accum_ms summed over waves, h2d_ms the streamed copies).
+ * Errors: ARG. */
 int vista_batch_timings(const vista_batch* b, vista_timings* t);
+/* Release the batch and its device results (waiting for the device).  Always succeeds for
+ * a non-NULL handle.  Errors: ARG (NULL). */
 int vista_batch_destroy(vista_batch* b);
 
 /* The paper's common rest grid (Sec. 3.1): dfreq = max over targets and channels of the
@@ -303,10 +341,12 @@ int vista_rebin_rows(const vista_rebin_desc* d, int32_t n_targets, const vista_t
 int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image, float* beam,
                 void* hip_stream, vista_timings* tim);
 
-/* Per (row, channel) indices the GPU computes for one target, for bit-exact checks:
- * iu, iv (the nearest cell before the bounds test, INT32_MIN when not representable),
- * j0 (first rest channel of the channel's overlap set, -1 if empty) and nj (its size).
- * Outputs [nrow][nchan] in host memory; the target's data follow t->mem. */
+/* Per (row, channel) indices the GPU computes for one target, for bit-exact checks of the
+ * cell assignment (uvw in wavelengths at the sample's frequency, Sec. 3.1 and Eq. 1) and of
+ * the Eq. 4 overlap set: iu, iv (the nearest cell before the bounds test, INT32_MIN when
+ * not representable), j0 (first rest channel of the channel's overlap set, -1 if empty)
+ * and nj (its size).  Outputs [nrow][nchan] int32 in host memory, caller-owned; the
+ * target's data follow t->mem.  Synchronises hip_stream.  Errors: ARG, NOMEM, HIP. */
 int vista_debug_indices(const vista_grid_desc* g, const vista_target* t, void* hip_stream,
                         int32_t* iu, int32_t* iv, int32_t* j0, int32_t* nj);
 

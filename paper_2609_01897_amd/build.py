@@ -32,9 +32,22 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc()] + COMMON + DEVICE + ["-c", os.path.join(SRC_DIR, src), "-o", obj]
+SANITIZERS = ("address", "undefined", "thread")
+
+
+def _san_flags(sanitize):
+    """Host-code sanitizer flags: each -fsanitize= goes after -Xarch_host, so device code
+    is built as usual (no GPU sanitizer)."""
+    if not sanitize:
+        return []
+    if sanitize not in SANITIZERS:
+        raise ValueError("sanitize must be one of %s" % (SANITIZERS,))
+    return ["-Xarch_host", "-fsanitize=" + sanitize, "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, verbose: bool, out_dir: str = OUT_DIR, sanitize=None) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [_hipcc()] + COMMON + DEVICE + _san_flags(sanitize) + ["-c", os.path.join(SRC_DIR, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,21 +56,33 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libvista.so; returns the library path."""
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: str | None = None) -> str:
+    """Compile every source and link libvista.so; returns the library path.
+
+    sanitize = "address", "undefined" or "thread" builds a host-sanitized copy instead, in
+    _build_<sanitize>/ (the normal library is left alone).  Load it by pointing VISTA_LIB at
+    it, with the sanitizer runtime preloaded, e.g. for AddressSanitizer:
+        VISTA_LIB=paper_2609_01897_amd/_build_address/libvista.so \
+        LD_PRELOAD=$(/opt/rocm/llvm/bin/clang -print-file-name=libclang_rt.asan-x86_64.so) \
+        ASAN_OPTIONS=detect_leaks=0 python -m pytest tests -m "not gpu"
+    (the interpreter itself is not instrumented, hence no leak check)."""
+    out_dir = OUT_DIR if not sanitize else os.path.join(HERE, "_build_" + sanitize)
+    lib = os.path.join(out_dir, "libvista.so")
+    os.makedirs(out_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
+        objs = list(ex.map(lambda s: _compile(s, verbose, out_dir, sanitize), SOURCES))
+    tmp = lib + ".tmp%d" % os.getpid()
+    link_san = ["-fsanitize=" + sanitize, "-shared-libsan"] if sanitize else []
+    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + link_san + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-6000:])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    san = next((a.split("=", 1)[1] for a in sys.argv[1:] if a.startswith("--sanitize=")), None)
+    print(build(verbose="-v" in sys.argv, sanitize=san))

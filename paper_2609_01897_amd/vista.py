@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "libvista.so")
+# VISTA_LIB selects another build of the library (e.g. a host-sanitized one).
+LIB_PATH = os.environ.get("VISTA_LIB") or os.path.join(HERE, "_build", "libvista.so")
 
 VISTA_OK, VISTA_E_ARG, VISTA_E_STATE, VISTA_E_NOMEM, VISTA_E_HIP, VISTA_E_RANGE = 0, -1, -2, -3, -4, -5
 MEM_HOST, MEM_HOST_PINNED, MEM_DEVICE = 0, 1, 2
@@ -449,3 +450,4 @@ def image(grid: dict, sum_wvis, sum_w, beam: bool = False, out=None, stream=None
 def release_workspace():
     """Free the calling thread's cached launch workspace (``vista_release_workspace``)."""
     _check(lib().vista_release_workspace())
+
