@@ -341,6 +341,21 @@ int vista_rebin_rows(const vista_rebin_desc* d, int32_t n_targets, const vista_t
 int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image, float* beam,
                 void* hip_stream, vista_timings* tim);
 
+/* vista_image without allocating: for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same images as
+ * vista_image (the same kernels, channels taken in passes that fit the scratch), with no
+ * device allocation, no host-device synchronisation and no timing: the call only enqueues the
+ * work on hip_stream and returns; the outputs are complete when the stream reaches that point.
+ * Staging lives in a fixed device scratch of the library (64 MiB of complex planes plus 512 KiB
+ * of channel weight sums), one per device, held until the process ends.  Limit: one
+ * nu x nv complex plane must fit the staging, nu * nv <= 8388608 (e.g. 4096 x 2048; a
+ * 4096 x 4096 grid is refused with VISTA_E_ARG).  Other arguments as vista_image.  Every call
+ * on a device shares that device's scratch: calls that overlap in time on one device (on
+ * different streams, or from several threads without ordering) race and corrupt each other's
+ * images; calls ordered on one stream do not.  Errors: ARG, HIP. */
+int vista_image_noalloc(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image,
+                        float* beam, void* hip_stream);
+
 /* Per (row, channel) indices the GPU computes for one target, for bit-exact checks of the
  * cell assignment (uvw in wavelengths at the sample's frequency, Sec. 3.1 and Eq. 1) and of
  * the Eq. 4 overlap set: iu, iv (the nearest cell before the bounds test, INT32_MIN when

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "vista_device.h"
 
@@ -232,35 +233,77 @@ int log2i(int n) {
 size_t image_temp_bytes(int nu, int nv, int nchan) { return (size_t)nu * nv * nchan * sizeof(float2); }
 
 hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, float* beam, int nu, int nv,
-                        int nchan, float2* tmp, double* wsum, hipStream_t stream) {
+                        int nchan, float2* tmp, size_t tmp_bytes, double* wsum, hipStream_t stream) {
     if (nchan <= 0) return hipSuccess;
     const int lognu = log2i(nu), lognv = log2i(nv);
     if ((1 << lognu) != nu || (1 << lognv) != nv || nu < 2 || nv < 2 || nu > kMaxSide || nv > kMaxSide)
         return hipErrorInvalidValue;
+    const size_t plane = (size_t)nu * nv;
+    // channels per pass: as many staging planes as tmp holds (all of them when it holds the cube)
+    const int64_t per_pass = std::min<int64_t>(nchan, (int64_t)(tmp_bytes / (plane * sizeof(float2))));
+    if (per_pass < 1) return hipErrorInvalidValue;
     const int rows = std::min(nv, std::max(1, kRowElems / nu));
     const int cols = std::min(nu, std::max(1, kColElems / nv));
     const int logcols = log2i(cols);
-    const int nct = (int)((int64_t)nchan * (nu / cols));
     const size_t lrow = 2 * (size_t)rows * nu * sizeof(float2), lcol = 2 * (size_t)cols * nv * sizeof(float2);
     const float sign = (nu == 2 ? -1.f : 1.f) * (nv == 2 ? -1.f : 1.f);
     if (((uintptr_t)sum_w & 15) == 0)
-        hipLaunchKernelGGL(k_image_wsum<true>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)nu * nv,
-                           wsum);
+        hipLaunchKernelGGL(k_image_wsum<true>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)plane, wsum);
     else
-        hipLaunchKernelGGL(k_image_wsum<false>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)nu * nv,
+        hipLaunchKernelGGL(k_image_wsum<false>, dim3(nchan), dim3(kSumThreads), 0, stream, sum_w, (int64_t)plane,
                            wsum);
     const bool cfull = cols * nv == kColThreads * kColRegs;
     auto cols_k = cfull ? k_image_cols<true> : k_image_cols<false>;
-    const dim3 grow(nv / rows, nchan), gcol(persistent_blocks(cols_k, kColThreads, lcol, nct));
-    hipLaunchKernelGGL(k_image_rows<false>, grow, dim3(kRowThreads), lrow, stream, sum_wvis, tmp, lognu, nv, rows);
-    hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum, image, lognu, lognv, logcols, nct,
-                       sign);
-    if (beam) {
-        hipLaunchKernelGGL(k_image_rows<true>, grow, dim3(kRowThreads), lrow, stream, sum_w, tmp, lognu, nv, rows);
-        hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum, beam, lognu, lognv, logcols,
-                           nct, sign);
+    // channels [j0, j0 + nc): the kernels see the pass's slice of every array (planes are
+    // multiples of 4 elements, so the slices keep the arrays' alignment)
+    for (int64_t j0 = 0; j0 < nchan; j0 += per_pass) {
+        const int nc = (int)std::min<int64_t>(per_pass, nchan - j0);
+        const int nct = (int)((int64_t)nc * (nu / cols));
+        const dim3 grow(nv / rows, nc), gcol(persistent_blocks(cols_k, kColThreads, lcol, nct));
+        const size_t off = (size_t)j0 * plane;
+        hipLaunchKernelGGL(k_image_rows<false>, grow, dim3(kRowThreads), lrow, stream,
+                           (const void*)((const float2*)sum_wvis + off), tmp, lognu, nv, rows);
+        hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum + j0, image + off, lognu, lognv,
+                           logcols, nct, sign);
+        if (beam) {
+            hipLaunchKernelGGL(k_image_rows<true>, grow, dim3(kRowThreads), lrow, stream,
+                               (const void*)(sum_w + off), tmp, lognu, nv, rows);
+            hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum + j0, beam + off, lognu,
+                               lognv, logcols, nct, sign);
+        }
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------- scratch of the no-alloc entry point
+
+// Device scratch of vista_image_noalloc: the complex staging planes of one pass and the
+// channels' FP64 weight sums.  Each device that loads the library holds its own copy until
+// the process ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is no device address on the host).
+static __device__ __align__(256) unsigned char scratch[kNoAllocImageStaging + kNoAllocImageWsum];
+
+void* image_noalloc_scratch(hipError_t* err) {
+    static std::mutex m;
+    static void* ptrs[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(m);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        ptrs[dev] = p;
+    }
+    *err = hipSuccess;
+    return ptrs[dev];
 }
 
 }  // namespace vista

@@ -218,11 +218,19 @@ hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 // Dirty image of every channel of a stacked grid (vista_image.hip): nu, nv powers of two
-// in 2..4096; tmp holds image_temp_bytes(nu, nv, nchan), wsum nchan doubles; beam may be
-// null.
+// in 2..4096; tmp holds tmp_bytes (at least one nu x nv complex plane; the channels are
+// imaged in passes of as many planes as it holds: image_temp_bytes(nu, nv, nchan) is one
+// pass), wsum nchan doubles; beam may be null.
 size_t image_temp_bytes(int nu, int nv, int nchan);
 hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, float* beam, int nu, int nv,
-                        int nchan, float2* tmp, double* wsum, hipStream_t stream);
+                        int nchan, float2* tmp, size_t tmp_bytes, double* wsum, hipStream_t stream);
+// The no-alloc imaging scratch: kNoAllocImageStaging bytes of staging planes, then
+// kNoAllocImageWsum bytes of weight sums (65535 doubles), 256-byte aligned.  Returns the
+// current device's address of it (looked up once per device), or nullptr with *err set.
+constexpr size_t kNoAllocImageStaging = (size_t)64 << 20;
+constexpr size_t kNoAllocImageWsum = (size_t)512 << 10;
+constexpr int kMaxDevices = 64;
+void* image_noalloc_scratch(hipError_t* err);
 // The per-row rebinning (vista_rebin.hip) over `nblocks` row blocks; every target of the
 // launch has `npol` polarisations (1, 2 or 4).
 hipError_t launch_rebin_rows(const RebinTarget* targets, const RebinBlock* blocks, int64_t nblocks, int npol,

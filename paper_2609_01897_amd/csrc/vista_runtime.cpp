@@ -1694,7 +1694,9 @@ int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum
         float2* tmp = (float2*)mem.alloc(image_temp_bytes(g->nu, g->nv, g->nchan));
         double* wsum = mem.alloc_n<double>(g->nchan);
         VISTA_HIP(hipEventRecord(ev.e[0], stream));
-        check_launch(launch_image(sum_wvis, sum_w, image, beam, g->nu, g->nv, g->nchan, tmp, wsum, stream), "image");
+        check_launch(launch_image(sum_wvis, sum_w, image, beam, g->nu, g->nv, g->nchan, tmp,
+                                  image_temp_bytes(g->nu, g->nv, g->nchan), wsum, stream),
+                     "image");
         VISTA_HIP(hipEventRecord(ev.e[1], stream));
         VISTA_HIP(hipStreamSynchronize(stream));
         mem.release();
@@ -1705,6 +1707,42 @@ int vista_image(const vista_grid_desc* g, const void* sum_wvis, const float* sum
             tim->total_ms = tim->accum_ms;
             tim->n_accum_launches = beam ? 5 : 3;
         }
+        return VISTA_OK;
+    });
+}
+
+int vista_image_noalloc(const vista_grid_desc* g, const void* sum_wvis, const float* sum_w, float* image,
+                        float* beam, void* hip_stream) {
+    if (!g) return fail(VISTA_E_ARG, "grid descriptor is NULL");
+    auto pow2 = [](int32_t n) { return n >= 2 && n <= 4096 && (n & (n - 1)) == 0; };
+    if (!pow2(g->nu) || !pow2(g->nv)) return fail(VISTA_E_ARG, "vista_image_noalloc needs nu and nv powers of two in 2..4096");
+    if (g->nchan < 1 || g->nchan > 65535) return fail(VISTA_E_ARG, "vista_image_noalloc needs nchan in 1..65535");
+    const size_t plane_bytes = (size_t)g->nu * g->nv * sizeof(float2);
+    if (plane_bytes > kNoAllocImageStaging)
+        return fail(VISTA_E_ARG, "vista_image_noalloc: one " + std::to_string(g->nu) + " x " + std::to_string(g->nv) +
+                                     " plane needs " + std::to_string(plane_bytes >> 20) +
+                                     " MiB of staging, more than its fixed 64 MiB scratch (nu * nv <= 8388608)");
+    if (!sum_wvis || !sum_w || !image) return fail(VISTA_E_ARG, "sum_wvis, sum_w and image are required");
+    if (((uintptr_t)sum_wvis % 8) || ((uintptr_t)sum_w % 4) || ((uintptr_t)image % 4) || ((uintptr_t)beam % 4))
+        return fail(VISTA_E_ARG, "arrays are not aligned to their element size");
+    for (const void* ptr : {(const void*)sum_wvis, (const void*)sum_w, (const void*)image, (const void*)beam}) {
+        if (!ptr) continue;
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(VISTA_E_ARG, "vista_image_noalloc needs device memory");
+        }
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    return guarded(nullptr, [&]() -> int {
+        hipError_t e = hipSuccess;
+        unsigned char* base = (unsigned char*)image_noalloc_scratch(&e);
+        if (!base) throw HipFail{e, "hipGetSymbolAddress(scratch)"};
+        float2* tmp = (float2*)base;
+        double* wsum = (double*)(base + kNoAllocImageStaging);
+        check_launch(launch_image(sum_wvis, sum_w, image, beam, g->nu, g->nv, g->nchan, tmp, kNoAllocImageStaging,
+                                  wsum, stream),
+                     "image");
         return VISTA_OK;
     });
 }

@@ -105,6 +105,8 @@ SYMBOLS = {
     "vista_batch_set_output": ([C.c_void_p, C.c_int32, C.POINTER(Output)], C.c_int),
     "vista_image": ([C.POINTER(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.POINTER(Timings)], C.c_int),
+    "vista_image_noalloc": ([C.POINTER(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                            C.c_int),
     "vista_rebin_window": ([C.POINTER(RebinDesc), C.POINTER(TargetDesc), C.POINTER(C.c_double)], C.c_int),
     "vista_rebin_rows": ([C.POINTER(RebinDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.POINTER(Timings)], C.c_int),
@@ -451,3 +453,10 @@ def release_workspace():
     """Free the calling thread's cached launch workspace (``vista_release_workspace``)."""
     _check(lib().vista_release_workspace())
 
+
+def image_noalloc(grid: dict, sum_wvis, sum_w, image, beam=None, stream=None):
+    """``vista_image_noalloc``: the dirty images written into the given device tensors with
+    no device allocation; only enqueued on the stream (torch's current one by default)."""
+    s = current_stream() if stream is None else stream
+    _check(lib().vista_image_noalloc(C.byref(grid_desc(grid)), _ptr(sum_wvis), _ptr(sum_w), _ptr(image),
+                                     _ptr(beam), s))
