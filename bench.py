@@ -382,7 +382,7 @@ BATCH_POOL_BYTES = 120e9      # device-resident pool of distinct datasets
 BATCH_CHECK = (3, (124, 132))  # stack checked against the oracle, and its rest channels
 
 
-def batched_leg(reps=1, with_reference=True):
+def batched_leg(reps=1, with_reference=True, forms=None):
     """The batched recipe at its own shape: 64 stacks of clip(round(lognormal(ln 40, 1)),
     5, 500) targets (3871 in all), 12-50 antennas, 60 integrations, channels from {128, 480,
     960, 3840}, z ~ U(0.5, 4), grids of 256 x 256 x 256.  Its 3.1 TB of input exceed HBM, so
@@ -460,10 +460,12 @@ def batched_leg(reps=1, with_reference=True):
                        "grid 256x256x256 per stack; targets draw on a device-resident pool of %d distinct datasets "
                        "(%.0f GB)" % (len(stacks), len(all_t), len(pool), pool_bytes / 1e9),
            "samples": nsamp, "algorithmic_bytes": nbytes, "launch_shape": "library defaults"}
-    forms = [("plain_fp32_one_stack_per_launch", per_launch(vista.F_PLAIN_FP32)),
-             ("compensated_one_stack_per_launch", per_launch(0)),
-             ("batched_compensated", batched(0))]
-    for name, fn in forms:
+    all_forms = [("plain_fp32_one_stack_per_launch", per_launch(vista.F_PLAIN_FP32)),
+                 ("compensated_one_stack_per_launch", per_launch(0)),
+                 ("batched_compensated", batched(0))]
+    for name, fn in all_forms:
+        if forms and name not in forms:
+            continue
         ms, acc_ms = timed(fn)
         rec = {"ms": ms, "accumulate_ms": acc_ms, "samples_per_s": nsamp / (ms / 1e3),
                "roofline": roofline(nbytes, acc_ms)}
@@ -474,10 +476,11 @@ def batched_leg(reps=1, with_reference=True):
         log("batched recipe, %s: %.1f ms (accumulate %.1f ms, %.0f GB/s)%s" % (
             name, ms, acc_ms, rec["roofline"]["achieved"],
             "" if ref is None else ", max |dS|/A %.2e" % rec["accuracy"]["max_dS_over_A"]))
-    res["speedup_batched_compensated_vs_plain_fp32_per_launch"] = (
-        res["plain_fp32_one_stack_per_launch"]["ms"] / res["batched_compensated"]["ms"])
-    res["speedup_batched_vs_per_launch_same_precision"] = (
-        res["compensated_one_stack_per_launch"]["ms"] / res["batched_compensated"]["ms"])
+    if not forms:
+        res["speedup_batched_compensated_vs_plain_fp32_per_launch"] = (
+            res["plain_fp32_one_stack_per_launch"]["ms"] / res["batched_compensated"]["ms"])
+        res["speedup_batched_vs_per_launch_same_precision"] = (
+            res["compensated_one_stack_per_launch"]["ms"] / res["batched_compensated"]["ms"])
     if ref_s is not None:
         res["oracle_reference_s"] = ref_s
     del outs, stacks, pool, all_t
@@ -678,6 +681,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the plain FP32 and deterministic forms")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision recipe")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched recipe")
+    ap.add_argument("--batched-forms", default="", help="comma list of the batched recipe's forms to run "
+                    "(plain_fp32_one_stack_per_launch, compensated_one_stack_per_launch, batched_compensated); "
+                    "default all")
     ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed recipe")
     ap.add_argument("--no-rebinned", action="store_true", help="skip the per-row rebinned leg")
     ap.add_argument("--no-rotated", action="store_true", help="skip the step with Eq. 1's rotation on")
@@ -815,7 +821,8 @@ def main():
         if skip:
             continue
         try:
-            res[name] = leg(with_reference=not args.no_cpu)
+            kw = {"forms": [f for f in args.batched_forms.split(",") if f]} if name == "batched" else {}
+            res[name] = leg(with_reference=not args.no_cpu, **kw)
         except Exception as e:                  # the main line is printed whatever a leg does
             log("%s leg failed: %r" % (name, e))
             res[name] = {"error": repr(e)}
