@@ -23,6 +23,18 @@
  *     VISTA_E_ARG and leaves the handle unchanged.  A HIP failure returns VISTA_E_HIP and
  *     poisons the handle: afterwards every call except *_destroy returns VISTA_E_STATE.
  *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ *
+ * Environment
+ *   VISTA_LOG=0..3           stderr diagnostics: 1 a line per launch and batch run (records,
+ *                            units, device times), 2 also autotune candidates and wave plans.
+ *   VISTA_TUNE_CACHE=path    file of JSON lines keyed by a workload signature: autotune calls
+ *                            take a cached shape instead of timing, and append new winners.
+ *   VISTA_AGGREGATE=0|1      force the accumulation's LDS updates direct (0) or summed across
+ *                            the lanes of a wavefront first (1); by default the latter is used
+ *                            for launches of mostly fine channels (6 or more per rest channel).
+ *   VISTA_DEVICE_MEM_LIMIT=n cap on the device bytes the library holds (failure testing).
+ *   VISTA_FAULT_INJECT=alloc|launch  fail the next device allocation or kernel launch from the
+ *                            host, before the operation (failure testing).
  */
 #ifndef VISTA_H
 #define VISTA_H

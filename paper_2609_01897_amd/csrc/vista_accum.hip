@@ -175,6 +175,56 @@ __device__ __forceinline__ void issue(const VISTA_GLOBAL DevChan* chan_all, cons
     load_sample<NPOL>(chan_all, f1_all, c, p1, x.s[1]);
 }
 
+// One slot of contributions from every lane of the wavefront (all lanes call it together):
+// lane adds (re, im, w, n) to LDS cell `key` (key < 0: nothing).  Lanes hold consecutive
+// stream positions, so lanes adding to one cell form contiguous runs -- long ones where many
+// input channels fall in one rest channel and one uv cell (fine channels, short baselines),
+// and there the cell's LDS address would take one atomic per lane, one after another.  When
+// the runs are 4 lanes long or more on average, each run is first summed across its lanes
+// (a segmented inclusive scan, the run's last lane ends with its total) and only that lane
+// adds to LDS; otherwise every lane adds its own values.  Sums are in Acc either way.
+template <class Acc>
+__device__ __forceinline__ void emit(Acc* s_re, Acc* s_im, Acc* s_w, uint32_t* s_n, int lane, int key, Acc re,
+                                     Acc im, Acc w, uint32_t n) {
+    const uint64_t act = __ballot(key >= 0);
+    if (act == 0) return;
+    const int prev = __shfl_up(key, 1, kWave);
+    const bool head = key >= 0 && (lane == 0 || prev != key);
+    const uint64_t heads = __ballot(head);
+    if (__popcll(heads) * 4 <= __popcll(act)) {
+        // the lane's run starts at the last head at or below it (an inactive lane ends a run,
+        // the next active lane heads one); the lanes d below it are in its run while
+        // d <= span
+        const uint64_t upto = heads & ((2ull << lane) - 1ull);      // lane 63: every bit
+        const int start = upto ? 63 - (int)__clzll(upto) : lane;
+        const int span = key >= 0 ? lane - start : -1;
+#pragma unroll 1
+        for (int d = 1; d < kWave; d <<= 1) {
+            const Acc r2 = __shfl_up(re, d, kWave), i2 = __shfl_up(im, d, kWave), w2 = __shfl_up(w, d, kWave);
+            const uint32_t n2 = __shfl_up(n, d, kWave);
+            if (d <= span) {
+                re += r2;
+                im += i2;
+                w += w2;
+                n += n2;
+            }
+        }
+        // the run's last lane holds its total
+        const uint64_t ends = heads | ~act;
+        if (key >= 0 && (lane == kWave - 1 || ((ends >> (lane + 1)) & 1ull))) {
+            atomicAdd(&s_re[key], re);
+            atomicAdd(&s_im[key], im);
+            atomicAdd(&s_w[key], w);
+            atomicAdd(&s_n[key], n);
+        }
+    } else if (key >= 0) {
+        atomicAdd(&s_re[key], re);
+        atomicAdd(&s_im[key], im);
+        atomicAdd(&s_w[key], w);
+        atomicAdd(&s_n[key], n);
+    }
+}
+
 // Per-wavefront classification and contribution counts (wave-uniform, from ballots), kept
 // over many units and added to the stack's statistics when the stack changes, every 64
 // units and at the end.
@@ -197,7 +247,10 @@ struct WaveStats {
 
 __device__ __forceinline__ uint64_t popc_ballot(bool p) { return (uint64_t)__popcll(__ballot(p)); }
 
-template <int TU, int TV, int JC, int NPOL, class Acc>
+// Pairs of stream positions per slice of a wavefront's share of a unit (4096 samples).
+constexpr uint64_t kSlicePairs = 2048;
+
+template <int TU, int TV, int JC, int NPOL, class Acc, bool AGG>
 __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __restrict__ Lp,
                                                           const uint64_t* __restrict__ order,
                                                           uint32_t* __restrict__ counter,
@@ -264,13 +317,25 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
         const uint32_t re = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit + 1]);
         uint64_t u_contrib = 0;           // wave-uniform (ballots)
         uint32_t u_contrib_l = 0;         // per lane (rest channels beyond j0 + 1)
-        uint64_t sw0 = 0, sw1 = 0;
+        // the unit's stream, in pairs, dealt to the wavefronts in slices of kSlicePairs: wave
+        // w takes slices w, w + nw, ... of every full round, then an even share of what the
+        // full rounds leave, so that at any time the wavefronts work on nearby records (rows
+        // of one target share channel-table entries and cache lines) and finish together
+        uint64_t sp0 = 0, npairs = 0;
         if (rb < re) {
-            // the unit's stream, in pairs, split evenly over the wavefronts
-            const uint64_t p0 = ufl64(cpre[rb]), p1 = ufl64(cpre[re]);
-            const uint64_t pairs = (p1 - p0) >> 1;
-            sw0 = p0 + 2 * (pairs * (uint64_t)wave / (uint64_t)nw);
-            sw1 = p0 + 2 * (pairs * (uint64_t)(wave + 1) / (uint64_t)nw);
+            sp0 = ufl64(cpre[rb]);
+            npairs = (ufl64(cpre[re]) - sp0) >> 1;
+        }
+        const uint64_t round = (uint64_t)nw * kSlicePairs;
+        const uint64_t nfull = npairs / round, rest = npairs - nfull * round;
+        for (uint64_t rr = 0; rr <= nfull; ++rr) {
+        uint64_t sw0, sw1;
+        if (rr < nfull) {
+            sw0 = sp0 + 2 * ((rr * nw + wave) * kSlicePairs);
+            sw1 = sw0 + 2 * kSlicePairs;
+        } else {
+            sw0 = sp0 + 2 * (nfull * round + rest * (uint64_t)wave / (uint64_t)nw);
+            sw1 = sp0 + 2 * (nfull * round + rest * (uint64_t)(wave + 1) / (uint64_t)nw);
         }
         if (sw0 < sw1) {
             // ---- the record holding sample sw0: largest i in [rb, re) with pre[i] <= sw0
@@ -362,9 +427,23 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 x.act = live && s + 2u * (uint64_t)lane < sw1;
             };
 
-            // one sample: g0, g1 tell whether the record's row weights are usable (NPOL == 2)
-            auto process = [&](const RecCtx<NPOL>& rc, const Loaded<NPOL>& x, bool valid, int32_t ci, bool g0,
+            // What one sample adds: its LDS cell row (cell + j is the cell of rest channel j),
+            // rest channel j0, whether it adds to j0 and j0 + 1 in this unit's block, the
+            // merged polarisations rotated (pr, pi), their weight q and count n, and the
+            // overlap fractions.
+            struct Contrib {
+                int cell;
+                int32_t j0;
+                bool add0, add1;
+                float pr, pi, q, f0, f1;
+                uint32_t n;
+            };
+            // one sample: g0, g1 tell whether the record's row weights are usable (NPOL == 2);
+            // the statistics are counted here, and the rare rest channels beyond j0 + 1 (a
+            // rest grid finer than the channel) are added here; the rest is returned
+            auto prepare = [&](const RecCtx<NPOL>& rc, const Loaded<NPOL>& x, bool valid, int32_t ci, bool g0,
                                bool g1) __attribute__((always_inline)) {
+                Contrib o;
                 const uint32_t nj = valid ? x.jn >> 24 : 0u;
                 const int32_t j0 = (int32_t)(x.jn & kJMask);
                 // cell within the tile (exact FP64 sequence of the definition)
@@ -396,45 +475,37 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     ai = fmaf(wu, x.vi[p], ai);
                     q += wu;
                 }
-                float c, s;
+                float c, sn;
                 if (phase_fp32) {
                     const float t = (float)rc.T * (float)x.a;
-                    sincos_turns(t - rintf(t), &s, &c);
+                    sincos_turns(t - rintf(t), &sn, &c);
                 } else {
-                    phasor(rc.T, x.a, &c, &s);
+                    phasor(rc.T, x.a, &c, &sn);
                 }
-                const float pr = ar * c - ai * s;
-                const float pi = fmaf(ar, s, ai * c);
+                o.pr = ar * c - ai * sn;
+                o.pi = fmaf(ar, sn, ai * c);
+                o.q = q;
+                o.n = n;
+                o.f0 = x.f0;
+                o.f1 = x.f1;
+                o.j0 = j0;
                 // rest channels j0 and j0 + 1 of this unit's block (counted before any lane leaves)
                 const bool live_add = in_tile && n > 0;
-                const bool add0 = live_add && j0 >= jb0 && j0 < jb1;
-                const bool add1 = live_add && nj > 1 && j0 + 1 >= jb0 && j0 + 1 < jb1;
+                o.add0 = live_add && j0 >= jb0 && j0 < jb1;
+                o.add1 = live_add && nj > 1 && j0 + 1 >= jb0 && j0 + 1 < jb1;
 #pragma unroll
                 for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p)
-                    u_contrib += popc_ballot(add0 && use_p[p]) + popc_ballot(add1 && use_p[p]);
-                if (!live_add) return;
-                const int cell = (lv * TU + lu) * JP - jb0;
-                // FP64: the products of FP32 values are exact; FP32: one rounding each
-                const Acc dr = (Acc)pr, di = (Acc)pi, dq = (Acc)q;
-#pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                    if (qq == 0 ? add0 : add1) {
-                        const Acc f = (Acc)(qq == 0 ? x.f0 : x.f1);
-                        const int cc = cell + j0 + qq;
-                        atomicAdd(&s_re[cc], f * dr);
-                        atomicAdd(&s_im[cc], f * di);
-                        atomicAdd(&s_w[cc], f * dq);
-                        atomicAdd(&s_n[cc], n);
-                    }
-                }
+                    u_contrib += popc_ballot(o.add0 && use_p[p]) + popc_ballot(o.add1 && use_p[p]);
+                o.cell = (lv * TU + lu) * JP - jb0;
                 // more than two rest channels (rest grid finer than the channel): rare
-                if (nj > 2) {
+                if (live_add && nj > 2) {
+                    const Acc dr = (Acc)o.pr, di = (Acc)o.pi, dq = (Acc)q;
                     const int32_t fo = gptr(L.foff_all)[ci];
                     for (int qq = 2; qq < (int)nj; ++qq) {
                         const int32_t j = j0 + qq;
                         if (j < jb0 || j >= jb1) continue;
                         const Acc f = (Acc)gptr(L.fval_all)[fo + qq];
-                        const int cc = cell + j;
+                        const int cc = o.cell + j;
                         atomicAdd(&s_re[cc], f * dr);
                         atomicAdd(&s_im[cc], f * di);
                         atomicAdd(&s_w[cc], f * dq);
@@ -442,6 +513,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                         u_contrib_l += n;
                     }
                 }
+                return o;
             };
             auto process_pair = [&](const Pair<NPOL>& x) __attribute__((always_inline)) {
                 settle<NPOL>(x.s[0]);
@@ -460,8 +532,26 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     rc.info = bperm(w.info, x.rec);
                 }
                 const int32_t ci = (int32_t)bperm((uint32_t)w.chan, x.rec) + (int32_t)x.pos;
-                process(rc, x.s[0], x.act, ci, g0, g1);
-                process(rc, x.s[1], x.two, ci + 1, g0, g1);
+                // each sample's contributions in turn, every lane's together.  AGG (launches
+                // of mostly fine channels): emit sums runs of lanes that add to one cell
+                // before they reach LDS; otherwise each lane adds its own.
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const Contrib c = prepare(rc, x.s[k], k == 0 ? x.act : x.two, ci + k, g0, g1);
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) {
+                        const Acc f = (Acc)(qq == 0 ? c.f0 : c.f1);
+                        const int key = (qq == 0 ? c.add0 : c.add1) ? c.cell + c.j0 + qq : -1;
+                        if constexpr (AGG) {
+                            emit<Acc>(s_re, s_im, s_w, s_n, lane, key, f * (Acc)c.pr, f * (Acc)c.pi, f * (Acc)c.q, c.n);
+                        } else if (key >= 0) {
+                            atomicAdd(&s_re[key], f * (Acc)c.pr);
+                            atomicAdd(&s_im[key], f * (Acc)c.pi);
+                            atomicAdd(&s_w[key], f * (Acc)c.q);
+                            atomicAdd(&s_n[key], c.n);
+                        }
+                    }
+                }
             };
 
             // ---- chunks, the next one's loads in flight while one is processed.  A chunk is
@@ -504,6 +594,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 load_window(s >= wend ? wb + nwin : wb + cur);
                 cur = 0;
             }
+        }
         }
 
         // a cell count can wrap only if the unit's contributions reach 2^32
@@ -650,16 +741,20 @@ bool accum_packed_shape_supported(int tu, int tv, int jc, int waves, int acc32) 
 
 hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
                                const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
-                               int npol, int acc32, hipStream_t stream) {
+                               int npol, int acc32, int agg, hipStream_t stream) {
     if (!accum_packed_shape_supported(L.tu, L.tv, L.jc, waves, acc32)) return hipErrorInvalidValue;
+#define X_LAUNCH(a, b, c, P, ACC, G)                                                                             \
+    hipLaunchKernelGGL((k_accum_packed<a, b, c, P, ACC, G>), dim3(grid), dim3(waves * kWave), 0, stream, dL,   \
+                       order, counter, unit_off, recs, pre)
 #define X_ACC(a, b, c, ACC)                                                                                     \
     if (L.tu == a && L.tv == b && L.jc == c) {                                                                  \
-        if (npol == 2)                                                                                          \
-            hipLaunchKernelGGL((k_accum_packed<a, b, c, 2, ACC>), dim3(grid), dim3(waves * kWave), 0, stream,  \
-                               dL, order, counter, unit_off, recs, pre);                                        \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_accum_packed<a, b, c, 0, ACC>), dim3(grid), dim3(waves * kWave), 0, stream,  \
-                               dL, order, counter, unit_off, recs, pre);                                        \
+        if (npol == 2) {                                                                                        \
+            if (agg) X_LAUNCH(a, b, c, 2, ACC, true);                                                           \
+            else X_LAUNCH(a, b, c, 2, ACC, false);                                                              \
+        } else {                                                                                                \
+            if (agg) X_LAUNCH(a, b, c, 0, ACC, true);                                                           \
+            else X_LAUNCH(a, b, c, 0, ACC, false);                                                              \
+        }                                                                                                       \
         return hipGetLastError();                                                                               \
     }
 #define X64(a, b, c) X_ACC(a, b, c, double)
@@ -672,19 +767,26 @@ hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const 
 #undef X64
 #undef X32
 #undef X_ACC
+#undef X_LAUNCH
     return hipErrorInvalidValue;
 }
 
-int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32) {
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32, int agg) {
     if (!accum_packed_shape_supported(tu, tv, jc, waves, acc32)) return 0;
     int nb = 0;
-#define X_ACC(a, b, c, ACC)                                                                                       \
-    if (tu == a && tv == b && jc == c) {                                                                         \
-        hipError_t e = npol == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
-                                       &nb, k_accum_packed<a, b, c, 2, ACC>, waves * kWave, 0)                    \
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
-                                       &nb, k_accum_packed<a, b, c, 0, ACC>, waves * kWave, 0);                   \
-        return e == hipSuccess ? nb : 0;                                                                         \
+    hipError_t e = hipErrorInvalidValue;
+#define X_OCC(a, b, c, P, ACC, G) \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_packed<a, b, c, P, ACC, G>, waves * kWave, 0)
+#define X_ACC(a, b, c, ACC)                                           \
+    if (tu == a && tv == b && jc == c) {                              \
+        if (npol == 2) {                                              \
+            if (agg) X_OCC(a, b, c, 2, ACC, true);                    \
+            else X_OCC(a, b, c, 2, ACC, false);                       \
+        } else {                                                      \
+            if (agg) X_OCC(a, b, c, 0, ACC, true);                    \
+            else X_OCC(a, b, c, 0, ACC, false);                       \
+        }                                                             \
+        return e == hipSuccess ? nb : 0;                              \
     }
 #define X64(a, b, c) X_ACC(a, b, c, double)
 #define X32(a, b, c) X_ACC(a, b, c, float)
@@ -696,6 +798,7 @@ int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, 
 #undef X64
 #undef X32
 #undef X_ACC
+#undef X_OCC
     return 0;
 }
 

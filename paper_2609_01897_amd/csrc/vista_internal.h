@@ -174,11 +174,13 @@ hipError_t launch_unit_order(const LaunchDesc* dL, const uint32_t* unit_off, con
                              void* sort_temp, hipStream_t stream);
 // The packed accumulation (atomic mode): `grid` workgroups of `waves` wavefronts pull units
 // from *counter (zeroed first) in the order of `order` (u64 unit ids, L.nunits of them).
-// acc32: per-tile sums in FP32 (the plain FP32 form) instead of FP64.
+// acc32: per-tile sums in FP32 (the plain FP32 form) instead of FP64.  agg: runs of lanes
+// adding to one cell are summed across the wavefront before they reach LDS (launches of
+// mostly fine channels, where many consecutive channels share a rest channel and a cell).
 hipError_t launch_accum_packed(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order, uint32_t* counter,
                                const uint32_t* unit_off, const uint64_t* recs, const uint64_t* pre, int grid, int waves,
-                               int npol, int acc32, hipStream_t stream);
-int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32);
+                               int npol, int acc32, int agg, hipStream_t stream);
+int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, int acc32, int agg);
 bool accum_packed_shape_supported(int tu, int tv, int jc, int waves, int acc32);
 int accum_packed_shape_list(int acc32, int* tu, int* tv, int* jc, int cap);
 size_t accum_packed_lds_bytes(int tu, int tv, int jc, int acc32);

@@ -223,9 +223,13 @@ ChannelPlan plan_target(const vista_grid_desc* g, const vista_target* t) {
             kmax[j] = std::max(kmax[j], k);
         }
     }
-    int32_t span = 0;
+    int32_t span = 0, reached = 0;
     for (int32_t j = 0; j < g->nchan; ++j)
-        if (kmax[j] >= 0) span = std::max(span, kmax[j] - kmin[j]);
+        if (kmax[j] >= 0) {
+            span = std::max(span, kmax[j] - kmin[j]);
+            ++reached;
+        }
+    p.chan_per_rest = reached > 0 ? (double)p.n_inband / (double)reached : 0.0;
     p.nphase = std::min(64, span + 1);
     if (p.nphase < 1) p.nphase = 1;
     return p;

@@ -32,6 +32,7 @@ struct ChannelPlan {
     int32_t kin_lo = 0, kin_hi = 0;  // hull of channels with nj > 0
     int32_t nphase = 1;            // channel distance with disjoint rest-channel sets
     int64_t n_inband = 0;          // channels with nj > 0
+    double chan_per_rest = 0.0;    // in-band channels per rest channel they reach
     double nm1 = 0.0;              // n - 1 for (l, m)
     Frame frame;                   // Eq. 1's rotation and the (l, m) in use
 };

@@ -499,7 +499,26 @@ struct HostLaunch {
     size_t o_chan = 0, o_f1 = 0, o_foff = 0, o_fval = 0;
     int64_t rows = 0, nunits = 0, zero_flag_bytes = 0;
     int npol_all = 2;
+    int agg = 0;                               // wave-aggregated LDS updates (fine channels)
 };
+
+// Whether a launch takes the packed kernel's wave-aggregated LDS updates: when at least
+// 30 % of its samples belong to targets whose in-band channels fall 6 or more to a rest
+// channel (lanes then hold long runs of samples adding to one cell).  VISTA_AGGREGATE=0
+// or 1 overrides the choice.
+static int choose_aggregate(const HostLaunch& h) {
+    if (const char* e = getenv("VISTA_AGGREGATE")) {
+        if (e[0] == '0') return 0;
+        if (e[0] == '1') return 1;
+    }
+    double fine = 0.0, all = 0.0;
+    for (const HostTarget* ht : h.hts) {
+        const double ns = (double)ht->t.nrow * ht->t.nchan * ht->t.npol;
+        all += ns;
+        if (ht->plan.chan_per_rest >= 6.0) fine += ns;
+    }
+    return all > 0.0 && fine >= 0.3 * all ? 1 : 0;
+}
 
 // Cells of one plane of a stack's carried state: every (tile, block) unit's full
 // tu x tv x jc block, edge units included.
@@ -635,6 +654,7 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
     h.row_base.push_back(h.rows);
     h.tile_base.push_back(tiles);
     h.unit_base.push_back(h.nunits);
+    h.agg = choose_aggregate(h);
     if (h.rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
     if (h.nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
     h.arena.resize(std::max<size_t>(cur, 256));
@@ -781,6 +801,7 @@ class Launcher {
         L.rowctx = rowctx_;
         L.zero_flags = zflags_;
         npol_ = h.npol_all;
+        agg_ = h.agg;
         // host sources stay alive until the stream has passed these copies (the count
         // below synchronises)
         VISTA_HIP(hipMemcpyAsync(d_arena_, h.arena.data(), h.arena.size(), hipMemcpyHostToDevice, s_));
@@ -817,13 +838,13 @@ class Launcher {
         int per_cu = tu_.wg_per_cu;
         if (per_cu <= 0)
             per_cu = mode_ == kModeAtomic
-                         ? accum_packed_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, npol_, acc32_)
+                         ? accum_packed_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, npol_, acc32_, agg_)
                          : accum_max_blocks_per_cu(tu_.tu, tu_.tv, tu_.jc, tu_.waves, mode_, kahan_, npol_);
         if (per_cu < 1) per_cu = 1;
         const int64_t grid = std::min<int64_t>((int64_t)per_cu * device_cus(), std::max<int64_t>(1, cap_.units));
         if (mode_ == kModeAtomic)
             check_launch(launch_accum_packed(L_, d_L_, order_, counter_, unit_off_, vals_, pre_, (int)grid, tu_.waves,
-                                             npol_, acc32_, s_),
+                                             npol_, acc32_, agg_, s_),
                          "accumulate");
         else
             check_launch(launch_accum_impl(L_, d_L_, order_, counter_, unit_off_, vals_, (int)grid, tu_.waves, npol_,
@@ -835,7 +856,7 @@ class Launcher {
     // Replay the captured sequence (capturing it first, or again after the buffers or
     // the specialisation changed).
     void replay() {
-        if (!exec_ || graph_npol_ != npol_) {
+        if (!exec_ || graph_npol_ != npol_ || graph_agg_ != agg_) {
             drop_graph();
             VISTA_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
             try {
@@ -849,6 +870,7 @@ class Launcher {
             VISTA_HIP(hipStreamEndCapture(s_, &graph_));
             VISTA_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
             graph_npol_ = npol_;
+            graph_agg_ = agg_;
             ++captures_;
         }
         VISTA_HIP(hipGraphLaunch(exec_, s_));
@@ -869,7 +891,7 @@ class Launcher {
 
     hipStream_t s_;
     Tuning tu_;
-    int mode_ = kModeAtomic, kahan_ = 0, acc32_ = 0, phase_fp32_ = 0, jsub_ = 0, npol_ = 2;
+    int mode_ = kModeAtomic, kahan_ = 0, acc32_ = 0, phase_fp32_ = 0, jsub_ = 0, npol_ = 2, agg_ = 0;
     DevMem mem_, recmem_;
     Capacity cap_;
     bool fixed_ = false, recs_ok_ = false;
@@ -891,7 +913,7 @@ class Launcher {
     uint64_t *pre_ = nullptr, *psums_ = nullptr;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
-    int graph_npol_ = -1, captures_ = 0;
+    int graph_npol_ = -1, graph_agg_ = -1, captures_ = 0;
 };
 
 // Point the launch's targets at device copies of their data: device-resident inputs as
@@ -1039,10 +1061,10 @@ static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning
     VISTA_HIP(hipEventRecord(ev.e[3], stream));
     VISTA_HIP(hipStreamSynchronize(stream));
     collect_stats(jobs, st);
-    vlog(1, "stack launch: %zu stack(s), %zu target(s), %lld rows, %lld records, %lld units, shape %dx%dx%d/%d; "
+    vlog(1, "stack launch: %zu stack(s), %zu target(s), %lld rows, %lld records, %lld units, shape %dx%dx%d/%d%s; "
             "binning %.3f ms, accumulation %.3f ms, total %.3f ms",
          jobs.size(), h.dts.size(), (long long)h.rows, (long long)nrec, (long long)h.nunits, tu.tu, tu.tv, tu.jc,
-         tu.waves, ev.ms(0, 1), ev.ms(1, 2), ev.ms(0, 3));
+         tu.waves, h.agg ? " aggregated" : "", ev.ms(0, 1), ev.ms(1, 2), ev.ms(0, 3));
     if (tim) {
         tim->bin_ms = ev.ms(0, 1);
         tim->accum_ms = ev.ms(1, 2);

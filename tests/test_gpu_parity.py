@@ -262,9 +262,16 @@ def small_case():
     return g, ds, oracle.stack(g, hs)
 
 
+@pytest.fixture(params=["direct", "aggregated"])
+def lds_updates(request, monkeypatch):
+    """Both forms of the packed kernel's LDS updates, forced on the same data."""
+    monkeypatch.setenv("VISTA_AGGREGATE", "1" if request.param == "aggregated" else "0")
+    return request.param
+
+
 @pytest.mark.parametrize("waves", [4, 16])
 @pytest.mark.parametrize("shape", PACKED_SHAPES)
-def test_every_tile_shape_matches(shape, waves, small_case):
+def test_every_tile_shape_matches(shape, waves, small_case, lds_updates):
     """The autotuner's candidates change only speed: counts identical, sums in tolerance
     (plain and compensated; the ordered kernel on the shapes it is built for), with 4
     wavefronts per workgroup and with the 16 whose per-wavefront stream split the
@@ -282,12 +289,34 @@ def test_every_tile_shape_matches(shape, waves, small_case):
 
 @pytest.mark.parametrize("waves", [4, 16])
 @pytest.mark.parametrize("shape", PACKED_SHAPES_F32)
-def test_every_fp32_tile_shape_matches(shape, waves, small_case):
+def test_every_fp32_tile_shape_matches(shape, waves, small_case, lds_updates):
     """The plain FP32 form's shapes (FP32 per-tile sums, 16 B of LDS per cell)."""
     g, ds, o = small_case
     tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
     out, st = gpu_stack(g, ds, flags=vista.F_PLAIN_FP32, tuning=tu)
     compare(o, out, st=st)
+
+
+@pytest.mark.parametrize("npol", [2, 1, 4])
+@pytest.mark.parametrize("mode", ["atomic", "kahan", "plain_fp32"])
+def test_fine_channels_match_oracle(mode, npol, lds_updates):
+    """Targets of 3000 channels over a band whose rest channels each take dozens of them
+    (and whose uv cells change slowly along the channel axis): lanes hold long runs of
+    samples adding to one cell, the case the aggregated LDS updates are for; both update
+    forms against the oracle, with a coarse target mixed in."""
+    cfg = synth.config("small", npol=npol)
+    g = synth.make_grid(cfg)
+    hs = [synth.make_target(cfg, 0, nchan=3000, n_int=6), synth.make_target(cfg, 1, nchan=2500, n_int=6,
+                                                                            descending=True),
+          synth.make_target(cfg, 2)]
+    o = oracle.stack(g, hs)
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=MODES[mode])
+    if mode == "plain_fp32":
+        from tests.gpu_util import compare_fp32_plain
+        compare_fp32_plain(o, out)
+        assert st == o["stats"]
+    else:
+        compare(o, out, st=st)
 
 
 def test_plain_fp32_rejects_compensated_flags():
