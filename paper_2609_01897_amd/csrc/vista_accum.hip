@@ -183,6 +183,42 @@ __device__ __forceinline__ void issue(const VISTA_GLOBAL DevChan* chan_all, cons
 // the runs are 4 lanes long or more on average, each run is first summed across its lanes
 // (a segmented inclusive scan, the run's last lane ends with its total) and only that lane
 // adds to LDS; otherwise every lane adds its own values.  Sums are in Acc either way.
+//
+// The scan moves values between lanes with DPP (a VALU operand modifier), not through LDS:
+// dppu/dppd/dppf give each lane the value of the lane that DPP control CTRL selects, in the
+// rows of 16 lanes that ROWS enables, and 0 where there is no such lane (or the row is off).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dppu(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dppd(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t r = ((uint64_t)dppu<CTRL, ROWS>((uint32_t)(b >> 32)) << 32) | dppu<CTRL, ROWS>((uint32_t)b);
+    return __builtin_bit_cast(double, r);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dppf(float v) {
+    return __builtin_bit_cast(float, dppu<CTRL, ROWS>(__builtin_bit_cast(uint32_t, v)));
+}
+// One scan step: the source lane's partial sums, added where `take` (the source is in the run).
+template <int CTRL, int ROWS, class Acc>
+__device__ __forceinline__ void scan_dpp(Acc& re, Acc& im, Acc& w, uint32_t& n, bool take) {
+    Acc r2, i2, w2;
+    if constexpr (sizeof(Acc) == 8) {
+        r2 = dppd<CTRL, ROWS>(re); i2 = dppd<CTRL, ROWS>(im); w2 = dppd<CTRL, ROWS>(w);
+    } else {
+        r2 = dppf<CTRL, ROWS>(re); i2 = dppf<CTRL, ROWS>(im); w2 = dppf<CTRL, ROWS>(w);
+    }
+    const uint32_t n2 = dppu<CTRL, ROWS>(n);
+    if (take) {
+        re += r2;
+        im += i2;
+        w += w2;
+        n += n2;
+    }
+}
+
 template <class Acc>
 __device__ __forceinline__ void emit(Acc* s_re, Acc* s_im, Acc* s_w, uint32_t* s_n, int lane, int key, Acc re,
                                      Acc im, Acc w, uint32_t n) {
@@ -193,22 +229,22 @@ __device__ __forceinline__ void emit(Acc* s_re, Acc* s_im, Acc* s_w, uint32_t* s
     const uint64_t heads = __ballot(head);
     if (__popcll(heads) * 4 <= __popcll(act)) {
         // the lane's run starts at the last head at or below it (an inactive lane ends a run,
-        // the next active lane heads one); the lanes d below it are in its run while
-        // d <= span
+        // the next active lane heads one); span = lanes of its run below it
         const uint64_t upto = heads & ((2ull << lane) - 1ull);      // lane 63: every bit
         const int start = upto ? 63 - (int)__clzll(upto) : lane;
         const int span = key >= 0 ? lane - start : -1;
-#pragma unroll 1
-        for (int d = 1; d < kWave; d <<= 1) {
-            const Acc r2 = __shfl_up(re, d, kWave), i2 = __shfl_up(im, d, kWave), w2 = __shfl_up(w, d, kWave);
-            const uint32_t n2 = __shfl_up(n, d, kWave);
-            if (d <= span) {
-                re += r2;
-                im += i2;
-                w += w2;
-                n += n2;
-            }
-        }
+        const int c16 = lane & 15;
+        // segmented inclusive scan: within each row of 16 lanes, shifts of 1, 2, 4 and 8 lanes
+        // (row_shr; a source before the row start reads 0), so that a lane holds its run's sum
+        // from max(run start, row start); then across rows, lane 15 to row 1 and lane 47 to
+        // row 3 (row_bcast:15), where the lane's run began before its row; then lane 31 (now
+        // complete) to rows 2 and 3 (row_bcast:31), where the run began at lane 31 or before
+        scan_dpp<0x111, 0xf>(re, im, w, n, span >= 1);
+        scan_dpp<0x112, 0xf>(re, im, w, n, span >= 2);
+        scan_dpp<0x114, 0xf>(re, im, w, n, span >= 4);
+        scan_dpp<0x118, 0xf>(re, im, w, n, span >= 8);
+        scan_dpp<0x142, 0xa>(re, im, w, n, span >= c16 + 1);
+        scan_dpp<0x143, 0xc>(re, im, w, n, span >= lane - 31);
         // the run's last lane holds its total
         const uint64_t ends = heads | ~act;
         if (key >= 0 && (lane == kWave - 1 || ((ends >> (lane + 1)) & 1ull))) {
@@ -532,23 +568,48 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     rc.info = bperm(w.info, x.rec);
                 }
                 const int32_t ci = (int32_t)bperm((uint32_t)w.chan, x.rec) + (int32_t)x.pos;
-                // each sample's contributions in turn, every lane's together.  AGG (launches
-                // of mostly fine channels): emit sums runs of lanes that add to one cell
-                // before they reach LDS; otherwise each lane adds its own.
+                if constexpr (AGG) {
+                    // fine channels: the pair's samples mostly add to the same cell of rest
+                    // channel j0 -- one set of values for both there (the FP64 products are
+                    // exact, their sum rounds once), each on its own otherwise
+                    const Contrib a = prepare(rc, x.s[0], x.act, ci, g0, g1);
+                    const Contrib b = prepare(rc, x.s[1], x.two, ci + 1, g0, g1);
+                    const bool comb = a.add0 && b.add0 && a.cell + a.j0 == b.cell + b.j0;
+                    const Acc fa = (Acc)a.f0, fb = (Acc)b.f0;
+                    Acc re = fa * (Acc)a.pr, im = fa * (Acc)a.pi, wq = fa * (Acc)a.q;
+                    uint32_t n = a.n;
+                    if (comb) {
+                        re += fb * (Acc)b.pr;
+                        im += fb * (Acc)b.pi;
+                        wq += fb * (Acc)b.q;
+                        n += b.n;
+                    }
+                    emit<Acc>(s_re, s_im, s_w, s_n, lane, a.add0 ? a.cell + a.j0 : -1, re, im, wq, n);
+                    // the rest is rare on fine channels (a run ends between the pair's samples,
+                    // or a channel reaches a second rest channel): added directly
+                    auto direct = [&](int key, Acc f, const Contrib& c) __attribute__((always_inline)) {
+                        atomicAdd(&s_re[key], f * (Acc)c.pr);
+                        atomicAdd(&s_im[key], f * (Acc)c.pi);
+                        atomicAdd(&s_w[key], f * (Acc)c.q);
+                        atomicAdd(&s_n[key], c.n);
+                    };
+                    if (b.add0 && !comb) direct(b.cell + b.j0, fb, b);
+                    if (a.add1) direct(a.cell + a.j0 + 1, (Acc)a.f1, a);
+                    if (b.add1) direct(b.cell + b.j0 + 1, (Acc)b.f1, b);
+                } else {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const Contrib c = prepare(rc, x.s[k], k == 0 ? x.act : x.two, ci + k, g0, g1);
+                    for (int k = 0; k < 2; ++k) {
+                        const Contrib c = prepare(rc, x.s[k], k == 0 ? x.act : x.two, ci + k, g0, g1);
 #pragma unroll
-                    for (int qq = 0; qq < 2; ++qq) {
-                        const Acc f = (Acc)(qq == 0 ? c.f0 : c.f1);
-                        const int key = (qq == 0 ? c.add0 : c.add1) ? c.cell + c.j0 + qq : -1;
-                        if constexpr (AGG) {
-                            emit<Acc>(s_re, s_im, s_w, s_n, lane, key, f * (Acc)c.pr, f * (Acc)c.pi, f * (Acc)c.q, c.n);
-                        } else if (key >= 0) {
-                            atomicAdd(&s_re[key], f * (Acc)c.pr);
-                            atomicAdd(&s_im[key], f * (Acc)c.pi);
-                            atomicAdd(&s_w[key], f * (Acc)c.q);
-                            atomicAdd(&s_n[key], c.n);
+                        for (int qq = 0; qq < 2; ++qq) {
+                            const int key = (qq == 0 ? c.add0 : c.add1) ? c.cell + c.j0 + qq : -1;
+                            if (key >= 0) {
+                                const Acc f = (Acc)(qq == 0 ? c.f0 : c.f1);
+                                atomicAdd(&s_re[key], f * (Acc)c.pr);
+                                atomicAdd(&s_im[key], f * (Acc)c.pi);
+                                atomicAdd(&s_w[key], f * (Acc)c.q);
+                                atomicAdd(&s_n[key], c.n);
+                            }
                         }
                     }
                 }

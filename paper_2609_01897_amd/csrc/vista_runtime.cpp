@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdarg>
 #include <condition_variable>
 #include <deque>
@@ -1851,6 +1852,8 @@ int vista_batch_run(vista_batch* b) {
     if (!b) return fail(VISTA_E_ARG, "batch is NULL");
     if (b->state != 0) return fail(VISTA_E_STATE, b->state == 1 ? "batch already ran" : "batch is poisoned");
     return guarded(&b->state, [&]() -> int {
+        using clk = std::chrono::steady_clock;
+        const clk::time_point h0 = clk::now();
         // the batch runs on streams of its own (a capture needs a stream other than the
         // legacy default one), ordered after the caller's stream and before it again
         struct StreamGuard {
@@ -1952,6 +1955,7 @@ int vista_batch_run(vista_batch* b) {
             stage[0] = b->keep->alloc_n<unsigned char>(maxw);
             if (nw > 1) stage[1] = b->keep->alloc_n<unsigned char>(maxw);
         }
+        const clk::time_point h1 = clk::now();
         // ---- the batch's streams start after the caller's stream (and these allocations)
         hipEvent_t e_in = g.make(hipEventDisableTiming);
         VISTA_HIP(hipEventRecord(e_in, us));
@@ -2000,6 +2004,7 @@ int vista_batch_run(vista_batch* b) {
             c0[w] = g.make(hipEventDefault); c1[w] = g.make(hipEventDefault);
         }
         hipEvent_t e_start = g.make(hipEventDefault), e_end = g.make(hipEventDefault);
+        const clk::time_point h2 = clk::now();
         VISTA_HIP(hipEventRecord(e_start, st));
         // device pointers of wave w's targets; streamed ones are copied into its buffer
         auto stage_wave = [&](size_t w) {
@@ -2086,9 +2091,14 @@ int vista_batch_run(vista_batch* b) {
         T.n_units = cap.units;
         T.n_accum_launches = (int32_t)nw;
         T.n_waves = (int32_t)nw;
+        auto host_ms = [](clk::time_point a, clk::time_point z) {
+            return std::chrono::duration<double, std::milli>(z - a).count();
+        };
         vlog(1, "batch run: %zu stack(s), %zu wave(s), %lld records; binning %.3f ms, accumulation %.3f ms, "
-                "input copies %.3f ms, total %.3f ms",
-             ns, nw, (long long)nrec_total, T.bin_ms, T.accum_ms, T.h2d_ms, T.total_ms);
+                "input copies %.3f ms, total %.3f ms; host set-up before the first launch %.1f ms "
+                "(allocation %.1f ms, launch build %.1f ms)",
+             ns, nw, (long long)nrec_total, T.bin_ms, T.accum_ms, T.h2d_ms, T.total_ms, host_ms(h0, h2),
+             host_ms(h0, h1), host_ms(h1, h2));
         b->state = 1;
         return VISTA_OK;
     });
