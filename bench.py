@@ -248,24 +248,28 @@ def copy_probe(nbytes, steps):
 
 
 def hbm_copy_rate(nbytes=4 << 30, reps=5):
-    """Measured copy bandwidth of the device (the library's plain 16-byte-vector copy kernel,
-    read + written bytes over hipEvent time), reported beside the specification peak."""
+    """Measured copy bandwidth of the device, read + written bytes over hipEvent time: the
+    library's plain 16-byte-vector copy kernel, and the runtime's own device-to-device copy
+    (hipMemcpyAsync, through torch's copy_) as a check that the first is the device's rate
+    and not the kernel's.  Returns (kernel GB/s, runtime copy GB/s)."""
     import torch
     from paper_2609_01897_amd import vista
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    vista.debug_copy(dst, src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        vista.debug_copy(dst, src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    rates = []
+    for copy in (lambda: vista.debug_copy(dst, src), lambda: dst.copy_(src)):
+        copy()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            copy()
+        e1.record()
+        torch.cuda.synchronize()
+        rates.append(2 * nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9)
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms / 1e3) / 1e9
+    return rates[0], rates[1]
 
 
 def timed_steps(step, steps):
@@ -726,8 +730,9 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe << 20, args.steps)
         return
-    copy_gbps = hbm_copy_rate()
-    log("measured copy bandwidth %.0f GB/s (specification peak %.0f GB/s)" % (copy_gbps, PEAK_HBM_GBS))
+    copy_gbps, memcpy_gbps = hbm_copy_rate()
+    log("measured copy bandwidth %.0f GB/s (the runtime's device-to-device copy: %.0f GB/s; specification "
+        "peak %.0f GB/s)" % (copy_gbps, memcpy_gbps, PEAK_HBM_GBS))
     cfg = synth.config(args.config)
     ntg = args.targets or cfg.n_targets
     grid = synth.make_grid(cfg)
@@ -812,6 +817,7 @@ def main():
         },
         "roofline": rl,
         "hbm_copy_GBps": copy_gbps,
+        "hbm_copy_GBps_runtime_memcpy": memcpy_gbps,
     }
     ref = None
     if not args.no_cpu:

@@ -240,8 +240,9 @@ int vista_release_workspace(void);
  * processed per launch, while the host reads the next ones) ---------------------------
  *
  * n_stacks independent stacks (each with its own grid g[i]; every stack of a batch has
- * the same KAHAN, DETERMINISTIC, PHASE_FP32 and PLAIN_FP32 flags) run in one persistent
- * launch sequence per wave, captured once as a hipGraph and replayed.  Targets are recorded
+ * the same KAHAN, DETERMINISTIC, PHASE_FP32 and PLAIN_FP32 flags) run in one launch
+ * sequence per wave: its binning part captured once as a hipGraph and replayed, then one
+ * persistent accumulation launch over every stack's units.  Targets are recorded
  * by vista_batch_add_target (as vista_stack_add_target, into stack `stack`);
  * vista_batch_run stacks them all.  Targets in host memory are streamed in waves of at most
  * the stream budget through two device staging buffers on a copy stream, double-buffered
@@ -273,7 +274,8 @@ int vista_batch_run(vista_batch* b);
 /* Copy one stack's results into o (may be NULL when its outputs were registered) and
  * return its classification in *st (may be NULL).  Errors: ARG, STATE, HIP, RANGE. */
 int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, vista_stats* st);
-/* Timings of the run (bin_ms and accum_ms summed over waves, h2d_ms the streamed copies).
+/* Timings of the run, summed over waves: bin_ms the binning (count pass and the replayed
+ * graph), accum_ms the accumulation kernel alone, h2d_ms the streamed copies.
  * Errors: ARG. */
 int vista_batch_timings(const vista_batch* b, vista_timings* t);
 /* Release the batch and its device results (waiting for the device).  Always succeeds for

@@ -7,10 +7,11 @@
 // For power-of-two sizes the centring factors split off: multiply the input by
 // (-1)^(iu + iv), take the unnormalised inverse FFT, multiply the output by (-1)^(p + q)
 // and by a constant (-1 per axis of length 2, else 1).  The 2-D transform is done as row
-// transforms then column transforms, each a Stockham (self-sorting) FFT in LDS;
-// the column pass stages a tile of adjacent columns so that its loads and stores are
-// contiguous runs.  Nothing here is a matrix product: the work is a few passes over the
-// grid in HBM.
+// transforms then column transforms.  Transforms of 64 to 1024 points are held in registers
+// (split into two shorter transforms with a twiddle, one exchange through LDS); other
+// lengths use a Stockham (self-sorting) FFT in LDS.  The column passes work on tiles of
+// adjacent columns so that their loads and stores are contiguous runs.  Nothing here is a
+// matrix product: the work is a few passes over the grid in HBM.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -211,6 +212,179 @@ __global__ void __launch_bounds__(kColThreads) k_image_cols(const float2* __rest
     }
 }
 
+// e^{+2 pi i j / 64} for j < 32, rounded to FP32: the twiddles of every in-register
+// transform below (lengths up to 64 take every 64/M-th entry).
+__device__ constexpr float kCos64[32] = {
+    1.000000000e+00f,  9.951847196e-01f,  9.807852507e-01f,  9.569403529e-01f,  9.238795042e-01f,
+    8.819212914e-01f,  8.314695954e-01f,  7.730104327e-01f,  7.071067691e-01f,  6.343932748e-01f,
+    5.555702448e-01f,  4.713967443e-01f,  3.826834261e-01f,  2.902846634e-01f,  1.950903237e-01f,
+    9.801714122e-02f,  0.0f,              -9.801714122e-02f, -1.950903237e-01f, -2.902846634e-01f,
+    -3.826834261e-01f, -4.713967443e-01f, -5.555702448e-01f, -6.343932748e-01f, -7.071067691e-01f,
+    -7.730104327e-01f, -8.314695954e-01f, -8.819212914e-01f, -9.238795042e-01f, -9.569403529e-01f,
+    -9.807852507e-01f, -9.951847196e-01f};
+__device__ constexpr float kSin64[32] = {
+    0.000000000e+00f, 9.801714122e-02f, 1.950903237e-01f, 2.902846634e-01f, 3.826834261e-01f,
+    4.713967443e-01f, 5.555702448e-01f, 6.343932748e-01f, 7.071067691e-01f, 7.730104327e-01f,
+    8.314695954e-01f, 8.819212914e-01f, 9.238795042e-01f, 9.569403529e-01f, 9.807852507e-01f,
+    9.951847196e-01f, 1.000000000e+00f, 9.951847196e-01f, 9.807852507e-01f, 9.569403529e-01f,
+    9.238795042e-01f, 8.819212914e-01f, 8.314695954e-01f, 7.730104327e-01f, 7.071067691e-01f,
+    6.343932748e-01f, 5.555702448e-01f, 4.713967443e-01f, 3.826834261e-01f, 2.902846634e-01f,
+    1.950903237e-01f, 9.801714122e-02f};
+
+// a e^{+2 pi i j / 64}; j is a constant once the calling loops are unrolled, so the trivial
+// factors (1 and i) cost nothing.
+__device__ __forceinline__ float2 rot64(float2 a, int j) {
+    if (j == 0) return a;
+    if (j == 16) return make_float2(-a.y, a.x);
+    return cmul(a, make_float2(kCos64[j], kSin64[j]));
+}
+
+template <int LOG>
+__device__ constexpr int bitrev(int k) {
+    int r = 0;
+    for (int b = 0; b < LOG; ++b) r |= ((k >> b) & 1) << (LOG - 1 - b);
+    return r;
+}
+
+// In-register inverse DFT of length M = 2^LOGM <= 64, Y[k] = sum_n v[n] e^{+2 pi i n k / M},
+// radix-2 decimation in frequency: a stage of span h maps (a, b) = (v[i], v[i + h]) within
+// each block of 2h to (a + b, (a - b) e^{2 pi i (i mod h) / (2h)}).  The input is in natural
+// order and Y[k] ends in v[bitrev(k)].  Every index is a constant after unrolling, so v
+// stays in registers.
+template <int LOGM>
+__device__ __forceinline__ void dft_regs(float2* v) {
+    constexpr int M = 1 << LOGM;
+#pragma unroll
+    for (int h = M / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int b = 0; b < M; b += 2 * h) {
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const float2 a = v[b + i], c = v[b + i + h];
+                v[b + i] = cadd(a, c);
+                v[b + i + h] = rot64(csub(a, c), i * (32 / h));
+            }
+        }
+    }
+}
+
+// Column pass held in registers, for nv = G R (G <= R, R <= 32): tile t is C adjacent
+// columns of one channel, as in k_image_cols, and thread (c, g) = (tid mod C, tid / C)
+// works on column c.  With input row n = g + G k and output row q = k' + R g',
+//   X[q] = sum_g e^{2 pi i g g' / G} [ e^{2 pi i g k' / nv} sum_k x[g + G k] e^{2 pi i k k' / R} ]:
+//   (1) thread (c, g) loads rows g + G k (k < R), takes their R-point transform in
+//       registers and multiplies output k' by e^{2 pi i g k' / nv};
+//   (2) the products cross the block once through LDS (cell (k' G + g) C + c), and thread
+//       (c, g) takes, for each k' = g + G s (s < R / G), the G-point transform over the
+//       block's g, which is output row k' + R g'.
+// One LDS write and one read per element, two barriers per tile; loads are C-column runs of
+// rows, stores C-float runs.  Persistent, with as many blocks as fit at once; the loads of
+// a tile are all issued before its first use.
+template <int LOGG, int LOGR, int LOGC>
+__global__ void __launch_bounds__(1 << (LOGC + LOGG)) k_image_cols_reg(const float2* __restrict__ tmp,
+                                                                        const double* __restrict__ wsum,
+                                                                        float* __restrict__ out, int lognu,
+                                                                        int ntiles, float sign) {
+    constexpr int G = 1 << LOGG, R = 1 << LOGR, C = 1 << LOGC, NV = G * R, S = R / G;
+    static_assert(G <= R && R <= 32, "tile split");
+    __shared__ float2 lds[NV * C];
+    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> LOGC;
+    const int nu = 1 << lognu, logtpc = lognu - LOGC;
+    const size_t plane = (size_t)nu * NV;
+    float2 v[R];
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const VISTA_GLOBAL float2* src = gptr(tmp) + (size_t)(tile >> logtpc) * plane +
+                                         ((size_t)(tile & ((1 << logtpc) - 1)) << LOGC) + c;
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = src[(size_t)(g + G * k) * nu];
+        dft_regs<LOGR>(v);
+#pragma unroll
+        for (int kp = 0; kp < R; ++kp) {
+            float t = (float)((g * kp) & (NV - 1)) * (1.f / (float)NV);    // exact
+            if (t > 0.5f) t -= 1.f;
+            float sn, cs;
+            sincos_turns(t, &sn, &cs);
+            lds[(kp * G + g) * C + c] = cmul(v[bitrev<LOGR>(kp)], make_float2(cs, sn));
+        }
+        lds_barrier();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) v[s * G + gg] = lds[((g + G * s) * G + gg) * C + c];
+        }
+        lds_barrier();
+        const int j = tile >> logtpc, p = ((tile & ((1 << logtpc) - 1)) << LOGC) + c;
+        const double wt = wsum[j];
+        const float inv = wt > 0.0 ? (float)(1.0 / wt) : 0.f;
+        VISTA_GLOBAL float* dst = (VISTA_GLOBAL float*)out + (size_t)j * plane + p;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            dft_regs<LOGG>(v + s * G);
+#pragma unroll
+            for (int gp = 0; gp < G; ++gp) {
+                const int q = g + G * s + R * gp;
+                const float sg = ((p + q) & 1) ? -sign : sign;                // centring (output side)
+                dst[(size_t)q * nu] = sg * v[s * G + bitrev<LOGG>(gp)].x * inv;
+            }
+        }
+    }
+}
+
+// Row pass held in registers, for nu = G R (G <= R, R <= 32): block (row tile, channel)
+// transforms RT consecutive rows, thread (g, r) = (tid mod G, tid / G) working on row r of
+// the tile, with the same split as the column pass along the row: input element n = g + G k
+// (loads of G consecutive elements per row), output element q = k' + R g' (stores of G
+// consecutive elements).  Row r's products sit at r (G (R + 1)) + g (R + 1) + k' in LDS (one
+// padding element per g keeps the writes of consecutive g on distinct banks).  The input
+// is complex (S) or real (the weights, for the beam), and takes the input-side centring.
+template <int LOGG, int LOGR, int LOGRT, bool REAL>
+__global__ void __launch_bounds__(1 << (LOGG + LOGRT)) k_image_rows_reg(const void* __restrict__ src,
+                                                                         float2* __restrict__ tmp, int lognv) {
+    constexpr int G = 1 << LOGG, R = 1 << LOGR, RT = 1 << LOGRT, NU = G * R, S = R / G, RP = R + 1;
+    static_assert(G <= R && R <= 32 && G % 2 == 0, "tile split");
+    __shared__ float2 lds[RT * G * RP];
+    const int g = threadIdx.x & (G - 1), r = threadIdx.x >> LOGG;
+    const int j = blockIdx.y, iv = blockIdx.x * RT + r;
+    const size_t row = ((size_t)j << lognv) + iv;
+    float2 v[R];
+    const float sg = ((g + iv) & 1) ? -1.f : 1.f;          // (-1)^(iu + iv), iu = g + G k, G even
+    if (REAL) {
+        const VISTA_GLOBAL float* x = gptr((const float*)src) + row * NU + g;
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = make_float2(sg * x[G * k], 0.f);
+    } else {
+        const VISTA_GLOBAL float2* x = gptr((const float2*)src) + row * NU + g;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float2 a = x[G * k];
+            v[k] = make_float2(sg * a.x, sg * a.y);
+        }
+    }
+    dft_regs<LOGR>(v);
+    float2* mine = lds + r * (G * RP);
+#pragma unroll
+    for (int kp = 0; kp < R; ++kp) {
+        float t = (float)((g * kp) & (NU - 1)) * (1.f / (float)NU);    // exact
+        if (t > 0.5f) t -= 1.f;
+        float sn, cs;
+        sincos_turns(t, &sn, &cs);
+        mine[g * RP + kp] = cmul(v[bitrev<LOGR>(kp)], make_float2(cs, sn));
+    }
+    lds_barrier();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) v[s * G + gg] = mine[gg * RP + g + G * s];
+    }
+    float2* dst = tmp + row * NU + g;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        dft_regs<LOGG>(v + s * G);
+#pragma unroll
+        for (int gp = 0; gp < G; ++gp) dst[G * s + R * gp] = v[s * G + bitrev<LOGG>(gp)];
+    }
+}
+
 // Blocks of a persistent launch: as many as fit on the device at once, at most `ntiles`.
 template <typename K>
 int persistent_blocks(K kernel, int threads, size_t lds, int ntiles) {
@@ -254,22 +428,66 @@ hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, 
                            wsum);
     const bool cfull = cols * nv == kColThreads * kColRegs;
     auto cols_k = cfull ? k_image_cols<true> : k_image_cols<false>;
+    // the in-register column pass, for 64 <= nv <= 1024 and at least one tile of columns:
+    // tiles of 32 columns (256-byte row runs), 16 for nv = 1024 (a tile's LDS, nv C 8
+    // bytes, stays within 128 KiB)
+    void (*reg_k)(const float2*, const double*, float*, int, int, float) = nullptr;
+    int reg_threads = 0, reg_cols = 0;
+    switch (lognv) {
+        case 6: reg_k = k_image_cols_reg<3, 3, 5>; reg_cols = 32; reg_threads = 32 << 3; break;
+        case 7: reg_k = k_image_cols_reg<3, 4, 5>; reg_cols = 32; reg_threads = 32 << 3; break;
+        case 8: reg_k = k_image_cols_reg<4, 4, 5>; reg_cols = 32; reg_threads = 32 << 4; break;
+        case 9: reg_k = k_image_cols_reg<4, 5, 5>; reg_cols = 32; reg_threads = 32 << 4; break;
+        case 10: reg_k = k_image_cols_reg<5, 5, 4>; reg_cols = 16; reg_threads = 16 << 5; break;
+        default: break;
+    }
+    if (nu < reg_cols) reg_k = nullptr;
+    // the in-register row pass, for 64 <= nu <= 1024 and at least one tile of rows
+    void (*rrow_c)(const void*, float2*, int) = nullptr;
+    void (*rrow_r)(const void*, float2*, int) = nullptr;
+    int rrow_rows = 0;
+    switch (lognu) {
+        case 6: rrow_c = k_image_rows_reg<3, 3, 5, false>; rrow_r = k_image_rows_reg<3, 3, 5, true>; rrow_rows = 32; break;
+        case 7: rrow_c = k_image_rows_reg<3, 4, 5, false>; rrow_r = k_image_rows_reg<3, 4, 5, true>; rrow_rows = 32; break;
+        case 8: rrow_c = k_image_rows_reg<4, 4, 4, false>; rrow_r = k_image_rows_reg<4, 4, 4, true>; rrow_rows = 16; break;
+        case 9: rrow_c = k_image_rows_reg<4, 5, 4, false>; rrow_r = k_image_rows_reg<4, 5, 4, true>; rrow_rows = 16; break;
+        case 10: rrow_c = k_image_rows_reg<5, 5, 3, false>; rrow_r = k_image_rows_reg<5, 5, 3, true>; rrow_rows = 8; break;
+        default: break;
+    }
+    if (nv < rrow_rows) rrow_c = rrow_r = nullptr;
+    auto rows_pass = [&](const void* src, bool real, int nc) {
+        if (rrow_c) {
+            hipLaunchKernelGGL(real ? rrow_r : rrow_c, dim3(nv / rrow_rows, nc), dim3(kRowThreads), 0, stream, src, tmp,
+                               lognv);
+        } else if (real) {
+            hipLaunchKernelGGL(k_image_rows<true>, dim3(nv / rows, nc), dim3(kRowThreads), lrow, stream, src, tmp,
+                               lognu, nv, rows);
+        } else {
+            hipLaunchKernelGGL(k_image_rows<false>, dim3(nv / rows, nc), dim3(kRowThreads), lrow, stream, src, tmp,
+                               lognu, nv, rows);
+        }
+    };
+    auto columns = [&](const double* ws, float* dst, int nc) {
+        if (reg_k) {
+            const int nct = (int)((int64_t)nc * (nu / reg_cols));
+            hipLaunchKernelGGL(reg_k, dim3(persistent_blocks(reg_k, reg_threads, 0, nct)), dim3(reg_threads), 0,
+                               stream, tmp, ws, dst, lognu, nct, sign);
+        } else {
+            const int nct = (int)((int64_t)nc * (nu / cols));
+            hipLaunchKernelGGL(cols_k, dim3(persistent_blocks(cols_k, kColThreads, lcol, nct)), dim3(kColThreads),
+                               lcol, stream, tmp, ws, dst, lognu, lognv, logcols, nct, sign);
+        }
+    };
     // channels [j0, j0 + nc): the kernels see the pass's slice of every array (planes are
     // multiples of 4 elements, so the slices keep the arrays' alignment)
     for (int64_t j0 = 0; j0 < nchan; j0 += per_pass) {
         const int nc = (int)std::min<int64_t>(per_pass, nchan - j0);
-        const int nct = (int)((int64_t)nc * (nu / cols));
-        const dim3 grow(nv / rows, nc), gcol(persistent_blocks(cols_k, kColThreads, lcol, nct));
         const size_t off = (size_t)j0 * plane;
-        hipLaunchKernelGGL(k_image_rows<false>, grow, dim3(kRowThreads), lrow, stream,
-                           (const void*)((const float2*)sum_wvis + off), tmp, lognu, nv, rows);
-        hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum + j0, image + off, lognu, lognv,
-                           logcols, nct, sign);
+        rows_pass((const void*)((const float2*)sum_wvis + off), false, nc);
+        columns(wsum + j0, image + off, nc);
         if (beam) {
-            hipLaunchKernelGGL(k_image_rows<true>, grow, dim3(kRowThreads), lrow, stream,
-                               (const void*)(sum_w + off), tmp, lognu, nv, rows);
-            hipLaunchKernelGGL(cols_k, gcol, dim3(kColThreads), lcol, stream, tmp, wsum + j0, beam + off, lognu,
-                               lognv, logcols, nct, sign);
+            rows_pass((const void*)(sum_w + off), true, nc);
+            columns(wsum + j0, beam + off, nc);
         }
     }
     return hipGetLastError();

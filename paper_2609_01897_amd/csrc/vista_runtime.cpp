@@ -826,6 +826,43 @@ class Launcher {
     // The rest of the sequence for the uploaded launch.  ev (optional, eager only) gets
     // its events 1 and 2 around the accumulation.
     void sequence(Events* ev) {
+        binning();
+        if (ev) VISTA_HIP(hipEventRecord(ev->e[1], s_));
+        accumulate();
+        if (ev) VISTA_HIP(hipEventRecord(ev->e[2], s_));
+    }
+
+    // Replay the captured binning part (capturing it first, or again after the buffers
+    // changed), then launch the accumulation itself; `mid` (optional)
+    // is recorded between the two, so that the accumulation kernel is timed on its own.
+    void replay(hipEvent_t mid) {
+        if (!exec_) {
+            drop_graph();
+            VISTA_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+            try {
+                binning();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(s_, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            VISTA_HIP(hipStreamEndCapture(s_, &graph_));
+            VISTA_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+            ++captures_;
+        }
+        VISTA_HIP(hipGraphLaunch(exec_, s_));
+        if (mid) VISTA_HIP(hipEventRecord(mid, s_));
+        accumulate();
+    }
+    int captures() const { return captures_; }
+    const Capacity& capacity() const { return cap_; }
+
+  private:
+    // After the count pass: emit the records, sort them by unit, unit offsets, record
+    // prefix sums, the units' work order, the work counter cleared.  Every size it needs is
+    // read from device memory, and it records no memset, so that a graph can hold it.
+    void binning() {
         check_launch(launch_track(cap_.rows, d_L_, nullptr, off_, keys_, vals_, 1, s_), "track emit");
         int bits = 1;
         while (bits < 32 && (int64_t(1) << bits) < cap_.units) ++bits;
@@ -835,7 +872,10 @@ class Launcher {
         check_launch(launch_unit_order(d_L_, unit_off_, pre_, nunits_dev(), cap_.units, okeys_, order_, otmp_, s_),
                      "unit order");
         check_launch(launch_fill_u32(counter_, 0u, 1, s_), "fill");
-        if (ev) VISTA_HIP(hipEventRecord(ev->e[1], s_));
+    }
+
+    // The accumulation kernel over the work list, one persistent grid.
+    void accumulate() {
         int per_cu = tu_.wg_per_cu;
         if (per_cu <= 0)
             per_cu = mode_ == kModeAtomic
@@ -851,35 +891,7 @@ class Launcher {
             check_launch(launch_accum_impl(L_, d_L_, order_, counter_, unit_off_, vals_, (int)grid, tu_.waves, npol_,
                                            s_),
                          "accumulate");
-        if (ev) VISTA_HIP(hipEventRecord(ev->e[2], s_));
     }
-
-    // Replay the captured sequence (capturing it first, or again after the buffers or
-    // the specialisation changed).
-    void replay() {
-        if (!exec_ || graph_npol_ != npol_ || graph_agg_ != agg_) {
-            drop_graph();
-            VISTA_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
-            try {
-                sequence(nullptr);
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(s_, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            VISTA_HIP(hipStreamEndCapture(s_, &graph_));
-            VISTA_HIP(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
-            graph_npol_ = npol_;
-            graph_agg_ = agg_;
-            ++captures_;
-        }
-        VISTA_HIP(hipGraphLaunch(exec_, s_));
-    }
-    int captures() const { return captures_; }
-    const Capacity& capacity() const { return cap_; }
-
-  private:
     const int64_t* nrows_dev() const { return (const int64_t*)((const char*)d_L_ + offsetof(LaunchDesc, nrows)); }
     const int64_t* nunits_dev() const { return (const int64_t*)((const char*)d_L_ + offsetof(LaunchDesc, nunits)); }
     const int64_t* nrec_dev() const { return (const int64_t*)(sums_ + (scan_temp_elems(cap_.rows) - 1)); }
@@ -914,7 +926,7 @@ class Launcher {
     uint64_t *pre_ = nullptr, *psums_ = nullptr;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t exec_ = nullptr;
-    int graph_npol_ = -1, graph_agg_ = -1, captures_ = 0;
+    int captures_ = 0;
 };
 
 // Point the launch's targets at device copies of their data: device-resident inputs as
@@ -2051,8 +2063,7 @@ int vista_batch_run(vista_batch* b) {
             Capacity c = ln.capacity();
             c.recs = nrec;
             ln.reserve(c);
-            VISTA_HIP(hipEventRecord(t1[w], st));
-            ln.replay();
+            ln.replay(t1[w]);
             VISTA_HIP(hipEventRecord(t2[w], st));
             VISTA_HIP(hipEventRecord(done[w], st));
         }

@@ -5,10 +5,11 @@ bound of an FFT of that length on that input, spread evenly, with room for the h
 twiddles -- plus an absolute 1e-30 (noiseless line wings reach FP32's denormal range, which
 the device flushes to zero); the beam within 1e-5 (it is normalised to 1).  A single cell
 dropped from a 512 x 512 channel moves its pixels by about ||S_j||_2 / (512 W_j), over ten
-times the bound; grids of every shape class the FFT handles (axes of 2,
-rectangular, up to 256 per side, and sampled pixels of axes up to 4096), 65535 channels, a grid stacked by the
-library, a weight array that is not 16-byte aligned, and the bench's full-size
-grid (512 x 512 x 960) on sampled pixels.
+times the bound; grids of every shape class the FFT handles (axes of 2, rectangular,
+each transform length of 64 to 1024 points both in registers and in LDS, lengths of 1024
+on sampled pixels, and sampled pixels of axes up to 4096), 65535 channels, a grid stacked
+by the library, a weight array that is not 16-byte aligned, and the bench's full-size grid
+(512 x 512 x 960) on sampled pixels.
 """
 import numpy as np
 import pytest
@@ -61,7 +62,11 @@ def test_channel_count_at_its_limit():
     _check(S.astype(np.complex128), W.astype(np.float64), img.cpu().numpy(), beam.cpu().numpy())
 
 
-@pytest.mark.parametrize("shape", [(2, 2), (2, 8), (16, 4), (32, 32), (64, 128), (256, 256)])
+# (nv, nu): transforms of 64 to 1024 points are held in registers when a tile fits (columns:
+# nu >= 32, or 16 at nv = 1024; rows: nv >= 8 to 32 rows by length), the rest use the LDS
+# Stockham passes; these shapes take each length both ways
+@pytest.mark.parametrize("shape", [(2, 2), (2, 8), (16, 4), (32, 32), (16, 64), (64, 8), (64, 128), (128, 16),
+                                   (128, 32), (256, 256), (512, 16), (512, 32)])
 def test_random_grids_match_oracle(shape):
     nv, nu = shape
     rng = np.random.default_rng(nv * 1000 + nu)
@@ -131,7 +136,8 @@ def _sampled(S, W, img, beam, rng, npix):
             assert np.max(np.abs(beam[j][q, p] - rb)) <= TOL
 
 
-@pytest.mark.parametrize("shape,nchan", [((4, 4096), 3), ((4096, 2), 3), ((2048, 8), 2), ((4096, 4096), 1)])
+@pytest.mark.parametrize("shape,nchan", [((4, 4096), 3), ((4096, 2), 3), ((2048, 8), 2), ((1024, 64), 3),
+                                         ((64, 1024), 3), ((1024, 1024), 2), ((4096, 4096), 1)])
 def test_longest_axes_sampled_pixels(shape, nchan):
     """Axes up to the 4096 limit, where one row or one column fills a whole tile."""
     nv, nu = shape
