@@ -26,7 +26,9 @@
  *
  * Environment
  *   VISTA_LOG=0..3           stderr diagnostics: 1 a line per launch and batch run (records,
- *                            units, device times), 2 also autotune candidates and wave plans.
+ *                            units, device times, host set-up), 2 also autotune candidates,
+ *                            wave plans and device allocations of 1 GiB or more, 3 also each
+ *                            launch's host build.
  *   VISTA_TUNE_CACHE=path    file of JSON lines keyed by a workload signature: autotune calls
  *                            take a cached shape instead of timing, and append new winners.
  *   VISTA_AGGREGATE=0|1      force the accumulation's LDS updates direct (0) or summed across
@@ -233,7 +235,8 @@ int vista_stack_destroy(vista_stack* s);
  * one thread neither allocate nor free device memory.  Every launch (stacks and batches)
  * also keeps the host buffers of its channel tables on the calling thread (about 40 B per
  * channel of the largest launch).  This frees both for the calling thread (the next launch
- * allocates them again).  It waits for the device.  Errors: HIP. */
+ * allocates them again), and the device blocks of 1 GiB or more that finished batches left
+ * for reuse on the current device.  It waits for the device.  Errors: HIP. */
 int vista_release_workspace(void);
 
 /* ---- Batched form (Sec. 3.3: N_batch datasets packed into contiguous device buffers and
@@ -278,8 +281,11 @@ int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, v
  * graph), accum_ms the accumulation kernel alone, h2d_ms the streamed copies.
  * Errors: ARG. */
 int vista_batch_timings(const vista_batch* b, vista_timings* t);
-/* Release the batch and its device results (waiting for the device).  Always succeeds for
- * a non-NULL handle.  Errors: ARG (NULL). */
+/* Release the batch and its device results (waiting for the device).  The batch's device
+ * blocks of 1 GiB or more (staging buffers, carried state) stay with the library for the
+ * next batch on the device (memory given back to the driver is cleared again when next
+ * allocated, at about 30 GB/s); vista_release_workspace frees them.  Always succeeds for a
+ * non-NULL handle.  Errors: ARG (NULL). */
 int vista_batch_destroy(vista_batch* b);
 
 /* The paper's common rest grid (Sec. 3.1): dfreq = max over targets and channels of the

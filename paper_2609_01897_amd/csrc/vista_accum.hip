@@ -261,27 +261,30 @@ __device__ __forceinline__ void emit(Acc* s_re, Acc* s_im, Acc* s_w, uint32_t* s
     }
 }
 
-// Per-wavefront classification and contribution counts (wave-uniform, from ballots), kept
-// over many units and added to the stack's statistics when the stack changes, every 64
-// units and at the end.
+// Per-wavefront classification and contribution counts, kept over many units and added to
+// the stack's statistics when the stack changes, every 64 units, after a unit of more than
+// 2^26 sample pairs, and at the end.  Each lane counts its own samples' live, flagged and
+// used polarisations (bad ones are the rest); the wave sums them only when it flushes.
 struct WaveStats {
-    uint64_t flag = 0, bad = 0, used = 0, contrib = 0;
+    uint32_t live = 0, flag = 0, used = 0;    // per lane
+    uint64_t contrib = 0;                     // wave-uniform
     int32_t stack = -1;
     uint32_t units = 0;
     __device__ void flush(const LaunchDesc& L, int lane) {
+        const uint64_t tl = wave_sum_u64(live), tf = wave_sum_u64(flag), tu = wave_sum_u64(used);
         if (lane == 0 && stack >= 0) {
             unsigned long long* st = cptr(L.stacks)[stack].stats;
-            if (flag) atomicAdd(&st[1], (unsigned long long)flag);
-            if (bad) atomicAdd(&st[2], (unsigned long long)bad);
-            if (used) atomicAdd(&st[5], (unsigned long long)used);
+            const uint64_t tb = tl - tf - tu;
+            if (tf) atomicAdd(&st[1], (unsigned long long)tf);
+            if (tb) atomicAdd(&st[2], (unsigned long long)tb);
+            if (tu) atomicAdd(&st[5], (unsigned long long)tu);
             if (contrib) atomicAdd(&st[6], (unsigned long long)contrib);
         }
-        flag = bad = used = contrib = 0;
+        live = flag = used = 0;
+        contrib = 0;
         units = 0;
     }
 };
-
-__device__ __forceinline__ uint64_t popc_ballot(bool p) { return (uint64_t)__popcll(__ballot(p)); }
 
 // Pairs of stream positions per slice of a wavefront's share of a unit (4096 samples).
 constexpr uint64_t kSlicePairs = 2048;
@@ -351,8 +354,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 
         const uint32_t rb = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit]);
         const uint32_t re = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit + 1]);
-        uint64_t u_contrib = 0;           // wave-uniform (ballots)
-        uint32_t u_contrib_l = 0;         // per lane (rest channels beyond j0 + 1)
+        uint32_t u_contrib_l = 0;         // contributions of this lane's samples
         // the unit's stream, in pairs, dealt to the wavefronts in slices of kSlicePairs: wave
         // w takes slices w, w + nw, ... of every full round, then an even share of what the
         // full rounds leave, so that at any time the wavefronts work on nearby records (rows
@@ -394,20 +396,23 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 first = lo + (uint32_t)(63 - __clzll(m));
             }
 
-            // ---- window of up to 64 records, one per lane
+            // ---- window of up to 64 records, one per lane.  Stream positions in the loops
+            // below are 32-bit offsets from sw0 (a slice and a window span far less than 2^31)
             uint32_t wb = 0, nwin = 0, cur = 0;
-            uint64_t pw = 0, wend = 0;
+            int32_t pw = 0, wend = 0;      // the window's first and end positions
+            const uint32_t se = (uint32_t)(sw1 - sw0);
             uint32_t wrel = 0;             // this lane's record start, relative to pw
             RecCtx<NPOL> w;
             auto load_window = [&](uint32_t nb) __attribute__((always_inline)) {
                 wb = nb;
                 nwin = min((uint32_t)kWave, re - nb);
-                pw = ufl64(cpre[nb]);
-                wend = ufl64(cpre[nb + nwin]);
+                const uint64_t pw64 = ufl64(cpre[nb]);
+                pw = (int32_t)(int64_t)(pw64 - sw0);
+                wend = (int32_t)(int64_t)(ufl64(cpre[nb + nwin]) - sw0);
                 const bool v = (uint32_t)lane < nwin;
                 const uint64_t rec = v ? grecs[nb + lane] : 0ull;
                 const uint64_t pg = v ? gpre[nb + lane] : 0ull;
-                wrel = v ? (uint32_t)(pg - pw) : 0xffffffffu;
+                wrel = v ? (uint32_t)(pg - pw64) : 0xffffffffu;
                 const uint32_t g = (uint32_t)(rec >> 32);
                 const uint32_t kin = (uint32_t)((rec >> 16) & 0xffffu), kout = (uint32_t)(rec & 0xffffu);
                 const int64_t d = (int64_t)kin - (int64_t)wrel;         // channel - position
@@ -440,8 +445,8 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
             // lanes of the chunk starting at s (two samples each): records and contexts.
             // live == false: an idle chunk (every lane inactive, the window cursor kept) whose
             // lanes load from the record at the cursor.
-            auto map = [&](uint64_t s, Pair<NPOL>& x, bool live) __attribute__((always_inline)) {
-                const uint32_t srel = (uint32_t)(s - pw);
+            auto map = [&](uint32_t s, Pair<NPOL>& x, bool live) __attribute__((always_inline)) {
+                const uint32_t srel = (uint32_t)((int32_t)s - pw);
                 const uint32_t pos = srel + 2u * (uint32_t)lane;
                 // (an idle chunk may find the cursor one past the window: use its last record)
                 int rec = live ? (int)cur : (int)min(cur, nwin - 1u);
@@ -460,7 +465,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 }
                 x.rec = rec;
                 x.pos = pos;
-                x.act = live && s + 2u * (uint64_t)lane < sw1;
+                x.act = live && s + 2u * (uint32_t)lane < se;
             };
 
             // What one sample adds: its LDS cell row (cell + j is the cell of rest channel j),
@@ -492,7 +497,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 float ar = 0.f, ai = 0.f, q = 0.f;
                 uint32_t n = 0;
                 const int np = NPOL == 2 ? 2 : (int)(rc.info & 0xffu);
-                bool use_p[NPOL == 2 ? 2 : 4];
+                uint32_t nflag = 0;
 #pragma unroll
                 for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p) {
                     const bool live = NPOL == 2 || p < np;
@@ -500,17 +505,18 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     const bool flagged = live && ((x.fl >> (8 * p)) & 0xffu) != 0u;
                     const bool good = NPOL == 2 ? (p == 0 ? g0 : g1)
                                                 : (live && (wgt > 0.0f) && (wgt < __builtin_inff()));
-                    ws.flag += popc_ballot(home && flagged);
-                    ws.bad += popc_ballot(home && live && !flagged && !good);
+                    nflag += flagged ? 1u : 0u;
                     const bool use = !flagged && good;
-                    use_p[p] = use;
-                    ws.used += popc_ballot(home && use);
                     const float wu = use ? wgt : 0.0f;
                     n += use ? 1u : 0u;
                     ar = fmaf(wu, x.vr[p], ar);
                     ai = fmaf(wu, x.vi[p], ai);
                     q += wu;
                 }
+                // statistics of the sample's home unit: live polarisations, flagged, used
+                ws.live += home ? (uint32_t)np : 0u;
+                ws.flag += home ? nflag : 0u;
+                ws.used += home ? n : 0u;
                 float c, sn;
                 if (phase_fp32) {
                     const float t = (float)rc.T * (float)x.a;
@@ -529,9 +535,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                 const bool live_add = in_tile && n > 0;
                 o.add0 = live_add && j0 >= jb0 && j0 < jb1;
                 o.add1 = live_add && nj > 1 && j0 + 1 >= jb0 && j0 + 1 < jb1;
-#pragma unroll
-                for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p)
-                    u_contrib += popc_ballot(o.add0 && use_p[p]) + popc_ballot(o.add1 && use_p[p]);
+                u_contrib_l += (o.add0 ? n : 0u) + (o.add1 ? n : 0u);
                 o.cell = (lv * TU + lu) * JP - jb0;
                 // more than two rest channels (rest grid finer than the channel): rare
                 if (live_add && nj > 2) {
@@ -620,16 +624,16 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
             // between runs of chunks, so no other load sits among the chunks' loads.
             // (After a reload at the record holding s, the window reaches at least 128
             // positions past s: records take whole pairs and s is even.)
-            auto fits = [&](uint64_t t) __attribute__((always_inline)) {
-                return t < sw1 && min(t + (uint64_t)kChunk, sw1) <= wend;
+            auto fits = [&](uint32_t t) __attribute__((always_inline)) {
+                return t < se && (int32_t)min(t + kChunk, se) <= wend;
             };
             load_window(first);
             cur = 0;
-            uint64_t s = sw0;
+            uint32_t s = 0;
             // the next chunks, or, at the end of a run, idle ones: the loads are issued on
             // every path, so the wait before processing a chunk is for its own loads only
-            auto next = [&](bool live, uint64_t t, Pair<NPOL>& x) __attribute__((always_inline)) {
-                map(live ? t : wend - 2u, x, live);
+            auto next = [&](bool live, uint32_t t, Pair<NPOL>& x) __attribute__((always_inline)) {
+                map(live ? t : (uint32_t)(wend - 2), x, live);
                 issue<NPOL>(chan_all, f1_all, w, x);
             };
             for (;;) {
@@ -648,19 +652,20 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     s += kChunk;
                     if (!l0) break;
                 }
-                if (s >= sw1) break;
+                if (s >= se) break;
                 // the record holding s and the 63 after it.  The cursor is the window's last
                 // record starting at or before s; when s is the window's end, that record ends
                 // at s and the one holding s is the first past the window.
-                load_window(s >= wend ? wb + nwin : wb + cur);
+                load_window((int32_t)s >= wend ? wb + nwin : wb + cur);
                 cur = 0;
             }
         }
         }
 
         // a cell count can wrap only if the unit's contributions reach 2^32
-        const unsigned long long t_contrib = u_contrib + wave_sum_u64(u_contrib_l);
+        const unsigned long long t_contrib = wave_sum_u64(u_contrib_l);
         ws.contrib += t_contrib;
+        if (npairs > (1ull << 26)) ws.units = 64;      // keep the lanes' 32-bit counts far from wrapping
         if (lane == 0 && t_contrib) atomicAdd(&s_contrib, t_contrib);
         __syncthreads();
         if (threadIdx.x == 0) {

@@ -82,7 +82,8 @@ static std::atomic<int64_t> g_dev_bytes{0};
 
 // VISTA_LOG=0..3 sets how much the library writes to stderr: 0 nothing (the default);
 // 1 one line per stack launch and batch run (records, units, device times); 2 also the
-// autotuner's candidates and the batch's wave plan; 3 also each launch's host build.
+// autotuner's candidates, the batch's wave plan and every device allocation of 1 GiB or
+// more; 3 also each launch's host build.
 static int log_level() {
     const char* s = getenv("VISTA_LOG");
     return s ? atoi(s) : 0;
@@ -111,13 +112,78 @@ static void pool_setup_once() {
     });
 }
 
+// Device blocks of 1 GiB or more that batches have released, kept for the next batch on the
+// same device: memory handed back to the driver is cleared again when it is next allocated
+// (about 30 GB/s here), which for a streamed batch's staging buffers and carried state costs
+// seconds per batch.  A block serves a request of 4/5 of its size or more.  The blocks stay
+// counted as the library's device memory until vista_release_workspace or an allocation
+// that would otherwise fail frees them.
+class BigBlocks {
+  public:
+    static constexpr size_t kMin = (size_t)1 << 30;
+    static BigBlocks& get() {
+        static BigBlocks b;
+        return b;
+    }
+    void* take(size_t n, int dev, size_t* got) {
+        std::lock_guard<std::mutex> lk(m_);
+        size_t best = blocks_.size();
+        for (size_t i = 0; i < blocks_.size(); ++i) {
+            const Block& b = blocks_[i];
+            if (b.dev == dev && b.n >= n && b.n - n <= b.n / 5 && (best == blocks_.size() || b.n < blocks_[best].n))
+                best = i;
+        }
+        if (best == blocks_.size()) return nullptr;
+        void* p = blocks_[best].p;
+        *got = blocks_[best].n;
+        blocks_.erase(blocks_.begin() + (std::ptrdiff_t)best);
+        return p;
+    }
+    void give(void* p, size_t n, int dev) {
+        std::lock_guard<std::mutex> lk(m_);
+        blocks_.push_back({p, n, dev});
+    }
+    // Free the current device's cached blocks (waiting for the device); returns their bytes.
+    int64_t release(int dev) {
+        std::lock_guard<std::mutex> lk(m_);
+        int64_t freed = 0;
+        for (size_t i = 0; i < blocks_.size();) {
+            if (blocks_[i].dev == dev) {
+                (void)hipFree(blocks_[i].p);
+                freed += (int64_t)blocks_[i].n;
+                blocks_.erase(blocks_.begin() + (std::ptrdiff_t)i);
+            } else {
+                ++i;
+            }
+        }
+        return freed;
+    }
+
+  private:
+    struct Block {
+        void* p;
+        size_t n;
+        int dev;
+    };
+    std::mutex m_;
+    std::vector<Block> blocks_;
+};
+
+static int current_device() {
+    int dev = 0;
+    return hipGetDevice(&dev) == hipSuccess ? dev : 0;
+}
+
 // Stream-ordered device buffers owned by one launch or handle.
 // Persistent buffers (a thread's cached launch workspace, which outlives any one stream)
 // are plain device allocations instead: every call that uses them synchronises its stream
 // before returning, so they are idle between calls, and freeing them waits for the device.
+// With `reuse_big`, blocks of 1 GiB or more come from and go back to BigBlocks (their
+// release waits for the stream first).
 class DevMem {
   public:
-    explicit DevMem(hipStream_t s, bool persistent = false) : s_(s), persistent_(persistent) {}
+    explicit DevMem(hipStream_t s, bool persistent = false, bool reuse_big = false)
+        : s_(s), persistent_(persistent), reuse_big_(reuse_big) {}
     DevMem(const DevMem&) = delete;
     ~DevMem() { release(); }
     void set_stream(hipStream_t s) { s_ = s; }
@@ -125,23 +191,47 @@ class DevMem {
         if (n == 0) n = 16;
         Env e = read_env();
         if (e.fail_alloc) throw NoMem{"injected allocation failure"};
-        if (e.mem_limit >= 0 && g_dev_bytes.load() + (int64_t)n > e.mem_limit)
-            throw NoMem{"device memory limit reached"};
+        if (reuse_big_ && n >= BigBlocks::kMin) {
+            size_t got = 0;
+            if (void* q = BigBlocks::get().take(n, current_device(), &got)) {
+                big_.push_back({q, got});
+                return q;
+            }
+        }
+        if (e.mem_limit >= 0 && g_dev_bytes.load() + (int64_t)n > e.mem_limit) {
+            g_dev_bytes -= BigBlocks::get().release(current_device());   // cached blocks first
+            if (g_dev_bytes.load() + (int64_t)n > e.mem_limit) throw NoMem{"device memory limit reached"};
+        }
         void* p = nullptr;
         hipError_t r;
-        if (persistent_) {
+        const bool big = n >= ((size_t)1 << 30) && log_level() >= 2;
+        const auto t0 = std::chrono::steady_clock::now();
+        size_t fr = 0, tot = 0;
+        if (big) (void)hipMemGetInfo(&fr, &tot);
+        const bool big_block = reuse_big_ && n >= BigBlocks::kMin;
+        if (persistent_ || big_block) {
             r = hipMalloc(&p, n);
+            if (r == hipErrorOutOfMemory && big_block) {          // the cached blocks make room
+                (void)hipGetLastError();
+                g_dev_bytes -= BigBlocks::get().release(current_device());
+                r = hipMalloc(&p, n);
+            }
         } else {
             pool_setup_once();
             r = hipMallocAsync(&p, n, s_);
         }
+        if (big)
+            vlog(2, "device allocation of %.2f GiB (%.2f GiB free before): %.1f ms", n / 1073741824.0,
+                 fr / 1073741824.0,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         if (r == hipErrorOutOfMemory) {
             (void)hipGetLastError();
             throw NoMem{"device allocation of " + std::to_string(n) + " bytes failed"};
         }
         if (r != hipSuccess) throw HipFail{r, persistent_ ? "hipMalloc" : "hipMallocAsync"};
         g_dev_bytes += (int64_t)n;
-        ptrs_.push_back({p, n});
+        if (big_block) big_.push_back({p, n});
+        else ptrs_.push_back({p, n});
         return p;
     }
     template <class T>
@@ -153,12 +243,18 @@ class DevMem {
             g_dev_bytes -= (int64_t)q.second;
         }
         ptrs_.clear();
+        if (!big_.empty()) {
+            (void)hipStreamSynchronize(s_);                // the stream's last use has passed
+            const int dev = current_device();
+            for (auto& q : big_) BigBlocks::get().give(q.first, q.second, dev);
+            big_.clear();
+        }
     }
 
   private:
     hipStream_t s_;
-    bool persistent_;
-    std::vector<std::pair<void*, size_t>> ptrs_;
+    bool persistent_, reuse_big_;
+    std::vector<std::pair<void*, size_t>> ptrs_, big_;
 };
 
 // Enqueue a kernel launch and check it.  An injected launch failure is raised before the
@@ -1371,6 +1467,7 @@ int vista_release_workspace(void) {
     return guarded(nullptr, [&]() -> int {
         t_workspaces.clear();
         t_host = HostScratch();
+        g_dev_bytes -= BigBlocks::get().release(current_device());
         return VISTA_OK;
     });
 }
@@ -1889,7 +1986,7 @@ int vista_batch_run(vista_batch* b) {
         VISTA_HIP(hipStreamCreateWithFlags(&g.c, hipStreamNonBlocking));
         hipStream_t us = b->stream;
         hipStream_t st = g.c;
-        b->keep = std::make_unique<DevMem>(us);
+        b->keep = std::make_unique<DevMem>(us, false, true);
         const size_t ns = b->g.size();
         const uint32_t flags = b->g[0].flags;
         const bool kahan = (flags & VISTA_F_KAHAN) != 0;

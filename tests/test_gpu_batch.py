@@ -76,6 +76,48 @@ def test_streamed_waves_match_oracle(flags):
         compare(o, out, st=st)
 
 
+@pytest.mark.parametrize("flags", [0, "kahan"])
+def test_large_carried_state_is_cleared_on_reused_memory(flags):
+    """A stack whose carried grid state holds more than 2^32 words (1024 x 1024 x 1536
+    cells: three FP32 sums each, 4.8e9 words), streamed in several waves, twice in a row.
+    The second run takes the first run's device blocks, which still hold its sums: its
+    state must be cleared in full (a fill over fewer than 2^32 work-items once left the
+    tail of such a state as it found it).  The two runs must agree."""
+    fl = vista.F_KAHAN if flags == "kahan" else 0
+    cfg = synth.config("c1")
+    grid = dict(synth.make_grid(cfg), nu=1024, nv=1024, nchan=1536)
+    assert 3 * grid["nu"] * grid["nv"] * grid["nchan"] > 1 << 32
+    ts = [_pinned(t) for t in synth.make_targets(cfg, n=3)]
+    outs = []
+    for _ in range(2):
+        g = dict(grid, flags=fl)
+        b = vista.Batch([g])
+        b.set_stream_budget(4 << 20)           # one 3 MB target per wave
+        for t in ts:
+            b.add(0, t)
+        out = vista.alloc_outputs(g)
+        b.set_output(0, out)
+        b.run()
+        assert b.timings()["n_waves"] >= 2
+        b.finalize(0)
+        b.close()
+        outs.append(out)
+    torch.cuda.synchronize()
+    a, c = outs
+    assert torch.equal(a["count"], c["count"])
+    assert int(a["count"].sum()) > 0
+    for k in ("sum_wvis", "sum_w"):
+        x, y = a[k], c[k]
+        if x.is_complex():
+            x, y = torch.view_as_real(x), torch.view_as_real(y)
+        scale = float(x.abs().max())
+        assert scale > 0
+        assert float((x - y).abs().max()) <= 1e-5 * scale, k
+    del outs, a, c
+    torch.cuda.empty_cache()
+    vista.release_workspace()
+
+
 def test_mixed_resident_and_streamed_targets():
     grids, hs = _stacks()
     mixed = [[t.to("cuda") if i % 2 == 0 else _pinned(t) for i, t in enumerate(ts)] for ts in hs]
