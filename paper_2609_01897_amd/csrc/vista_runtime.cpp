@@ -193,8 +193,9 @@ class DevMem {
         if (e.fail_alloc) throw NoMem{"injected allocation failure"};
         if (reuse_big_ && n >= BigBlocks::kMin) {
             size_t got = 0;
-            if (void* q = BigBlocks::get().take(n, current_device(), &got)) {
-                big_.push_back({q, got});
+            const int dev = current_device();
+            if (void* q = BigBlocks::get().take(n, dev, &got)) {
+                big_.push_back({q, got, dev});
                 return q;
             }
         }
@@ -230,7 +231,7 @@ class DevMem {
         }
         if (r != hipSuccess) throw HipFail{r, persistent_ ? "hipMalloc" : "hipMallocAsync"};
         g_dev_bytes += (int64_t)n;
-        if (big_block) big_.push_back({p, n});
+        if (big_block) big_.push_back({p, n, current_device()});
         else ptrs_.push_back({p, n});
         return p;
     }
@@ -245,8 +246,7 @@ class DevMem {
         ptrs_.clear();
         if (!big_.empty()) {
             (void)hipStreamSynchronize(s_);                // the stream's last use has passed
-            const int dev = current_device();
-            for (auto& q : big_) BigBlocks::get().give(q.first, q.second, dev);
+            for (auto& q : big_) BigBlocks::get().give(q.p, q.n, q.dev);
             big_.clear();
         }
     }
@@ -254,7 +254,13 @@ class DevMem {
   private:
     hipStream_t s_;
     bool persistent_, reuse_big_;
-    std::vector<std::pair<void*, size_t>> ptrs_, big_;
+    struct Big {
+        void* p;
+        size_t n;
+        int dev;                                     // the device it was allocated on
+    };
+    std::vector<std::pair<void*, size_t>> ptrs_;
+    std::vector<Big> big_;
 };
 
 // Enqueue a kernel launch and check it.  An injected launch failure is raised before the
