@@ -321,11 +321,12 @@ def stack_step(grid, targets, flags, tuning, out):
 FORMS_SLAB = (432, 528)     # 96 rest channels around the line, reached by every target
 
 
-def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps=3):
+def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps=3, autotune=True):
     """The c2 workload in the plain FP32 form (FP32 per-tile sums) and the deterministic
-    form (fixed-order compensated FP32 per-tile sums), timed on all targets; the accuracy
-    of each form, and of the compensated form the main step runs, on the cpu_baseline
-    sample against its oracle grid."""
+    form (fixed-order compensated FP32 per-tile sums), timed on all targets, each in the
+    launch shape the autotuner picks for it (as the main step's compensated form is); the
+    accuracy of each form, and of the compensated form the main step runs, on the
+    cpu_baseline sample against its oracle grid."""
     import torch
     from paper_2609_01897_amd import vista
     out = vista.alloc_outputs(grid)
@@ -335,9 +336,18 @@ def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps
     for name, flags, tuning in forms:
         rec = {}
         if name != "compensated":
+            if autotune:
+                t0 = time.perf_counter()
+                s = vista.Stack(grid, flags=flags)
+                for t in targets:
+                    s.add(t)
+                tuning = s.autotune()
+                s.close()
+                log("form %s: autotuned launch shape %s in %.1f s" % (name, tuning, time.perf_counter() - t0))
             ms, acc_ms, (st, tim) = timed_steps(stack_step(grid, targets, flags, tuning, out), steps)
             rec.update(ms_per_step=ms, accumulate_ms=acc_ms, samples_per_s=st["n_samples"] / (ms / 1e3),
-                       roofline=roofline(nbytes, acc_ms))
+                       roofline=roofline(nbytes, acc_ms),
+                       launch_shape=dict(tuning or {}, source="autotuned" if autotune else "default"))
             log("form %s: step %.2f ms, accumulate %.2f ms" % (name, ms, acc_ms))
         if ref is not None:
             s = vista.Stack(grid, flags=flags, tuning=tuning)
@@ -849,7 +859,8 @@ def main():
     del out
     torch.cuda.empty_cache()
     if not args.no_forms and flags == 0:
-        res["forms"] = forms_leg(targets, grid, nbytes, ref, targets[:args.cpu_targets], tuning)
+        res["forms"] = forms_leg(targets, grid, nbytes, ref, targets[:args.cpu_targets], tuning,
+                                 autotune=not args.no_autotune)
     ref = None
     if not args.no_rebinned:
         res["rebinned"] = rebinned_leg(targets, cfg, grid)

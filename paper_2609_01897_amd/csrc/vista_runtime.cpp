@@ -469,7 +469,7 @@ static bool shape_ok(const Tuning& t, uint32_t flags) {
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
     if (flags & VISTA_F_DETERMINISTIC) {
-        t.tu = 8; t.tv = 4; t.jc = 128; t.waves = 8;   // ordered: 16-channel slices per wave
+        t.tu = 4; t.tv = 2; t.jc = 512; t.waves = 16;  // ordered: 32-channel slices per wave
     } else if (flags & VISTA_F_PLAIN_FP32) {
         t.tu = 8; t.tv = 4; t.jc = 288; t.waves = 16;  // FP32 tiles: 1.75 times the cells
     }

@@ -308,6 +308,17 @@ def test_every_tile_shape_matches(shape, waves, small_case, lds_updates):
 
 
 @pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("shape", ORDERED_SHAPES)
+def test_every_ordered_shape_matches(shape, waves, small_case):
+    """The deterministic form in every launch shape built for it, compensated and not."""
+    g, ds, o = small_case
+    tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
+    for flags in (vista.F_DETERMINISTIC, vista.F_DETERMINISTIC | vista.F_KAHAN):
+        out, st = gpu_stack(g, ds, flags=flags, tuning=tu)
+        compare(o, out, st=st)
+
+
+@pytest.mark.parametrize("waves", [4, 16])
 @pytest.mark.parametrize("shape", PACKED_SHAPES_F32)
 def test_every_fp32_tile_shape_matches(shape, waves, small_case, lds_updates):
     """The plain FP32 form's shapes (FP32 per-tile sums, 16 B of LDS per cell)."""
