@@ -601,21 +601,33 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
                     if (a.add1) direct(a.cell + a.j0 + 1, (Acc)a.f1, a);
                     if (b.add1) direct(b.cell + b.j0 + 1, (Acc)b.f1, b);
                 } else {
-#pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        const Contrib c = prepare(rc, x.s[k], k == 0 ? x.act : x.two, ci + k, g0, g1);
-#pragma unroll
-                        for (int qq = 0; qq < 2; ++qq) {
-                            const int key = (qq == 0 ? c.add0 : c.add1) ? c.cell + c.j0 + qq : -1;
-                            if (key >= 0) {
-                                const Acc f = (Acc)(qq == 0 ? c.f0 : c.f1);
-                                atomicAdd(&s_re[key], f * (Acc)c.pr);
-                                atomicAdd(&s_im[key], f * (Acc)c.pi);
-                                atomicAdd(&s_w[key], f * (Acc)c.q);
-                                atomicAdd(&s_n[key], c.n);
-                            }
+                    // coarse channels: the pair's second channel mostly starts in the rest
+                    // channel where the first one ends (or shares the first's), so its first
+                    // contribution joins one of the first channel's in registers (the FP64
+                    // products are exact, their sum rounds once) and three sets of LDS
+                    // updates serve the pair instead of four
+                    const Contrib a = prepare(rc, x.s[0], x.act, ci, g0, g1);
+                    const Contrib b = prepare(rc, x.s[1], x.two, ci + 1, g0, g1);
+                    const int ka0 = a.add0 ? a.cell + a.j0 : -1, ka1 = a.add1 ? a.cell + a.j0 + 1 : -1;
+                    const int kb0 = b.add0 ? b.cell + b.j0 : -1, kb1 = b.add1 ? b.cell + b.j0 + 1 : -1;
+                    const Acc fa0 = (Acc)a.f0, fa1 = (Acc)a.f1, fb0 = (Acc)b.f0, fb1 = (Acc)b.f1;
+                    const bool m1 = kb0 >= 0 && kb0 == ka1;                 // b's first = a's second
+                    const bool m0 = kb0 >= 0 && !m1 && kb0 == ka0;          // b's first = a's first
+                    auto add = [&](int key, Acc re, Acc im, Acc w, uint32_t n) __attribute__((always_inline)) {
+                        if (key >= 0) {
+                            atomicAdd(&s_re[key], re);
+                            atomicAdd(&s_im[key], im);
+                            atomicAdd(&s_w[key], w);
+                            atomicAdd(&s_n[key], n);
                         }
-                    }
+                    };
+                    const Acc br = fb0 * (Acc)b.pr, bi = fb0 * (Acc)b.pi, bw = fb0 * (Acc)b.q;
+                    add(ka0, fa0 * (Acc)a.pr + (m0 ? br : Acc(0)), fa0 * (Acc)a.pi + (m0 ? bi : Acc(0)),
+                        fa0 * (Acc)a.q + (m0 ? bw : Acc(0)), a.n + (m0 ? b.n : 0u));
+                    add(ka1, fa1 * (Acc)a.pr + (m1 ? br : Acc(0)), fa1 * (Acc)a.pi + (m1 ? bi : Acc(0)),
+                        fa1 * (Acc)a.q + (m1 ? bw : Acc(0)), a.n + (m1 ? b.n : 0u));
+                    add(m0 || m1 ? -1 : kb0, br, bi, bw, b.n);
+                    add(kb1, fb1 * (Acc)b.pr, fb1 * (Acc)b.pi, fb1 * (Acc)b.q, b.n);
                 }
             };
 
