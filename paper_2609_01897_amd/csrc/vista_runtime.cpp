@@ -45,6 +45,9 @@ struct HipFail {
     std::string where;
 };
 
+// Upper bound (exclusive) on the rows, units and track records of one launch.
+constexpr int64_t kMaxItems = 0xffffff00LL;
+
 #define VISTA_HIP(call)                                                              \
     do {                                                                             \
         hipError_t _e = (call);                                                      \
@@ -758,8 +761,10 @@ static HostLaunch build_launch(const std::vector<StackJob>& jobs, const Tuning& 
     h.tile_base.push_back(tiles);
     h.unit_base.push_back(h.nunits);
     h.agg = choose_aggregate(h);
-    if (h.rows >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "more than 2^32-1 rows in one launch"};
-    if (h.nunits >= 0xffffffffLL) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
+    // One thread per row, unit or record in the element-wise passes: a dispatch's work-item
+    // count is 32 bits wide, so each count stays below 2^32 - 256 (a whole last block).
+    if (h.rows >= kMaxItems) throw HipFail{hipErrorInvalidValue, "2^32-256 rows or more in one launch"};
+    if (h.nunits >= kMaxItems) throw HipFail{hipErrorInvalidValue, "too many (tile, block) units in one launch"};
     h.arena.resize(std::max<size_t>(cur, 256));
     return h;
 }
@@ -921,7 +926,7 @@ class Launcher {
         uint64_t total = 0;
         VISTA_HIP(hipMemcpyAsync(&total, nrec_dev(), 8, hipMemcpyDeviceToHost, s_));
         VISTA_HIP(hipStreamSynchronize(s_));
-        if (total >= 0xffffffffull) throw HipFail{hipErrorInvalidValue, "too many track records in one launch"};
+        if (total >= (uint64_t)kMaxItems) throw HipFail{hipErrorInvalidValue, "too many track records in one launch"};
         return (int64_t)total;
     }
 
