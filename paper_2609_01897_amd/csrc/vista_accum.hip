@@ -1,4 +1,5 @@
-// Packed accumulation of the atomic mode (Eq. 2 rotation, Eq. 3-4 rest-frame rebinning).
+// The accumulation kernels (Eq. 2 rotation, Eq. 3-4 rest-frame rebinning): the packed
+// kernel of the atomic mode, and below it the ordered kernel of the deterministic form.
 //
 // The binning pass leaves the records of every (uv tile, rest-channel block) unit
 // contiguous; a record is a run [k_lo, k_hi) of channels of one row.  Concatenated, the
@@ -18,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "vista_device.h"
 
@@ -692,6 +694,382 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
     ws.flush(L, lane);
 }
 
+// ------------------------------------------------------------- ordered accumulation
+
+// The deterministic form: results are bit-identical from run to run.  A workgroup owns one
+// unit at a time, as above, but each wavefront owns a slice of jsub rest channels of the
+// unit's block and walks every record of the unit, keeping the channels that reach its
+// slice (its target's sub-block range): no cell has two writers.  The clipped records of
+// a window of 64 form one stream that the wavefront takes 64 positions (one channel with
+// all its polarisations per lane) at a time, whatever records they come from, so lanes do
+// not idle at record ends.  The lanes of a chunk add in phases: channels of one row that
+// are nphase or more apart never share a rest channel, so with P phases (the window's
+// largest nphase, at least two) phase p takes the lanes whose channel plus record index is
+// congruent to p modulo P, which also puts the same channel of consecutive records (rows
+// of one baseline, which often share a cell) in different phases.  Lanes of one phase from
+// different rows can still meet in a cell; they take turns: every waiting lane bids for
+// its cells with an LDS max of its lane id, the lanes that hold every cell they bid for
+// add, the others bid again.  The order of the additions to a cell thus depends on the
+// records and lane ids only.  Sums are FP32 with a Kahan compensation per addition (KAHAN)
+// or FP64, read and written plainly.
+
+// Keeps the compiler from moving LDS accesses across this point: the lanes of a wavefront
+// read what other lanes of it wrote just before (the LDS serves one wavefront's
+// instructions in order).
+__device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
+
+// Fewest addition phases per chunk of the ordered kernel.
+constexpr int32_t kOrdPhases = 2;
+
+// One lane's sample of a chunk: window lane of its record, stream position (relative to
+// the window), whether it is inside the stream.
+template <int NPOL>
+struct OrdSample {
+    int rec;
+    uint32_t pos;
+    bool act;
+    Loaded<NPOL> s;
+};
+
+template <int TU, int TV, int JC, int NPOL, bool KAHAN>
+__global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __restrict__ Lp,
+                                                           const uint64_t* __restrict__ order,
+                                                           uint32_t* __restrict__ counter,
+                                                           const uint32_t* __restrict__ unit_off,
+                                                           const uint64_t* __restrict__ recs) {
+    constexpr int JP = JC + 1;            // padded channel stride of a cell
+    constexpr int NC = TU * TV * JP;
+    using Acc = typename std::conditional<KAHAN, float, double>::type;
+    __shared__ Acc s_re[NC], s_im[NC], s_w[NC];
+    __shared__ uint32_t s_n[NC];
+    __shared__ float c_re[KAHAN ? NC : 1], c_im[KAHAN ? NC : 1], c_w[KAHAN ? NC : 1];
+    __shared__ uint32_t s_bid[NC];        // highest lane id (+1) bidding for a cell; 0 between rounds
+    __shared__ uint32_t s_unit;
+
+    const LaunchDesc& L = *Lp;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = sgpr(threadIdx.x / kWave);
+    const VISTA_GLOBAL uint64_t* grecs = gptr(recs);
+    const VISTA_GLOBAL RowCtx* rctx = gptr((const RowCtx*)L.rowctx);
+    const VISTA_GLOBAL int32_t* rtgt = gptr((const int32_t*)L.row_target);
+    const VISTA_GLOBAL DevTarget* gtgts = gptr(L.targets);
+    const VISTA_GLOBAL DevChan* chan_all = gptr(L.chan_all);
+    const VISTA_GLOBAL float* f1_all = gptr(L.f1_all);
+    const int phase_fp32 = L.phase_fp32;
+    const int32_t jsub = L.jsub;
+    const uint32_t id = (uint32_t)lane + 1u;
+
+    for (int i = threadIdx.x; i < NC; i += blockDim.x) s_bid[i] = 0u;
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t li = (uint32_t)sgpr((int32_t)s_unit);
+        if (li >= L.nunits) break;
+        const int64_t unit = (int64_t)ufl64(cptr(order)[li]);
+        const int32_t si = sgpr((int32_t)find_le_uniform(L.stack_unit_base, L.nstacks, unit));
+        const VISTA_CONST DevStack& S = cptr(L.stacks)[si];
+        const int64_t local = unit - S.unit_base;
+        const int64_t tile = local / S.nblocks;
+        const int32_t b = (int32_t)(local - tile * S.nblocks);
+        const int32_t tu0 = (int32_t)(tile % S.tiles_u) * TU;
+        const int32_t tv0 = (int32_t)(tile / S.tiles_u) * TV;
+        const int32_t jb0 = b * JC;
+        const int32_t jb1 = min(jb0 + JC, S.nchan);
+        const int32_t cu = S.nu / 2 - tu0, cv = S.nv / 2 - tv0;
+        const uint32_t ntu = (uint32_t)min(TU, S.nu - tu0), ntv = (uint32_t)min(TV, S.nv - tv0);   // in-grid part
+        const double inv_du = S.inv_du, inv_dv = S.inv_dv;
+
+        for (int i = threadIdx.x; i < NC; i += blockDim.x) {
+            s_re[i] = Acc(0); s_im[i] = Acc(0); s_w[i] = Acc(0); s_n[i] = 0u;
+            if (KAHAN) { c_re[i] = 0.f; c_im[i] = 0.f; c_w[i] = 0.f; }
+        }
+        __syncthreads();
+
+        const uint32_t rb = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit]);
+        const uint32_t re = (uint32_t)sgpr((int32_t)cptr(unit_off)[unit + 1]);
+        // this wavefront's slice of rest channels and its index among the stack's sub-blocks
+        const int32_t js0 = jb0 + wave * jsub;
+        const int32_t js1 = min(js0 + jsub, jb1);
+        const int32_t sbi = jb0 / jsub + wave;
+        // this lane's statistics of the unit: live, flagged and used polarisations of the
+        // samples whose first rest channel is in the slice, and contributions added
+        uint32_t st_live = 0, st_flag = 0, st_used = 0, st_contrib = 0;
+
+        // one addition to cell cc; no other lane writes cc meanwhile
+        auto add = [&](int cc, float f, float pr, float pi, float q, uint32_t n) __attribute__((always_inline)) {
+            if (KAHAN) {
+                const float xr = f * pr, xi = f * pi, xw = f * q;
+                float y, t;
+                y = xr - c_re[cc]; t = s_re[cc] + y; c_re[cc] = (t - s_re[cc]) - y; s_re[cc] = t;
+                y = xi - c_im[cc]; t = s_im[cc] + y; c_im[cc] = (t - s_im[cc]) - y; s_im[cc] = t;
+                y = xw - c_w[cc]; t = s_w[cc] + y; c_w[cc] = (t - s_w[cc]) - y; s_w[cc] = t;
+            } else {
+                s_re[cc] += (double)f * (double)pr;     // exact products, one rounding each
+                s_im[cc] += (double)f * (double)pi;
+                s_w[cc] += (double)f * (double)q;
+            }
+            s_n[cc] += n;
+            st_contrib += n;
+        };
+        // a lane's additions to its two cells c0 and c1 (< 0: none), which differ: every read
+        // is issued before any write, so the pair costs one LDS round trip
+        auto add2 = [&](int c0, int c1, float f0, float f1, float pr, float pi, float q, uint32_t n)
+                        __attribute__((always_inline)) {
+            const bool h0 = c0 >= 0, h1 = c1 >= 0;
+            Acc r0 = Acc(0), i0 = Acc(0), w0 = Acc(0), r1 = Acc(0), i1 = Acc(0), w1 = Acc(0);
+            float kr0 = 0.f, ki0 = 0.f, kw0 = 0.f, kr1 = 0.f, ki1 = 0.f, kw1 = 0.f;
+            uint32_t n0 = 0u, n1 = 0u;
+            if (h0) {
+                r0 = s_re[c0]; i0 = s_im[c0]; w0 = s_w[c0]; n0 = s_n[c0];
+                if (KAHAN) { kr0 = c_re[c0]; ki0 = c_im[c0]; kw0 = c_w[c0]; }
+            }
+            if (h1) {
+                r1 = s_re[c1]; i1 = s_im[c1]; w1 = s_w[c1]; n1 = s_n[c1];
+                if (KAHAN) { kr1 = c_re[c1]; ki1 = c_im[c1]; kw1 = c_w[c1]; }
+            }
+            if constexpr (KAHAN) {
+                auto kadd = [](float& sum, float& comp, float x) __attribute__((always_inline)) {
+                    const float y = x - comp, t = sum + y;
+                    comp = (t - sum) - y;
+                    sum = t;
+                };
+                kadd(r0, kr0, f0 * pr); kadd(i0, ki0, f0 * pi); kadd(w0, kw0, f0 * q);
+                kadd(r1, kr1, f1 * pr); kadd(i1, ki1, f1 * pi); kadd(w1, kw1, f1 * q);
+            } else {
+                r0 += (double)f0 * (double)pr; i0 += (double)f0 * (double)pi; w0 += (double)f0 * (double)q;
+                r1 += (double)f1 * (double)pr; i1 += (double)f1 * (double)pi; w1 += (double)f1 * (double)q;
+            }
+            if (h0) {
+                s_re[c0] = r0; s_im[c0] = i0; s_w[c0] = w0; s_n[c0] = n0 + n;
+                if (KAHAN) { c_re[c0] = kr0; c_im[c0] = ki0; c_w[c0] = kw0; }
+            }
+            if (h1) {
+                s_re[c1] = r1; s_im[c1] = i1; s_w[c1] = w1; s_n[c1] = n1 + n;
+                if (KAHAN) { c_re[c1] = kr1; c_im[c1] = ki1; c_w[c1] = kw1; }
+            }
+            st_contrib += (h0 ? n : 0u) + (h1 ? n : 0u);
+        };
+
+        for (uint32_t wb = rb; js0 < js1 && wb < re; wb += (uint32_t)kWave) {
+            // ---- window: records wb .. wb + 63, one per lane, clipped to the slice
+            const uint32_t nwin = min((uint32_t)kWave, re - wb);
+            const bool v = (uint32_t)lane < nwin;
+            const uint64_t rec = v ? grecs[wb + lane] : 0ull;
+            const uint32_t g = (uint32_t)(rec >> 32);
+            int32_t kin = (int32_t)((rec >> 16) & 0xffffu), kout = (int32_t)(rec & 0xffffu);
+            int32_t len = 0, nph = 1;
+            RecCtx<NPOL> w;
+            w.U = 0.0; w.V = 0.0; w.T = 0.0; w.w0 = 0.f; w.w1 = 0.f;
+            w.vis = 0; w.flag = 0; w.wadj = 0; w.info = 0; w.chan = 0; w.end = 0;
+            if (v) {
+                const VISTA_GLOBAL DevTarget& T = gtgts[rtgt[g]];
+                const VISTA_GLOBAL int32_t* sb = gptr(T.sblk);
+                kin = max(kin, sb[2 * sbi]);
+                kout = min(kout, sb[2 * sbi + 1]);
+                len = max(0, kout - kin);
+                nph = max(1, T.nphase);
+            }
+            // stream position of each clipped record: exclusive prefix sum of the lengths
+            uint32_t incl = (uint32_t)len;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, d, kWave);
+                if (lane >= d) incl += t;
+            }
+            const uint32_t P = incl - (uint32_t)len;
+            const uint32_t ltot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+            if (ltot == 0) continue;
+            // phases of this window: the largest nphase of its records, at least kOrdPhases
+            int32_t nphw = len > 0 ? max(nph, kOrdPhases) : kOrdPhases;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) nphw = max(nphw, __shfl_xor(nphw, d, kWave));
+            nphw = sgpr(nphw);
+            if (len > 0) {
+                // the record's context, its addresses rebased to stream positions
+                const VISTA_GLOBAL RowCtx& rc = rctx[g];
+                const int64_t d = (int64_t)kin - (int64_t)P;      // channel minus position
+                w.U = rc.U;
+                w.V = rc.V;
+                w.T = rc.T;
+                w.chan = rc.chan0 + (int32_t)d;
+                if (NPOL == 2) {
+                    w.w0 = rc.w0;
+                    w.w1 = rc.w1;
+                    w.vis = rc.vis + (uint64_t)(d * 16);
+                    w.flag = rc.flag + (uint64_t)(d * 2);
+                } else {
+                    const uint32_t info = rc.info;
+                    const int64_t np = info & 0xffu;
+                    const bool wpc = (info >> 8) & 1u;
+                    w.vis = rc.vis + (uint64_t)(d * np * 8);
+                    w.flag = rc.flag + (uint64_t)(d * np);
+                    w.wadj = rc.wrow + (wpc ? (uint64_t)(d * np * 4) : 0ull);
+                    w.info = (uint32_t)np | ((wpc ? (uint32_t)np * 4u : 0u) << 8);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): no window load stays pending below
+
+            // ---- chunks of 64 positions; live == false: an idle chunk at c0 (no lane active)
+            auto map = [&](uint32_t c0, OrdSample<NPOL>& x, bool live) __attribute__((always_inline)) {
+                // the record holding position c0, then those starting inside the chunk
+                const uint64_t m0 = __ballot(len > 0 && P <= c0);
+                const int r0 = 63 - (int)__clzll(m0);
+                const uint32_t p = c0 + (uint32_t)lane;
+                int r = r0;
+                uint64_t bm = __ballot(len > 0 && P > c0 && P < c0 + (uint32_t)kWave);
+                while (bm) {
+                    const int i = (int)__builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane((int)P, i);
+                    r = p >= pi ? i : r;
+                }
+                x.act = live && p < ltot;
+                x.rec = x.act ? r : r0;
+                x.pos = x.act ? p : c0;
+            };
+            auto issue = [&](OrdSample<NPOL>& x) __attribute__((always_inline)) {
+                const Bases<NPOL> c = gather_bases<NPOL>(w, x.rec);
+                load_sample<NPOL>(chan_all, f1_all, c, x.pos, x.s);
+            };
+            auto process = [&](const OrdSample<NPOL>& x) __attribute__((always_inline)) {
+                settle<NPOL>(x.s);
+                const Loaded<NPOL>& s = x.s;
+                const double U = bpermd(w.U, x.rec), V = bpermd(w.V, x.rec), T = bpermd(w.T, x.rec);
+                float w0 = 0.f, w1 = 0.f;
+                uint32_t info = 2u;
+                if (NPOL == 2) {
+                    w0 = bpermf(w.w0, x.rec);
+                    w1 = bpermf(w.w1, x.rec);
+                } else {
+                    info = bperm(w.info, x.rec);
+                }
+                const int32_t ci = (int32_t)bperm((uint32_t)w.chan, x.rec) + (int32_t)x.pos;
+                const uint32_t nj = x.act ? s.jn >> 24 : 0u;
+                const int32_t j0 = (int32_t)(s.jn & kJMask);
+                // cell within the tile (exact FP64 sequence of the definition)
+                const double ru = cell_coord(U, s.a, inv_du);
+                const double rv = cell_coord(V, s.a, inv_dv);
+                const int32_t lu = (int32_t)ru + cu, lv = (int32_t)rv + cv;
+                const bool in_tile = nj > 0 && (uint32_t)lu < ntu && (uint32_t)lv < ntv;
+                // polarisations: drop flagged and bad-weight samples, merge the rest
+                float ar = 0.f, ai = 0.f, q = 0.f;
+                uint32_t n = 0, nflag = 0;
+                const int np = NPOL == 2 ? 2 : (int)(info & 0xffu);
+#pragma unroll
+                for (int p = 0; p < (NPOL == 2 ? 2 : 4); ++p) {
+                    const bool live = NPOL == 2 || p < np;
+                    const float wgt = NPOL == 2 ? (p == 0 ? w0 : w1) : s.wc[p];
+                    const bool flagged = live && ((s.fl >> (8 * p)) & 0xffu) != 0u;
+                    const bool good = live && (wgt > 0.0f) && (wgt < __builtin_inff());
+                    nflag += flagged ? 1u : 0u;
+                    const bool use = !flagged && good;
+                    const float wu = use ? wgt : 0.0f;
+                    n += use ? 1u : 0u;
+                    ar = fmaf(wu, s.vr[p], ar);
+                    ai = fmaf(wu, s.vi[p], ai);
+                    q += wu;
+                }
+                // classification, counted once: in the slice holding j0
+                const bool home = in_tile && j0 >= js0 && j0 < js1;
+                st_live += home ? (uint32_t)np : 0u;
+                st_flag += home ? nflag : 0u;
+                st_used += home ? n : 0u;
+                float c, sn;
+                if (phase_fp32) {
+                    const float t = (float)T * (float)s.a;
+                    sincos_turns(t - rintf(t), &sn, &c);
+                } else {
+                    phasor(T, s.a, &c, &sn);
+                }
+                const float pr = ar * c - ai * sn;
+                const float pi = fmaf(ar, sn, ai * c);
+                const bool live_add = in_tile && n > 0;
+                const int cell = (lv * TU + lu) * JP - jb0;
+                const int a0 = (live_add && j0 >= js0 && j0 < js1) ? cell + j0 : -1;
+                const int a1 = (live_add && nj > 1 && j0 + 1 >= js0 && j0 + 1 < js1) ? cell + j0 + 1 : -1;
+                // phase: channel plus window lane of the record, modulo nphw.  Channels of one
+                // record fewer than nphw apart get different phases; so do the same channel
+                // of consecutive records (rows of one baseline often share a cell)
+                const int32_t ph_l = (ci + x.rec) % nphw;
+                for (int32_t ph = 0; ph < nphw; ++ph) {
+                    bool pend = (a0 >= 0 || a1 >= 0) && ph_l == ph;
+                    // each turn the highest waiting lane adds, so 64 turns always suffice
+                    for (int turn = 0; turn < kWave && __ballot(pend); ++turn) {
+                        if (pend) {
+                            if (a0 >= 0) atomicMax(&s_bid[a0], id);
+                            if (a1 >= 0) atomicMax(&s_bid[a1], id);
+                        }
+                        lds_order();
+                        bool win = false;
+                        if (pend) win = (a0 < 0 || s_bid[a0] == id) && (a1 < 0 || s_bid[a1] == id);
+                        lds_order();
+                        if (win) add2(a0, a1, s.f0, s.f1, pr, pi, q, n);
+                        if (pend) {
+                            if (a0 >= 0) s_bid[a0] = 0u;
+                            if (a1 >= 0) s_bid[a1] = 0u;
+                        }
+                        pend = pend && !win;
+                        lds_order();
+                    }
+                    if (__ballot(pend) && lane == 0) atomicOr(&S.stats[7], 2ull);
+                }
+                // rest channels beyond j0 + 1 (a rest grid finer than the channel): rare, one
+                // lane at a time in lane order
+                uint64_t xm = __ballot(live_add && nj > 2);
+                while (xm) {
+                    const int i = (int)__builtin_ctzll(xm);
+                    xm &= xm - 1;
+                    if (lane == i) {
+                        const int32_t fo = gptr(L.foff_all)[ci];
+                        for (int qq = 2; qq < (int)nj; ++qq) {
+                            const int32_t j = j0 + qq;
+                            if (j < js0 || j >= js1) continue;
+                            add(cell + j, gptr(L.fval_all)[fo + qq], pr, pi, q, n);
+                        }
+                    }
+                }
+            };
+
+            // two chunks in the pipeline: one processed while the next one's loads fly (an
+            // idle chunk's loads at the end, so that every path issues the same loads)
+            OrdSample<NPOL> x0, x1;
+            uint32_t c0 = 0;
+            map(0u, x0, true);
+            issue(x0);
+            for (;;) {
+                const bool l1 = c0 + (uint32_t)kWave < ltot;
+                map(l1 ? c0 + (uint32_t)kWave : c0, x1, l1);
+                issue(x1);
+                process(x0);
+                c0 += (uint32_t)kWave;
+                if (!l1) break;
+                const bool l0 = c0 + (uint32_t)kWave < ltot;
+                map(l0 ? c0 + (uint32_t)kWave : c0, x0, l0);
+                issue(x0);
+                process(x1);
+                c0 += (uint32_t)kWave;
+                if (!l0) break;
+            }
+        }
+
+        // statistics: one set of atomics per wavefront and unit; bad = live - flagged - used
+        const unsigned long long t_live = wave_sum_u64(st_live), t_flag = wave_sum_u64(st_flag);
+        const unsigned long long t_used = wave_sum_u64(st_used), t_contrib = wave_sum_u64(st_contrib);
+        if (lane == 0) {
+            const unsigned long long t_bad = t_live - t_flag - t_used;
+            if (t_flag) atomicAdd(&S.stats[1], t_flag);
+            if (t_bad) atomicAdd(&S.stats[2], t_bad);
+            if (t_used) atomicAdd(&S.stats[5], t_used);
+            if (t_contrib) atomicAdd(&S.stats[6], t_contrib);
+            if (t_contrib > 0xffffffffull) atomicOr(&S.stats[7], 1ull);   // a cell count may have wrapped
+        }
+        __syncthreads();
+
+        flush_unit<TU, TV, JP, Acc, KAHAN>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, c_re, c_im, c_w);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- record prefix, order
 
 __global__ void k_record_lens(const uint64_t* __restrict__ recs, const int64_t* __restrict__ n_dev,
@@ -876,6 +1254,93 @@ int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, 
 #undef X64
 #undef X32
 #undef X_ACC
+#undef X_OCC
+    return 0;
+}
+
+// Launch shapes (tile_u, tile_v, jblock) of the ordered kernel: 32 B of LDS per cell (FP64
+// sums, or FP32 sums with their compensations; a count; a bid slot).
+#define VISTA_ORDERED_SHAPES(X) \
+    X(8, 8, 64)                 \
+    X(16, 4, 64)                \
+    X(16, 8, 32)                \
+    X(8, 4, 128)                \
+    X(16, 2, 128)               \
+    X(4, 4, 256)                \
+    X(8, 2, 256)                \
+    X(4, 2, 512)
+
+static size_t ordered_lds_bytes(int tu, int tv, int jc) { return (size_t)tu * tv * (jc + 1) * 32 + 16; }
+
+int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap) {
+    if (mode == kModeAtomic) return accum_packed_shape_list(0, tu, tv, jc, cap);
+    int n = 0;
+#define X(a, b, c)            \
+    if (n < cap) {            \
+        tu[n] = a; tv[n] = b; jc[n] = c; \
+    }                         \
+    ++n;
+    VISTA_ORDERED_SHAPES(X)
+#undef X
+    return n;
+}
+
+size_t accum_lds_bytes(int tu, int tv, int jc, int mode, int kahan) { return ordered_lds_bytes(tu, tv, jc); }
+
+bool accum_shape_supported(int tu, int tv, int jc, int waves, int mode, int kahan) {
+    if (mode != kModeOrdered || waves < 1 || waves > 16 || (jc % waves) != 0) return false;
+#define X(a, b, c) \
+    if (tu == a && tv == b && jc == c) return ordered_lds_bytes(a, b, c) <= 160 * 1024;
+    VISTA_ORDERED_SHAPES(X)
+#undef X
+    return false;
+}
+
+// npol: 2 for launches whose targets all have two polarisations and row weights (the
+// specialised path); anything else selects the generic path.
+hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order,
+                             uint32_t* counter, const uint32_t* unit_off, const uint64_t* recs, int grid,
+                             int waves, int npol, hipStream_t stream) {
+    if (!accum_shape_supported(L.tu, L.tv, L.jc, waves, L.mode, L.kahan)) return hipErrorInvalidValue;
+#define X_LAUNCH(a, b, c, P, K)                                                                               \
+    hipLaunchKernelGGL((k_accum_ordered<a, b, c, P, K>), dim3(grid), dim3(waves * kWave), 0, stream, dL,     \
+                       order, counter, unit_off, recs)
+#define X(a, b, c)                                                                                            \
+    if (L.tu == a && L.tv == b && L.jc == c) {                                                                \
+        if (L.kahan) {                                                                                        \
+            if (npol == 2) X_LAUNCH(a, b, c, 2, true);                                                        \
+            else X_LAUNCH(a, b, c, 0, true);                                                                  \
+        } else {                                                                                              \
+            if (npol == 2) X_LAUNCH(a, b, c, 2, false);                                                       \
+            else X_LAUNCH(a, b, c, 0, false);                                                                 \
+        }                                                                                                     \
+        return hipGetLastError();                                                                             \
+    }
+    VISTA_ORDERED_SHAPES(X)
+#undef X
+#undef X_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+int accum_max_blocks_per_cu(int tu, int tv, int jc, int waves, int mode, int kahan, int npol) {
+    if (!accum_shape_supported(tu, tv, jc, waves, mode, kahan)) return 0;
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X_OCC(a, b, c, P, K) \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_accum_ordered<a, b, c, P, K>, waves * kWave, 0)
+#define X(a, b, c)                                     \
+    if (tu == a && tv == b && jc == c) {               \
+        if (kahan) {                                   \
+            if (npol == 2) X_OCC(a, b, c, 2, true);    \
+            else X_OCC(a, b, c, 0, true);              \
+        } else {                                       \
+            if (npol == 2) X_OCC(a, b, c, 2, false);   \
+            else X_OCC(a, b, c, 0, false);             \
+        }                                              \
+        return e == hipSuccess ? nb : 0;               \
+    }
+    VISTA_ORDERED_SHAPES(X)
+#undef X
 #undef X_OCC
     return 0;
 }

@@ -52,8 +52,8 @@ struct DevTarget {
     int32_t rotate, pad_rot;
 };
 
-// Context of row g of a launch, written once by the binning pass and read by the packed
-// accumulation for every record of the row.
+// Context of row g of a launch, written once by the binning pass and read by the
+// accumulation kernels for every record of the row.
 struct RowCtx {
     double U, V;              // uvw[r][0], uvw[r][1] [m]
     double T;                 // U l + V m + W (n - 1) [m]: channel k's Eq. 2 phase is T a_k
@@ -113,6 +113,7 @@ struct LaunchDesc {
     const int32_t* foff_all;          // offsets into fval_all
     const float* fval_all;
     RowCtx* rowctx;                   // [nrows]
+    int32_t* row_target;              // [nrows] each row's target (ordered mode; else null)
     const uint8_t* zero_flags;        // a zero row for targets without flags
 };
 

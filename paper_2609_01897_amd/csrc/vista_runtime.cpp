@@ -40,6 +40,15 @@ static int fail(int code, const std::string& msg) {
     return code;
 }
 
+// A launch's fault bits (its stacks' statistics slot 7): 1 = some cell took 2^32 or more
+// contributions, so its count may have wrapped; 2 = the ordered accumulation gave up on
+// ordering a chunk's additions (it bounds its turns; this cannot happen while each turn
+// lets the highest bidder add).
+static int fault_fail(uint64_t bits) {
+    if (bits & 1u) return fail(VISTA_E_RANGE, "a cell count exceeds 2^32-1");
+    return fail(VISTA_E_HIP, "the ordered accumulation left a chunk's additions unordered");
+}
+
 struct HipFail {
     hipError_t e;
     std::string where;
@@ -520,7 +529,7 @@ struct vista_batch {
         double2* vis64 = nullptr;
         double* w64 = nullptr;
         vista_stats st{};
-        bool overflow = false;
+        uint64_t overflow = 0;     // fault bits of the stack's launch (fault_fail)
     };
     std::vector<Result> res;
     std::vector<vista_output> reg;    // outputs registered before the run (mem < 0: none)
@@ -536,7 +545,7 @@ struct StackJob {
     std::vector<HostTarget*> targets;
     vista_output out;          // device pointers (or NULL)
     vista_stats stats{};
-    bool overflow = false;
+    uint64_t overflow = 0;     // fault bits of the stack's launch (fault_fail)
     int32_t index = 0;         // slot of the stack's statistics
     // carried state of a stack streamed over several waves, and this launch's role
     float* st_s = nullptr;
@@ -834,7 +843,8 @@ class Launcher {
             d_tb_ = mem_.alloc_n<int64_t>(c.stacks + 1);
             d_ub_ = mem_.alloc_n<int64_t>(c.stacks + 1);
             d_arena_ = mem_.alloc_n<unsigned char>(std::max<int64_t>(256, c.arena));
-            rowctx_ = mode_ == kModeAtomic ? mem_.alloc_n<RowCtx>(std::max<int64_t>(1, c.rows)) : nullptr;
+            rowctx_ = mem_.alloc_n<RowCtx>(std::max<int64_t>(1, c.rows));
+            row_target_ = mode_ == kModeOrdered ? mem_.alloc_n<int32_t>(std::max<int64_t>(1, c.rows)) : nullptr;
             zflags_ = nullptr;
             if (c.zflag > 0) {
                 int64_t words = (c.zflag + 3) / 4;
@@ -907,6 +917,7 @@ class Launcher {
         L.foff_all = d_foff;
         L.fval_all = d_fval;
         L.rowctx = rowctx_;
+        L.row_target = row_target_;
         L.zero_flags = zflags_;
         npol_ = h.npol_all;
         agg_ = h.agg;
@@ -1022,6 +1033,7 @@ class Launcher {
     int64_t *d_rb_ = nullptr, *d_tb_ = nullptr, *d_ub_ = nullptr;
     unsigned char* d_arena_ = nullptr;
     RowCtx* rowctx_ = nullptr;
+    int32_t* row_target_ = nullptr;
     const uint8_t* zflags_ = nullptr;
     uint32_t *cnt_ = nullptr, *off_ = nullptr, *unit_off_ = nullptr, *okeys_ = nullptr, *counter_ = nullptr;
     uint64_t *sums_ = nullptr, *order_ = nullptr;
@@ -1077,7 +1089,7 @@ static void collect_stats(std::vector<StackJob>& jobs, const std::vector<unsigne
         o.n_outside_uv = st[k + 3];
         o.n_used = st[k + 5];
         o.n_contrib = st[k + 6];
-        jobs[s].overflow = st[k + 7] != 0;
+        jobs[s].overflow = st[k + 7];
     }
 }
 
@@ -1549,7 +1561,7 @@ int vista_stack_finalize(vista_stack* s, const vista_output* o, vista_stats* st)
         VISTA_HIP(hipStreamSynchronize(s->stream));
         if (st) *st = jobs[0].stats;
         s->state = 1;
-        if (jobs[0].overflow) return fail(VISTA_E_RANGE, "a cell count exceeds 2^32-1");
+        if (jobs[0].overflow) return fault_fail(jobs[0].overflow);
         return VISTA_OK;
     });
 }
@@ -2260,7 +2272,7 @@ int vista_batch_finalize(vista_batch* b, int32_t stack, const vista_output* o, v
         }
         VISTA_HIP(hipStreamSynchronize(b->stream));
         if (st) *st = R.st;
-        if (R.overflow) return fail(VISTA_E_RANGE, "a cell count exceeds 2^32-1");
+        if (R.overflow) return fault_fail(R.overflow);
         return VISTA_OK;
     });
 }
