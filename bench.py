@@ -87,13 +87,22 @@ def counter_traffic(config_name, shape):
     return None
 
 
-def batched_counter_traffic():
+def parse_tuning(text):
+    """A launch shape from "tile_u,tile_v,jblock,waves" ("" -> None)."""
+    if not text:
+        return None
+    a = [int(x) for x in text.split(",")]
+    return dict(tile_u=a[0], tile_v=a[1], jblock=a[2], waves=a[3])
+
+
+def batched_counter_traffic(shape):
     """Counter-measured HBM bytes of the batched recipe's accumulation launch, if the
-    committed summary was taken on the current kernel source (library default shape)."""
+    committed summary was taken on the current kernel source and in this launch shape."""
     try:
         d = json.load(open(PROFILE_BATCHED))
         h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if d.get("kernel_sha256") == h and d.get("config") == "c4":
+        want = {k: int(shape[k]) for k in ("tile_u", "tile_v", "jblock", "waves")} if shape else None
+        if d.get("kernel_sha256") == h and d.get("config") == "c4" and d.get("launch_shape") == want:
             return d.get("hbm_bytes_per_launch")
     except Exception:
         pass
@@ -425,14 +434,18 @@ BATCH_POOL_BYTES = 120e9      # device-resident pool of distinct datasets
 BATCH_CHECK = (3, (124, 132))  # stack checked against the oracle, and its rest channels
 
 
-def batched_leg(reps=1, with_reference=True, forms=None):
+def batched_leg(reps=1, with_reference=True, forms=None, autotune=True, batched_tuning=None):
     """The batched recipe at its own shape: 64 stacks of clip(round(lognormal(ln 40, 1)),
     5, 500) targets (3871 in all), 12-50 antennas, 60 integrations, channels from {128, 480,
     960, 3840}, z ~ U(0.5, 4), grids of 256 x 256 x 256.  Its 3.1 TB of input exceed HBM, so
     targets draw on a device-resident pool of distinct datasets (each target with its own
     z, offset and channel axis); every target's bytes are read in full.  Forms: (a) plain
     FP32, one stack per launch; (b) compensated, one stack per launch; (c) every stack in
-    one batched, compensated launch (one captured graph)."""
+    one batched, compensated launch (one captured graph).  Each form runs the launch shape
+    the autotuner picks for it: the batched form on the whole batch, the per-launch forms
+    on the stack of median size (one shape for all 64 launches); with autotune=False every
+    form takes the library default.  batched_tuning, if given, is the batched form's shape
+    (no autotuning for it)."""
     import torch
     import synth
     from paper_2609_01897_amd import vista
@@ -456,19 +469,19 @@ def batched_leg(reps=1, with_reference=True, forms=None):
                                               nbytes / 1e12, time.perf_counter() - t0))
     outs = [vista.alloc_outputs(grid) for _ in stacks]
 
-    def per_launch(flags):
+    def per_launch(flags, tuning):
         def run():
             acc = 0.0
             for s, ts in enumerate(stacks):
-                _, st, tim = vista.stack(grid, ts, flags=flags, out=outs[s], with_timings=True)
+                _, st, tim = vista.stack(grid, ts, flags=flags, out=outs[s], tuning=tuning, with_timings=True)
                 acc += tim["accum_ms"]
             return acc
         return run
 
-    def batched(flags):
+    def batched(flags, tuning):
         def run():
             g = dict(grid, flags=flags)
-            b = vista.Batch([g] * len(stacks))
+            b = vista.Batch([g] * len(stacks), tuning=tuning)
             for s, ts in enumerate(stacks):
                 for t in ts:
                     b.add(s, t)
@@ -502,17 +515,46 @@ def batched_leg(reps=1, with_reference=True, forms=None):
                        "total), 12-50 antennas, 60 integrations, channels from {128, 480, 960, 3840}, z ~ U(0.5, 4), "
                        "grid 256x256x256 per stack; targets draw on a device-resident pool of %d distinct datasets "
                        "(%.0f GB)" % (len(stacks), len(all_t), len(pool), pool_bytes / 1e9),
-           "samples": nsamp, "algorithmic_bytes": nbytes, "launch_shape": "library defaults"}
-    all_forms = [("plain_fp32_one_stack_per_launch", per_launch(vista.F_PLAIN_FP32)),
-                 ("compensated_one_stack_per_launch", per_launch(0)),
-                 ("batched_compensated", batched(0))]
-    for name, fn in all_forms:
+           "samples": nsamp, "algorithmic_bytes": nbytes}
+    median = sorted(range(len(stacks)), key=lambda i: (len(stacks[i]), i))[len(stacks) // 2]
+
+    def shape_for(name, flags):
+        """The form's launch shape and where it came from."""
+        if name == "batched_compensated" and batched_tuning:
+            return batched_tuning, "given"
+        if not autotune:
+            return None, "default"
+        t0 = time.perf_counter()
+        if name == "batched_compensated":
+            b = vista.Batch([dict(grid, flags=flags)] * len(stacks))
+            for s, ts in enumerate(stacks):
+                for t in ts:
+                    b.add(s, t)
+            tu = b.autotune()
+            b.close()
+            src = "autotuned on the whole batch"
+        else:
+            st = vista.Stack(grid, flags=flags)
+            for t in stacks[median]:
+                st.add(t)
+            tu = st.autotune()
+            st.close()
+            src = "autotuned on the stack of median size (%d targets)" % len(stacks[median])
+        log("batched recipe, %s: %s launch shape %s in %.1f s" % (name, src, tu, time.perf_counter() - t0))
+        return tu, src
+
+    all_forms = [("plain_fp32_one_stack_per_launch", vista.F_PLAIN_FP32, per_launch),
+                 ("compensated_one_stack_per_launch", 0, per_launch),
+                 ("batched_compensated", 0, batched)]
+    for name, flags, make in all_forms:
         if forms and name not in forms:
             continue
-        ms, acc_ms = timed(fn)
+        tuning, src = shape_for(name, flags)
+        ms, acc_ms = timed(make(flags, tuning))
         rec = {"ms": ms, "accumulate_ms": acc_ms, "samples_per_s": nsamp / (ms / 1e3),
+               "launch_shape": dict(tuning or {}, source=src),
                "roofline": roofline(nbytes, acc_ms,
-                                    batched_counter_traffic() if name == "batched_compensated" else None)}
+                                    batched_counter_traffic(tuning) if name == "batched_compensated" else None)}
         if ref is not None:
             rec["accuracy"] = errors(ref, outs[si], *slab)
             rec["accuracy"]["stack"] = si
@@ -731,6 +773,8 @@ def main():
     ap.add_argument("--batched-forms", default="", help="comma list of the batched recipe's forms to run "
                     "(plain_fp32_one_stack_per_launch, compensated_one_stack_per_launch, batched_compensated); "
                     "default all")
+    ap.add_argument("--batched-tuning", default="", help="tile_u,tile_v,jblock,waves of the batched recipe's "
+                    "batched form (default: autotuned on the batch)")
     ap.add_argument("--no-streamed", action="store_true", help="skip the pinned-host streamed recipe")
     ap.add_argument("--no-rebinned", action="store_true", help="skip the per-row rebinned leg")
     ap.add_argument("--no-rotated", action="store_true", help="skip the step with Eq. 1's rotation on")
@@ -765,10 +809,7 @@ def main():
     for f in filter(None, args.flags.split(",")):
         flags |= {"kahan": vista.F_KAHAN, "deterministic": vista.F_DETERMINISTIC,
                   "phase_fp32": vista.F_PHASE_FP32, "plain_fp32": vista.F_PLAIN_FP32}[f]
-    tuning = None
-    if args.tuning:
-        a = [int(x) for x in args.tuning.split(",")]
-        tuning = dict(tile_u=a[0], tile_v=a[1], jblock=a[2], waves=a[3])
+    tuning = parse_tuning(args.tuning)
 
     t0 = time.perf_counter()
     targets = []
@@ -812,6 +853,7 @@ def main():
     log("step %.2f ms, accumulate %.2f ms, binning %.2f ms; %.3e samples/s; %.0f GB/s algorithmic" % (
         ms, acc_ms, sum(binms) / len(binms), value, rl["achieved"]))
     assert st["n_samples"] == nsamp, (st, nsamp)
+    del step                                  # it holds the workload and the grid
 
     res = {
         "metric": METRIC,
@@ -871,7 +913,10 @@ def main():
         if skip:
             continue
         try:
-            kw = {"forms": [f for f in args.batched_forms.split(",") if f]} if name == "batched" else {}
+            kw = {}
+            if name == "batched":
+                kw = {"forms": [f for f in args.batched_forms.split(",") if f], "autotune": not args.no_autotune,
+                      "batched_tuning": parse_tuning(args.batched_tuning)}
             res[name] = leg(with_reference=not args.no_cpu, **kw)
         except Exception as e:                  # the main line is printed whatever a leg does
             log("%s leg failed: %r" % (name, e))
