@@ -58,7 +58,12 @@ def _slab_check(grid, targets, bulk_of, out, jlo, jhi, tol_fn=compare):
     return err
 
 
-def test_c4_seeded_subset_in_one_batch():
+@pytest.mark.parametrize("tuning", [None, dict(tile_u=8, tile_v=4, jblock=64, waves=8)],
+                         ids=["default_shape", "tuned_shape"])
+def test_c4_seeded_subset_in_one_batch(tuning):
+    """Four seeded stacks of the batched recipe in one batch, in the library's default
+    launch shape and in the one the autotuner picks for the whole recipe (8 x 4 x 64,
+    8 wavefronts), each stack against the oracle."""
     cfg = synth.config("c4")
     sizes = synth.batch_stack_sizes(64, seed=C4_SIZES_SEED)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(C4_PICK_SEED)))
@@ -68,7 +73,7 @@ def test_c4_seeded_subset_in_one_batch():
     print("stacks", pick, "targets", [len(x) for x in stacks], flush=True)
     grid = synth.make_grid(cfg)
     outs = [vista.alloc_outputs(grid) for _ in stacks]
-    b = vista.Batch([grid] * len(stacks))
+    b = vista.Batch([grid] * len(stacks), tuning=tuning)
     for s, ts in enumerate(stacks):
         for t in ts:
             b.add(s, t)

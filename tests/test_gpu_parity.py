@@ -289,13 +289,14 @@ def lds_updates(request, monkeypatch):
     return request.param
 
 
-@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("waves", [4, 8, 16])
 @pytest.mark.parametrize("shape", PACKED_SHAPES)
 def test_every_tile_shape_matches(shape, waves, small_case, lds_updates):
     """The autotuner's candidates change only speed: counts identical, sums in tolerance
     (plain and compensated; the ordered kernel on the shapes it is built for), with 4
-    wavefronts per workgroup and with the 16 whose per-wavefront stream split the
-    benchmark runs."""
+    wavefronts per workgroup, with 8 (two workgroups per compute unit, as the batched
+    recipe's tuned shape runs) and with the 16 whose per-wavefront stream split the
+    default workload's benchmark runs."""
     g, ds, o = small_case
     tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
     out, st = gpu_stack(g, ds, tuning=tu)
@@ -318,7 +319,7 @@ def test_every_ordered_shape_matches(shape, waves, small_case):
         compare(o, out, st=st)
 
 
-@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("waves", [4, 8, 16])
 @pytest.mark.parametrize("shape", PACKED_SHAPES_F32)
 def test_every_fp32_tile_shape_matches(shape, waves, small_case, lds_updates):
     """The plain FP32 form's shapes (FP32 per-tile sums, 16 B of LDS per cell)."""
