@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
     __shared__ Acc s_re[NC], s_im[NC], s_w[NC];
     __shared__ uint32_t s_n[NC];
     __shared__ float c_re[KAHAN ? NC : 1], c_im[KAHAN ? NC : 1], c_w[KAHAN ? NC : 1];
-    __shared__ uint32_t s_bid[NC];        // highest lane id (+1) bidding for a cell; 0 between turns
+    __shared__ uint32_t s_bid[NC];        // highest lane id (+1) bidding for a cell; 0 between rounds
     __shared__ uint32_t s_unit;
 
     const LaunchDesc& L = *Lp;
