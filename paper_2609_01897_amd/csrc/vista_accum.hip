@@ -739,10 +739,13 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                                                            const uint64_t* __restrict__ recs) {
     constexpr int JP = JC + 1;            // padded channel stride of a cell
     constexpr int NC = TU * TV * JP;
-    using Acc = typename std::conditional<KAHAN, float, double>::type;
-    __shared__ Acc s_re[NC], s_im[NC], s_w[NC];
+    // a cell's state, a lane's few LDS accesses: KAHAN, (re, its compensation, im, its
+    // compensation) and (w, its compensation) in FP32; else (re, im) and w in FP64
+    using Sri = typename std::conditional<KAHAN, float4, double2>::type;
+    using Sw = typename std::conditional<KAHAN, float2, double>::type;
+    __shared__ Sri s_ri[NC];
+    __shared__ Sw s_w[NC];
     __shared__ uint32_t s_n[NC];
-    __shared__ float c_re[KAHAN ? NC : 1], c_im[KAHAN ? NC : 1], c_w[KAHAN ? NC : 1];
     __shared__ uint32_t s_bid[NC];        // highest lane id (+1) bidding for a cell; 0 between rounds
     __shared__ uint32_t s_unit;
 
@@ -780,8 +783,9 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         const double inv_du = S.inv_du, inv_dv = S.inv_dv;
 
         for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-            s_re[i] = Acc(0); s_im[i] = Acc(0); s_w[i] = Acc(0); s_n[i] = 0u;
-            if (KAHAN) { c_re[i] = 0.f; c_im[i] = 0.f; c_w[i] = 0.f; }
+            s_ri[i] = Sri{};
+            s_w[i] = Sw{};
+            s_n[i] = 0u;
         }
         __syncthreads();
 
@@ -795,20 +799,34 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         // samples whose first rest channel is in the slice, and contributions added
         uint32_t st_live = 0, st_flag = 0, st_used = 0, st_contrib = 0;
 
+        // one addition of (f pr, f pi, f q) and count n to a cell's state in registers
+        auto accum = [&](Sri& ri, Sw& w, uint32_t& cnt, float f, float pr, float pi, float q, uint32_t n)
+                         __attribute__((always_inline)) {
+            if constexpr (KAHAN) {
+                auto kadd = [](float& sum, float& comp, float x) __attribute__((always_inline)) {
+                    const float y = x - comp, t = sum + y;
+                    comp = (t - sum) - y;
+                    sum = t;
+                };
+                kadd(ri.x, ri.y, f * pr);
+                kadd(ri.z, ri.w, f * pi);
+                kadd(w.x, w.y, f * q);
+            } else {
+                ri.x += (double)f * (double)pr;     // exact products, one rounding each
+                ri.y += (double)f * (double)pi;
+                w += (double)f * (double)q;
+            }
+            cnt += n;
+        };
         // one addition to cell cc; no other lane writes cc meanwhile
         auto add = [&](int cc, float f, float pr, float pi, float q, uint32_t n) __attribute__((always_inline)) {
-            if (KAHAN) {
-                const float xr = f * pr, xi = f * pi, xw = f * q;
-                float y, t;
-                y = xr - c_re[cc]; t = s_re[cc] + y; c_re[cc] = (t - s_re[cc]) - y; s_re[cc] = t;
-                y = xi - c_im[cc]; t = s_im[cc] + y; c_im[cc] = (t - s_im[cc]) - y; s_im[cc] = t;
-                y = xw - c_w[cc]; t = s_w[cc] + y; c_w[cc] = (t - s_w[cc]) - y; s_w[cc] = t;
-            } else {
-                s_re[cc] += (double)f * (double)pr;     // exact products, one rounding each
-                s_im[cc] += (double)f * (double)pi;
-                s_w[cc] += (double)f * (double)q;
-            }
-            s_n[cc] += n;
+            Sri ri = s_ri[cc];
+            Sw w = s_w[cc];
+            uint32_t cnt = s_n[cc];
+            accum(ri, w, cnt, f, pr, pi, q, n);
+            s_ri[cc] = ri;
+            s_w[cc] = w;
+            s_n[cc] = cnt;
             st_contrib += n;
         };
         // a lane's additions to its two cells c0 and c1 (< 0: none), which differ: every read
@@ -816,37 +834,15 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         auto add2 = [&](int c0, int c1, float f0, float f1, float pr, float pi, float q, uint32_t n)
                         __attribute__((always_inline)) {
             const bool h0 = c0 >= 0, h1 = c1 >= 0;
-            Acc r0 = Acc(0), i0 = Acc(0), w0 = Acc(0), r1 = Acc(0), i1 = Acc(0), w1 = Acc(0);
-            float kr0 = 0.f, ki0 = 0.f, kw0 = 0.f, kr1 = 0.f, ki1 = 0.f, kw1 = 0.f;
+            Sri ri0{}, ri1{};
+            Sw w0{}, w1{};
             uint32_t n0 = 0u, n1 = 0u;
-            if (h0) {
-                r0 = s_re[c0]; i0 = s_im[c0]; w0 = s_w[c0]; n0 = s_n[c0];
-                if (KAHAN) { kr0 = c_re[c0]; ki0 = c_im[c0]; kw0 = c_w[c0]; }
-            }
-            if (h1) {
-                r1 = s_re[c1]; i1 = s_im[c1]; w1 = s_w[c1]; n1 = s_n[c1];
-                if (KAHAN) { kr1 = c_re[c1]; ki1 = c_im[c1]; kw1 = c_w[c1]; }
-            }
-            if constexpr (KAHAN) {
-                auto kadd = [](float& sum, float& comp, float x) __attribute__((always_inline)) {
-                    const float y = x - comp, t = sum + y;
-                    comp = (t - sum) - y;
-                    sum = t;
-                };
-                kadd(r0, kr0, f0 * pr); kadd(i0, ki0, f0 * pi); kadd(w0, kw0, f0 * q);
-                kadd(r1, kr1, f1 * pr); kadd(i1, ki1, f1 * pi); kadd(w1, kw1, f1 * q);
-            } else {
-                r0 += (double)f0 * (double)pr; i0 += (double)f0 * (double)pi; w0 += (double)f0 * (double)q;
-                r1 += (double)f1 * (double)pr; i1 += (double)f1 * (double)pi; w1 += (double)f1 * (double)q;
-            }
-            if (h0) {
-                s_re[c0] = r0; s_im[c0] = i0; s_w[c0] = w0; s_n[c0] = n0 + n;
-                if (KAHAN) { c_re[c0] = kr0; c_im[c0] = ki0; c_w[c0] = kw0; }
-            }
-            if (h1) {
-                s_re[c1] = r1; s_im[c1] = i1; s_w[c1] = w1; s_n[c1] = n1 + n;
-                if (KAHAN) { c_re[c1] = kr1; c_im[c1] = ki1; c_w[c1] = kw1; }
-            }
+            if (h0) { ri0 = s_ri[c0]; w0 = s_w[c0]; n0 = s_n[c0]; }
+            if (h1) { ri1 = s_ri[c1]; w1 = s_w[c1]; n1 = s_n[c1]; }
+            accum(ri0, w0, n0, f0, pr, pi, q, n);
+            accum(ri1, w1, n1, f1, pr, pi, q, n);
+            if (h0) { s_ri[c0] = ri0; s_w[c0] = w0; s_n[c0] = n0; }
+            if (h1) { s_ri[c1] = ri1; s_w[c1] = w1; s_n[c1] = n1; }
             st_contrib += (h0 ? n : 0u) + (h1 ? n : 0u);
         };
 
@@ -1065,7 +1061,20 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         }
         __syncthreads();
 
-        flush_unit<TU, TV, JP, Acc, KAHAN>(L, S, tu0, tv0, jb0, jb1, s_re, s_im, s_w, s_n, c_re, c_im, c_w);
+        flush_cells<TU, TV, JP>(L, S, tu0, tv0, jb0, jb1,
+                                [&](int c, double& dre, double& dim, double& dw, uint32_t& n)
+                                    __attribute__((always_inline)) {
+            const Sri ri = s_ri[c];
+            const Sw w = s_w[c];
+            if constexpr (KAHAN) {
+                dre = (double)ri.x - (double)ri.y;
+                dim = (double)ri.z - (double)ri.w;
+                dw = (double)w.x - (double)w.y;
+            } else {
+                dre = ri.x; dim = ri.y; dw = w;
+            }
+            n = s_n[c];
+        });
         __syncthreads();
     }
 }

@@ -115,13 +115,12 @@ __device__ __forceinline__ void phasor_fp32(float u, float v, float w, float l, 
 // state (cell c = (lv TU + lu) JP + j - jb0) to the outputs, iu fastest so that stores are
 // contiguous runs of TU cells; with a carried state, merge into it instead (the unit owns
 // its cells, so no other workgroup touches them).  Every field of the stack is read once,
-// into registers, before the first store.  ZERO: also clear every cell read (the next unit
-// then starts from zero without a separate pass).
-template <int TU, int TV, int JP, class Acc, bool KAHAN, bool ZERO = false>
-__device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONST DevStack& S, int32_t tu0,
-                                           int32_t tv0, int32_t jb0, int32_t jb1, Acc* s_re,
-                                           Acc* s_im, Acc* s_w, uint32_t* s_n,
-                                           const float* c_re, const float* c_im, const float* c_w) {
+// into registers, before the first store.  The cells' values come from
+// read(c, re, im, w, n), which may also clear cell c (the next unit then starts from zero
+// without a separate pass).
+template <int TU, int TV, int JP, class Read>
+__device__ __forceinline__ void flush_cells(const LaunchDesc& L, const VISTA_CONST DevStack& S, int32_t tu0,
+                                            int32_t tv0, int32_t jb0, int32_t jb1, Read read) {
     const int32_t nu = S.nu, nv = S.nv;
     VISTA_GLOBAL float2* const o_vis = (VISTA_GLOBAL float2*)S.out_vis;
     VISTA_GLOBAL float* const o_w = (VISTA_GLOBAL float*)S.out_w;
@@ -147,17 +146,8 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
         const int c = (lv * TU + lu) * JP + jl;
         const size_t o = ((size_t)(jb0 + jl) * nv + iv) * nu + iu;
         double dre, dim, dw;
-        if (KAHAN) {
-            dre = (double)s_re[c] - (double)c_re[c];
-            dim = (double)s_im[c] - (double)c_im[c];
-            dw = (double)s_w[c] - (double)c_w[c];
-        } else {
-            dre = (double)s_re[c]; dim = (double)s_im[c]; dw = (double)s_w[c];
-        }
-        uint32_t n = s_n[c];
-        if (ZERO) {
-            s_re[c] = 0; s_im[c] = 0; s_w[c] = 0; s_n[c] = 0u;
-        }
+        uint32_t n;
+        read(c, dre, dim, dw, n);
         if (carry) {
             // merge into the state carried across passes
             const size_t os = sbase + (size_t)i;        // the unit's state block, contiguous in i
@@ -193,6 +183,30 @@ __device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONS
         if (o_vis64) o_vis64[o] = make_double2(dre, dim);
         if (o_w64) o_w64[o] = dw;
     }
+}
+
+// flush_cells over per-cell arrays of sums (and, KAHAN, their compensations) and counts;
+// ZERO: clear every cell read.
+template <int TU, int TV, int JP, class Acc, bool KAHAN, bool ZERO = false>
+__device__ __forceinline__ void flush_unit(const LaunchDesc& L, const VISTA_CONST DevStack& S, int32_t tu0,
+                                           int32_t tv0, int32_t jb0, int32_t jb1, Acc* s_re,
+                                           Acc* s_im, Acc* s_w, uint32_t* s_n,
+                                           const float* c_re, const float* c_im, const float* c_w) {
+    flush_cells<TU, TV, JP>(L, S, tu0, tv0, jb0, jb1,
+                            [&](int c, double& dre, double& dim, double& dw, uint32_t& n)
+                                __attribute__((always_inline)) {
+        if (KAHAN) {
+            dre = (double)s_re[c] - (double)c_re[c];
+            dim = (double)s_im[c] - (double)c_im[c];
+            dw = (double)s_w[c] - (double)c_w[c];
+        } else {
+            dre = (double)s_re[c]; dim = (double)s_im[c]; dw = (double)s_w[c];
+        }
+        n = s_n[c];
+        if (ZERO) {
+            s_re[c] = 0; s_im[c] = 0; s_w[c] = 0; s_n[c] = 0u;
+        }
+    });
 }
 
 }  // namespace
