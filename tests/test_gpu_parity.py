@@ -215,8 +215,9 @@ def test_empty_and_single_channel_targets():
     empty.flag = empty.flag[:0]
     hs = [h0, empty, h1, h2]
     o = oracle.stack(g, hs)
-    out, st = gpu_stack(g, [h.to("cuda") for h in hs])
-    compare(o, out, st=st)
+    for flags in (0, vista.F_DETERMINISTIC | vista.F_KAHAN):
+        out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=flags)
+        compare(o, out, st=st)
 
 
 def _one_tile_one_channel(cfg, g, i, k=None):
@@ -255,6 +256,11 @@ def test_long_runs_of_one_channel_records(wide, waves):
     out, st = gpu_stack(g, [h.to("cuda") for h in hs], tuning=dict(tile_u=8, tile_v=8, jblock=64, waves=waves))
     compare(o, out, st=st)
     out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=vista.F_KAHAN,
+                        tuning=dict(tile_u=8, tile_v=8, jblock=64, waves=waves))
+    compare(o, out, st=st)
+    # the ordered kernel: chunks of 64 one-channel records whose rows share a few cells, so
+    # lanes of one phase meet in a cell and take many turns
+    out, st = gpu_stack(g, [h.to("cuda") for h in hs], flags=vista.F_DETERMINISTIC | vista.F_KAHAN,
                         tuning=dict(tile_u=8, tile_v=8, jblock=64, waves=waves))
     compare(o, out, st=st)
 
@@ -330,12 +336,13 @@ def test_every_fp32_tile_shape_matches(shape, waves, small_case, lds_updates):
 
 
 @pytest.mark.parametrize("npol", [2, 1, 4])
-@pytest.mark.parametrize("mode", ["atomic", "kahan", "plain_fp32"])
+@pytest.mark.parametrize("mode", ["atomic", "kahan", "plain_fp32", "deterministic_kahan"])
 def test_fine_channels_match_oracle(mode, npol, lds_updates):
     """Targets of 3000 channels over a band whose rest channels each take dozens of them
     (and whose uv cells change slowly along the channel axis): lanes hold long runs of
     samples adding to one cell, the case the aggregated LDS updates are for; both update
-    forms against the oracle, with a coarse target mixed in."""
+    forms against the oracle, with a coarse target mixed in.  The ordered kernel (which has
+    one update form) meets the same runs as dozens of phases per chunk."""
     cfg = synth.config("small", npol=npol)
     g = synth.make_grid(cfg)
     hs = [synth.make_target(cfg, 0, nchan=3000, n_int=6), synth.make_target(cfg, 1, nchan=2500, n_int=6,
