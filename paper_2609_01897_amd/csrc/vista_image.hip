@@ -9,7 +9,10 @@
 // and by a constant (-1 per axis of length 2, else 1).  The 2-D transform is done as row
 // transforms then column transforms.  Transforms of 64 to 1024 points are held in registers
 // (split into two shorter transforms with a twiddle, one exchange through LDS); other
-// lengths use a Stockham (self-sorting) FFT in LDS.  The column passes work on tiles of
+// lengths use a Stockham (self-sorting) FFT in LDS.  Where both passes run in registers
+// and 128 <= nv <= 2048, only the real part is formed: the row pass transforms the input's
+// Hermitian part, of which rows 0 .. nv/2 are kept, and the column pass is a real
+// transform from them (half the staging bytes).  The column passes work on tiles of
 // adjacent columns so that their loads and stores are contiguous runs.  Nothing here is a
 // matrix product: the work is a few passes over the grid in HBM.
 #include <hip/hip_runtime.h>
@@ -385,6 +388,144 @@ __global__ void __launch_bounds__(1 << (LOGG + LOGRT)) k_image_rows_reg(const vo
     }
 }
 
+// The Hermitian path (real output from half the staging).  With y the centred input, the
+// image is Re F(y) = F(y_h), y_h(iu, iv) = (y(iu, iv) + conj(y(-iu, -iv))) / 2 (indices
+// modulo the sides; the centring sign of (-iu, -iv) is that of (iu, iv), the sides being
+// even).  y_h's row transforms T are Hermitian along each column, T(p, nv - k) =
+// conj(T(p, k)), so rows 0 .. nv/2 of T determine the image and the column pass is a
+// complex-to-real transform.
+//
+// Row pass: as k_image_rows_reg, for rows k = 0 .. nv/2 only, each loaded together with the
+// mirror row (nv - k) mod nv read backwards ((nu - iu) mod nu) and folded into y_h before
+// the transform.  Block x takes rows x RT .. x RT + RT - 1; rows past nv/2 (the last block)
+// are transformed but not stored.
+template <int LOGG, int LOGR, int LOGRT, bool REAL>
+__global__ void __launch_bounds__(1 << (LOGG + LOGRT)) k_image_rows_herm(const void* __restrict__ src,
+                                                                          float2* __restrict__ tmp, int lognv) {
+    constexpr int G = 1 << LOGG, R = 1 << LOGR, RT = 1 << LOGRT, NU = G * R, S = R / G, RP = R + 1;
+    static_assert(G <= R && R <= 32 && G % 2 == 0, "tile split");
+    __shared__ float2 lds[RT * G * RP];
+    const int g = threadIdx.x & (G - 1), r = threadIdx.x >> LOGG;
+    const int nv = 1 << lognv;
+    const int j = blockIdx.y, k = blockIdx.x * RT + r;
+    const int kr = min(k, nv - 1);                         // (rows past nv/2 are not stored)
+    const int km = (nv - kr) & (nv - 1);                   // the mirror row
+    const size_t row = ((size_t)j << lognv) + kr, mrow = ((size_t)j << lognv) + km;
+    float2 v[R];
+    const float sg = ((g + kr) & 1) ? -0.5f : 0.5f;        // (-1)^(iu + k) / 2, iu = g + G kk, G even
+    if (REAL) {
+        const VISTA_GLOBAL float* x = gptr((const float*)src) + row * NU;
+        const VISTA_GLOBAL float* xm = gptr((const float*)src) + mrow * NU;
+#pragma unroll
+        for (int kk = 0; kk < R; ++kk) {
+            const int iu = g + G * kk;
+            v[kk] = make_float2(sg * (x[iu] + xm[(NU - iu) & (NU - 1)]), 0.f);
+        }
+    } else {
+        const VISTA_GLOBAL float2* x = gptr((const float2*)src) + row * NU;
+        const VISTA_GLOBAL float2* xm = gptr((const float2*)src) + mrow * NU;
+#pragma unroll
+        for (int kk = 0; kk < R; ++kk) {
+            const int iu = g + G * kk;
+            const float2 a = x[iu], b = xm[(NU - iu) & (NU - 1)];
+            v[kk] = make_float2(sg * (a.x + b.x), sg * (a.y - b.y));
+        }
+    }
+    dft_regs<LOGR>(v);
+    float2* mine = lds + r * (G * RP);
+#pragma unroll
+    for (int kp = 0; kp < R; ++kp) {
+        float t = (float)((g * kp) & (NU - 1)) * (1.f / (float)NU);    // exact
+        if (t > 0.5f) t -= 1.f;
+        float sn, cs;
+        sincos_turns(t, &sn, &cs);
+        mine[g * RP + kp] = cmul(v[bitrev<LOGR>(kp)], make_float2(cs, sn));
+    }
+    lds_barrier();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) v[s * G + gg] = mine[gg * RP + g + G * s];
+    }
+    if (k > nv / 2) return;
+    float2* dst = tmp + row * NU + g;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        dft_regs<LOGG>(v + s * G);
+#pragma unroll
+        for (int gp = 0; gp < G; ++gp) dst[G * s + R * gp] = v[s * G + bitrev<LOGG>(gp)];
+    }
+}
+
+// Column pass of the Hermitian path: a real transform of length nv = 2 M from the rows
+// H[0 .. M] of one column, as one complex transform of length M = G R.  Output row 2n is
+// Re z[n] and row 2n + 1 is Im z[n], with z the length-M inverse transform of
+//   Z[k] = E[k] + i O[k],  E[k] = H[k] + conj(H[M - k]),
+//   O[k] = (H[k] - conj(H[M - k])) e^{2 pi i k / nv}    (k < M)
+// (the even and the odd outputs are the length-M transforms of E and of O, both real).
+// Tiles, threads and the two-step split of the length-M transform are those of
+// k_image_cols_reg; thread (c, g) loads rows k = g + G kk and M - k of column c.
+template <int LOGG, int LOGR, int LOGC>
+__global__ void __launch_bounds__(1 << (LOGC + LOGG)) k_image_cols_herm(const float2* __restrict__ tmp,
+                                                                         const double* __restrict__ wsum,
+                                                                         float* __restrict__ out, int lognu,
+                                                                         int ntiles, float sign) {
+    constexpr int G = 1 << LOGG, R = 1 << LOGR, C = 1 << LOGC, M = G * R, NV = 2 * M, S = R / G;
+    static_assert(G <= R && R <= 32, "tile split");
+    __shared__ float2 lds[M * C];
+    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> LOGC;
+    const int nu = 1 << lognu, logtpc = lognu - LOGC;
+    const size_t plane = (size_t)nu * NV;
+    float2 v[R];
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const VISTA_GLOBAL float2* src = gptr(tmp) + (size_t)(tile >> logtpc) * plane +
+                                         ((size_t)(tile & ((1 << logtpc) - 1)) << LOGC) + c;
+#pragma unroll
+        for (int kk = 0; kk < R; ++kk) {
+            const int k = g + G * kk;
+            const float2 h = src[(size_t)k * nu], hm = src[(size_t)(M - k) * nu];
+            const float2 e = make_float2(h.x + hm.x, h.y - hm.y);             // H[k] + conj(H[M - k])
+            const float2 d = make_float2(h.x - hm.x, h.y + hm.y);             // H[k] - conj(H[M - k])
+            float sn, cs;
+            sincos_turns((float)k * (1.f / (float)NV), &sn, &cs);            // exact fraction, < 1/2
+            const float2 o = cmul(d, make_float2(cs, sn));
+            v[kk] = make_float2(e.x - o.y, e.y + o.x);                         // E + i O
+        }
+        dft_regs<LOGR>(v);
+#pragma unroll
+        for (int kp = 0; kp < R; ++kp) {
+            float t = (float)((g * kp) & (M - 1)) * (1.f / (float)M);      // exact
+            if (t > 0.5f) t -= 1.f;
+            float sn, cs;
+            sincos_turns(t, &sn, &cs);
+            lds[(kp * G + g) * C + c] = cmul(v[bitrev<LOGR>(kp)], make_float2(cs, sn));
+        }
+        lds_barrier();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) v[s * G + gg] = lds[((g + G * s) * G + gg) * C + c];
+        }
+        lds_barrier();
+        const int j = tile >> logtpc, p = ((tile & ((1 << logtpc) - 1)) << LOGC) + c;
+        const double wt = wsum[j];
+        const float inv = wt > 0.0 ? (float)(1.0 / wt) : 0.f;
+        VISTA_GLOBAL float* dst = (VISTA_GLOBAL float*)out + (size_t)j * plane + p;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            dft_regs<LOGG>(v + s * G);
+#pragma unroll
+            for (int gp = 0; gp < G; ++gp) {
+                const int n = g + G * s + R * gp;
+                const float2 z = v[s * G + bitrev<LOGG>(gp)];
+                const float sg = ((p + 2 * n) & 1) ? -sign : sign;            // centring, row 2n
+                dst[(size_t)(2 * n) * nu] = sg * z.x * inv;
+                dst[(size_t)(2 * n + 1) * nu] = -sg * z.y * inv;              // row 2n + 1
+            }
+        }
+    }
+}
+
 // Blocks of a persistent launch: as many as fit on the device at once, at most `ntiles`.
 template <typename K>
 int persistent_blocks(K kernel, int threads, size_t lds, int ntiles) {
@@ -455,8 +596,34 @@ hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, 
         default: break;
     }
     if (nv < rrow_rows) rrow_c = rrow_r = nullptr;
+    // the Hermitian path (rows 0 .. nv/2 staged, a real column transform), for register row
+    // passes and 128 <= nv <= 2048: the same tiles, on the half-length column transform
+    void (*hrow_c)(const void*, float2*, int) = nullptr;
+    void (*hrow_r)(const void*, float2*, int) = nullptr;
+    switch (lognu) {
+        case 6: hrow_c = k_image_rows_herm<3, 3, 5, false>; hrow_r = k_image_rows_herm<3, 3, 5, true>; break;
+        case 7: hrow_c = k_image_rows_herm<3, 4, 5, false>; hrow_r = k_image_rows_herm<3, 4, 5, true>; break;
+        case 8: hrow_c = k_image_rows_herm<4, 4, 4, false>; hrow_r = k_image_rows_herm<4, 4, 4, true>; break;
+        case 9: hrow_c = k_image_rows_herm<4, 5, 4, false>; hrow_r = k_image_rows_herm<4, 5, 4, true>; break;
+        case 10: hrow_c = k_image_rows_herm<5, 5, 3, false>; hrow_r = k_image_rows_herm<5, 5, 3, true>; break;
+        default: break;
+    }
+    void (*hcol_k)(const float2*, const double*, float*, int, int, float) = nullptr;
+    int hcol_threads = 0, hcol_cols = 0;
+    switch (lognv) {
+        case 7: hcol_k = k_image_cols_herm<3, 3, 5>; hcol_cols = 32; hcol_threads = 32 << 3; break;
+        case 8: hcol_k = k_image_cols_herm<3, 4, 5>; hcol_cols = 32; hcol_threads = 32 << 3; break;
+        case 9: hcol_k = k_image_cols_herm<4, 4, 5>; hcol_cols = 32; hcol_threads = 32 << 4; break;
+        case 10: hcol_k = k_image_cols_herm<4, 5, 5>; hcol_cols = 32; hcol_threads = 32 << 4; break;
+        case 11: hcol_k = k_image_cols_herm<5, 5, 4>; hcol_cols = 16; hcol_threads = 16 << 5; break;
+        default: break;
+    }
+    const bool herm = hrow_c && hcol_k && nu >= hcol_cols && nv / 2 >= rrow_rows;
     auto rows_pass = [&](const void* src, bool real, int nc) {
-        if (rrow_c) {
+        if (herm) {
+            hipLaunchKernelGGL(real ? hrow_r : hrow_c, dim3(nv / 2 / rrow_rows + 1, nc), dim3(kRowThreads), 0, stream,
+                               src, tmp, lognv);
+        } else if (rrow_c) {
             hipLaunchKernelGGL(real ? rrow_r : rrow_c, dim3(nv / rrow_rows, nc), dim3(kRowThreads), 0, stream, src, tmp,
                                lognv);
         } else if (real) {
@@ -468,7 +635,11 @@ hipError_t launch_image(const void* sum_wvis, const float* sum_w, float* image, 
         }
     };
     auto columns = [&](const double* ws, float* dst, int nc) {
-        if (reg_k) {
+        if (herm) {
+            const int nct = (int)((int64_t)nc * (nu / hcol_cols));
+            hipLaunchKernelGGL(hcol_k, dim3(persistent_blocks(hcol_k, hcol_threads, 0, nct)), dim3(hcol_threads), 0,
+                               stream, tmp, ws, dst, lognu, nct, sign);
+        } else if (reg_k) {
             const int nct = (int)((int64_t)nc * (nu / reg_cols));
             hipLaunchKernelGGL(reg_k, dim3(persistent_blocks(reg_k, reg_threads, 0, nct)), dim3(reg_threads), 0,
                                stream, tmp, ws, dst, lognu, nct, sign);

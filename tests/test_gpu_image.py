@@ -64,9 +64,11 @@ def test_channel_count_at_its_limit():
 
 # (nv, nu): transforms of 64 to 1024 points are held in registers when a tile fits (columns:
 # nu >= 32, or 16 at nv = 1024; rows: nv >= 8 to 32 rows by length), the rest use the LDS
-# Stockham passes; these shapes take each length both ways
+# Stockham passes; these shapes take each length both ways.  With register rows (64 <= nu
+# <= 1024) and 128 <= nv <= 2048 the real part is formed from half the staging (the
+# Hermitian path): (128, 64) and (256, 256) here, more in the sampled tests below
 @pytest.mark.parametrize("shape", [(2, 2), (2, 8), (16, 4), (32, 32), (16, 64), (64, 8), (64, 128), (128, 16),
-                                   (128, 32), (256, 256), (512, 16), (512, 32)])
+                                   (128, 32), (256, 256), (512, 16), (512, 32), (128, 64)])
 def test_random_grids_match_oracle(shape):
     nv, nu = shape
     rng = np.random.default_rng(nv * 1000 + nu)
@@ -137,9 +139,11 @@ def _sampled(S, W, img, beam, rng, npix):
 
 
 @pytest.mark.parametrize("shape,nchan", [((4, 4096), 3), ((4096, 2), 3), ((2048, 8), 2), ((1024, 64), 3),
-                                         ((64, 1024), 3), ((1024, 1024), 2), ((4096, 4096), 1)])
+                                         ((64, 1024), 3), ((1024, 1024), 2), ((4096, 4096), 1), ((2048, 64), 2),
+                                         ((2048, 1024), 1), ((128, 512), 2), ((256, 1024), 2), ((512, 128), 2)])
 def test_longest_axes_sampled_pixels(shape, nchan):
-    """Axes up to the 4096 limit, where one row or one column fills a whole tile."""
+    """Axes up to the 4096 limit, where one row or one column fills a whole tile; and
+    sizes of the Hermitian path (register rows, 128 <= nv <= 2048) up to its longest."""
     nv, nu = shape
     rng = np.random.default_rng(nv + 7 * nu)
     S = (rng.normal(size=(nchan, nv, nu)) + 1j * rng.normal(size=(nchan, nv, nu))).astype(np.complex64)
