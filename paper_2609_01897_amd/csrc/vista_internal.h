@@ -148,8 +148,8 @@ struct RebinBlock {
 constexpr int kModeAtomic = 0;
 constexpr int kModeOrdered = 1;
 
-// Kernel launchers (vista_kernels.hip).  All enqueue on `stream` and return the first
-// HIP error.
+// Kernel launchers (vista_kernels.hip, vista_accum.hip).  All enqueue on `stream` and
+// return the first HIP error.
 // Binning pass over every row of the launch.  emit == 0 counts the records of each row
 // into seg_count and adds the outside-uv samples to the stacks' stats; emit == 1 writes
 // them at seg_off: key = global (tile, block) unit, value = row << 32 | k_lo << 16 | k_hi,
@@ -166,7 +166,7 @@ hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_
 // sorted records before i (pre[nrec] = total); lens is nrec u32 of scratch.
 hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, int64_t nrec_cap, uint32_t* lens,
                                 uint64_t* pre, uint64_t* sums, hipStream_t stream);
-// Work list of the packed accumulation (keys/vals: nunits entries each, sorted in place;
+// Work list of the accumulation (keys/vals: nunits entries each, sorted in place;
 // vals end as the unit ids).  One stack in the launch (dL->nstacks): units above four times
 // the mean channel-sample count first, largest first, then the rest in unit order; several
 // stacks: all units by descending channel-sample count.
@@ -185,9 +185,11 @@ int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, 
 bool accum_packed_shape_supported(int tu, int tv, int jc, int waves, int acc32);
 int accum_packed_shape_list(int acc32, int* tu, int* tv, int* jc, int cap);
 size_t accum_packed_lds_bytes(int tu, int tv, int jc, int acc32);
-// The accumulation over the work list `order` (global unit ids); `grid` workgroups of
-// `waves` wavefronts pull list entries from *counter (zeroed first).
-// npol == 2 when every target of the launch has two polarisations (specialised path).
+// The ordered accumulation (deterministic modes) over the work list `order` (global unit
+// ids); `grid` workgroups of `waves` wavefronts pull list entries from *counter (zeroed
+// first).  It reads the count pass's row contexts and row targets (L.rowctx,
+// L.row_target).  npol == 2 when every target of the launch has two polarisations and row
+// weights (specialised path).
 hipError_t launch_accum_impl(const LaunchDesc& L, const LaunchDesc* dL, const uint64_t* order,
                              uint32_t* counter, const uint32_t* unit_off,
                              const uint64_t* recs, int grid, int waves, int npol, hipStream_t stream);
@@ -217,7 +219,8 @@ hipError_t launch_debug_rotate(const DevTarget* t, float2* out, int64_t nrow, in
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 // *flag |= 1 when a and b differ anywhere in [0, n) (the caller zeroes *flag).
 hipError_t launch_diff_u32(const uint32_t* a, const uint32_t* b, int64_t n, uint32_t* flag, hipStream_t stream);
-// Launch shapes the ordered kernel is built for, in order.
+// Launch shapes of the accumulation of `mode`, in order: the ordered kernel's, or for the
+// atomic mode the packed kernel's FP64-sum shapes.
 int accum_shape_list(int mode, int* tu, int* tv, int* jc, int cap);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 // Dirty image of every channel of a stacked grid (vista_image.hip): nu, nv powers of two
