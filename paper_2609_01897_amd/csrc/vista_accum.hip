@@ -708,9 +708,10 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 // congruent to p modulo P, which also puts the same channel of consecutive records (rows
 // of one baseline, which often share a cell) in different phases.  Lanes of one phase from
 // different rows can still meet in a cell; they take turns: every waiting lane bids for
-// its cells with an LDS max of its lane id, the lanes that hold every cell they bid for
-// add, the others bid again.  The order of the additions to a cell thus depends on the
-// records and lane ids only.  Sums are FP32 with a Kahan compensation per addition (KAHAN)
+// its cells with an LDS max of a stamp (the wavefront's turn count, then its lane id), the
+// lanes that hold every cell they bid for add, the others bid again.  A turn's stamps
+// exceed every earlier turn's, so stale bids lose without being cleared.  The order of the
+// additions to a cell thus depends on the records and lane ids only.  Sums are FP32 with a Kahan compensation per addition (KAHAN)
 // or FP64, read and written plainly.
 
 // Keeps the compiler from moving LDS accesses across this point: the lanes of a wavefront
@@ -746,7 +747,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
     __shared__ Sri s_ri[NC];
     __shared__ Sw s_w[NC];
     __shared__ uint32_t s_n[NC];
-    __shared__ uint32_t s_bid[NC];        // highest lane id (+1) bidding for a cell; 0 between rounds
+    __shared__ uint32_t s_bid[NC];        // highest stamp bid for a cell; 0 at a unit's start
     __shared__ uint32_t s_unit;
 
     const LaunchDesc& L = *Lp;
@@ -760,9 +761,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
     const VISTA_GLOBAL float* f1_all = gptr(L.f1_all);
     const int phase_fp32 = L.phase_fp32;
     const int32_t jsub = L.jsub;
-    const uint32_t id = (uint32_t)lane + 1u;
 
-    for (int i = threadIdx.x; i < NC; i += blockDim.x) s_bid[i] = 0u;
     for (;;) {
         if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
         __syncthreads();
@@ -786,6 +785,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
             s_ri[i] = Sri{};
             s_w[i] = Sw{};
             s_n[i] = 0u;
+            s_bid[i] = 0u;
         }
         __syncthreads();
 
@@ -798,6 +798,9 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         // this lane's statistics of the unit: live, flagged and used polarisations of the
         // samples whose first rest channel is in the slice, and contributions added
         uint32_t st_live = 0, st_flag = 0, st_used = 0, st_contrib = 0;
+        // turns of this wavefront in this unit: a turn's bids carry (turn << 6 | lane) + 1,
+        // above every earlier turn's, so that earlier bids need no clearing
+        uint32_t turns = 0;
 
         // one addition of (f pr, f pi, f q) and count n to a cell's state in registers
         auto accum = [&](Sri& ri, Sw& w, uint32_t& cnt, float f, float pr, float pi, float q, uint32_t n)
@@ -995,6 +998,17 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                     bool pend = (a0 >= 0 || a1 >= 0) && ph_l == ph;
                     // each turn the highest waiting lane adds, so 64 turns always suffice
                     for (int turn = 0; turn < kWave && __ballot(pend); ++turn) {
+                        if (turns == (1u << 25)) {
+                            // the stamps would wrap: clear this slice's bids and start again
+                            for (int c = lane; c < TU * TV * JP; c += kWave) {
+                                const int j = c % JP + jb0;
+                                if (j >= js0 && j < js1) s_bid[c] = 0u;
+                            }
+                            lds_order();
+                            turns = 0;
+                        }
+                        ++turns;
+                        const uint32_t id = (turns << 6 | (uint32_t)lane) + 1u;
                         if (pend) {
                             if (a0 >= 0) atomicMax(&s_bid[a0], id);
                             if (a1 >= 0) atomicMax(&s_bid[a1], id);
@@ -1004,10 +1018,6 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                         if (pend) win = (a0 < 0 || s_bid[a0] == id) && (a1 < 0 || s_bid[a1] == id);
                         lds_order();
                         if (win) add2(a0, a1, s.f0, s.f1, pr, pi, q, n);
-                        if (pend) {
-                            if (a0 >= 0) s_bid[a0] = 0u;
-                            if (a1 >= 0) s_bid[a1] = 0u;
-                        }
                         pend = pend && !win;
                         lds_order();
                     }
