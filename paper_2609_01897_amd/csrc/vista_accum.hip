@@ -1283,15 +1283,23 @@ int accum_packed_max_blocks_per_cu(int tu, int tv, int jc, int waves, int npol, 
 
 // Launch shapes (tile_u, tile_v, jblock) of the ordered kernel: 32 B of LDS per cell (FP64
 // sums, or FP32 sums with their compensations; a count; a bid slot).
+// Small tiles first: at 32 B a cell, 2 x 2 x 64 and the other 8 KB shapes let sixteen
+// one-wavefront workgroups share a compute unit, each wavefront owning a whole block (no
+// wavefront walks records for channels another one adds); the larger shapes serve wider
+// workgroups.
 #define VISTA_ORDERED_SHAPES(X) \
-    X(8, 8, 64)                 \
-    X(16, 4, 64)                \
-    X(16, 8, 32)                \
+    X(2, 2, 64)                 \
+    X(2, 1, 128)                \
+    X(1, 2, 128)                \
+    X(1, 1, 256)                \
+    X(2, 2, 128)                \
+    X(2, 1, 256)                \
+    X(2, 2, 256)                \
+    X(4, 2, 256)                \
+    X(2, 2, 512)                \
+    X(4, 2, 512)                \
     X(8, 4, 128)                \
-    X(16, 2, 128)               \
-    X(4, 4, 256)                \
-    X(8, 2, 256)                \
-    X(4, 2, 512)
+    X(8, 8, 64)
 
 static size_t ordered_lds_bytes(int tu, int tv, int jc) { return (size_t)tu * tv * (jc + 1) * 32 + 16; }
 

@@ -481,7 +481,7 @@ static bool shape_ok(const Tuning& t, uint32_t flags) {
 static Tuning default_tuning(uint32_t flags) {
     Tuning t;
     if (flags & VISTA_F_DETERMINISTIC) {
-        t.tu = 4; t.tv = 2; t.jc = 512; t.waves = 16;  // ordered: 32-channel slices per wave
+        t.tu = 2; t.tv = 2; t.jc = 64; t.waves = 1;    // ordered: 16 one-wavefront workgroups a CU
     } else if (flags & VISTA_F_PLAIN_FP32) {
         t.tu = 8; t.tv = 4; t.jc = 288; t.waves = 16;  // FP32 tiles: 1.75 times the cells
     }
@@ -1212,9 +1212,12 @@ static void run_jobs_in(Workspace& ws, std::vector<StackJob>& jobs, const Tuning
 
 // ------------------------------------------------------------------------ autotuning
 
-// Candidate launch shapes of a mode: every (tile, block) shape the kernel is built for,
-// with 16 wavefronts per workgroup, and with 8 where two workgroups share a compute
-// unit's LDS.  The first candidate is the mode's default.
+// Candidate launch shapes of a mode: every (tile, block) shape the kernel is built for.
+// The packed kernel's come with 16 wavefronts per workgroup, and with 8 where two
+// workgroups share a compute unit's LDS.  The ordered kernel's come with the fewest
+// wavefronts (1, 2, 4, 8 or 16) whose workgroups, 16 wavefronts' worth, fit one compute
+// unit's LDS: every wavefront of a workgroup walks all of its unit's records, so fewer per
+// workgroup walk less at the same occupancy.  The first candidate is the mode's default.
 static std::vector<Tuning> tuning_candidates(uint32_t flags) {
     const int mode = (flags & VISTA_F_DETERMINISTIC) ? kModeOrdered : kModeAtomic;
     const int kahan = (flags & VISTA_F_KAHAN) ? 1 : 0;
@@ -1224,17 +1227,28 @@ static std::vector<Tuning> tuning_candidates(uint32_t flags) {
                                                : accum_shape_list(mode, tu, tv, jc, 64),
                            64);
     std::vector<Tuning> out{default_tuning(flags)};
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
+        if (mode == kModeOrdered) {
+            const size_t lds = accum_lds_bytes(tu[i], tv[i], jc[i], mode, kahan);
+            for (int waves : {1, 2, 4, 8, 16}) {
+                Tuning t;
+                t.tu = tu[i]; t.tv = tv[i]; t.jc = jc[i]; t.waves = waves;
+                if (lds * (16 / waves) > 160 * 1024 || !shape_ok(t, flags)) continue;
+                if (!(t.tu == out[0].tu && t.tv == out[0].tv && t.jc == out[0].jc && t.waves == out[0].waves))
+                    out.push_back(t);
+                break;
+            }
+            continue;
+        }
         for (int waves : {16, 8}) {
             Tuning t;
             t.tu = tu[i]; t.tv = tv[i]; t.jc = jc[i]; t.waves = waves;
             if (!shape_ok(t, flags)) continue;
-            const size_t lds = mode == kModeAtomic ? accum_packed_lds_bytes(t.tu, t.tv, t.jc, acc32)
-                                                   : accum_lds_bytes(t.tu, t.tv, t.jc, mode, kahan);
-            if (waves == 8 && lds > 80 * 1024) continue;
+            if (waves == 8 && accum_packed_lds_bytes(t.tu, t.tv, t.jc, acc32) > 80 * 1024) continue;
             if (t.tu == out[0].tu && t.tv == out[0].tv && t.jc == out[0].jc && t.waves == out[0].waves) continue;
             out.push_back(t);
         }
+    }
     return out;
 }
 

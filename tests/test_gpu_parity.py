@@ -275,7 +275,8 @@ def test_no_targets_gives_zero_grid():
 PACKED_SHAPES = [(8, 8, 64), (16, 4, 64), (16, 8, 32), (8, 4, 128), (16, 2, 128), (4, 4, 256), (8, 2, 256),
                  (4, 2, 512), (4, 4, 128), (8, 4, 64), (8, 2, 128), (4, 2, 256), (16, 2, 160), (8, 2, 320),
                  (8, 4, 160)]
-ORDERED_SHAPES = PACKED_SHAPES[:8]
+ORDERED_SHAPES = [(2, 2, 64), (2, 1, 128), (1, 2, 128), (1, 1, 256), (2, 2, 128), (2, 1, 256), (2, 2, 256),
+                  (4, 2, 256), (2, 2, 512), (4, 2, 512), (8, 4, 128), (8, 8, 64)]
 PACKED_SHAPES_F32 = [(8, 4, 288), (16, 4, 144), (8, 8, 144), (16, 2, 288), (4, 4, 576), (8, 2, 576), (16, 8, 64),
                      (8, 4, 128), (8, 4, 144), (16, 4, 64)]
 
@@ -314,10 +315,12 @@ def test_every_tile_shape_matches(shape, waves, small_case, lds_updates):
         compare(o, out, st=st)
 
 
-@pytest.mark.parametrize("waves", [4, 16])
+@pytest.mark.parametrize("waves", [1, 4, 16])
 @pytest.mark.parametrize("shape", ORDERED_SHAPES)
 def test_every_ordered_shape_matches(shape, waves, small_case):
-    """The deterministic form in every launch shape built for it, compensated and not."""
+    """The deterministic form in every launch shape built for it, compensated and not, with
+    one wavefront per workgroup (its default: the wavefront owns the whole block), four and
+    sixteen (slices of the block per wavefront)."""
     g, ds, o = small_case
     tu = dict(tile_u=shape[0], tile_v=shape[1], jblock=shape[2], waves=waves)
     for flags in (vista.F_DETERMINISTIC, vista.F_DETERMINISTIC | vista.F_KAHAN):
