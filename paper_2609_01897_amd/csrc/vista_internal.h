@@ -161,7 +161,8 @@ hipError_t launch_track(int64_t rows_cap, const LaunchDesc* dL, uint32_t* seg_co
 // unit_off[u] = first record of unit u in the sorted keys (u = 0..nunits).  Counts are
 // read from device memory (nrec_dev, nunits_dev); capacities size the grids.
 hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
-                               const int64_t* nunits_dev, uint32_t* unit_off, hipStream_t stream);
+                               const int64_t* nunits_dev, int64_t units_cap, uint32_t* unit_off,
+                               hipStream_t stream);
 // Per-record prefix of the records' channel counts: pre[i] = sum of (k_hi - k_lo) over the
 // sorted records before i (pre[nrec] = total); lens is nrec u32 of scratch.
 hipError_t launch_record_prefix(const uint64_t* recs, const int64_t* nrec_dev, int64_t nrec_cap, uint32_t* lens,

@@ -223,31 +223,25 @@ __global__ void __launch_bounds__(kTrackThreads) k_track(const LaunchDesc* __res
     }
 }
 
-// unit_off[u] = index of the first record of unit u (records sorted by unit).  Thread t
-// covers record positions 4t .. 4t + 3 (position nrec stands for the end) and reads their
-// keys with one 16-byte load where all four are records.
+// unit_off[u] = index of the first record of unit u, for u = 0 .. nunits (records sorted by
+// unit, so unit_off[nunits] = nrec): one lower-bound search of the sorted keys per unit.
+// Neighbouring units share the search's upper levels in cache, and a run of empty units
+// costs no more than occupied ones (a pass over the records that filled the gaps between
+// keys gave a whole run of empty units to one thread).  nunits <= units_cap.
 __global__ void k_unit_offsets(const uint32_t* __restrict__ keys, const int64_t* __restrict__ nrec_dev,
                                int64_t nrec_cap, const int64_t* __restrict__ nunits_dev,
                                uint32_t* __restrict__ off) {
     const int64_t nunits = *nunits_dev;
     const int64_t nrec = nrec_dev ? *nrec_dev : nrec_cap;
-    const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (i0 > nrec) return;
-    int64_t cur[4];
-    if (i0 + 4 <= nrec && ((uintptr_t)(keys + i0) & 15) == 0) {
-        const uint4 k4 = *(const uint4*)(keys + i0);
-        cur[0] = k4.x; cur[1] = k4.y; cur[2] = k4.z; cur[3] = k4.w;
-    } else {
-        for (int j = 0; j < 4; ++j) {
-            const int64_t i = i0 + j;
-            cur[j] = i < nrec ? (int64_t)keys[i] : nunits;
-        }
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > nunits) return;
+    int64_t lo = 0, hi = nrec;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)keys[mid] < u) lo = mid + 1;
+        else hi = mid;
     }
-    int64_t prev = (i0 == 0) ? -1 : (int64_t)keys[i0 - 1];
-    for (int j = 0; j < 4 && i0 + j <= nrec; ++j) {
-        for (int64_t t = prev + 1; t <= cur[j] && t <= nunits; ++t) off[t] = (uint32_t)(i0 + j);
-        prev = cur[j];
-    }
+    off[u] = (uint32_t)lo;
 }
 
 // Fills walk the array in grid strides: a dispatch covers fewer than 2^32 work-items, and
@@ -356,8 +350,9 @@ hipError_t launch_track(int64_t rows_cap, const LaunchDesc* dL, uint32_t* seg_co
 }
 
 hipError_t launch_unit_offsets(const uint32_t* sorted_keys, const int64_t* nrec_dev, int64_t nrec_cap,
-                               const int64_t* nunits_dev, uint32_t* unit_off, hipStream_t stream) {
-    int64_t n = (nrec_cap + 1 + 3) / 4;     // threads: four record positions each
+                               const int64_t* nunits_dev, int64_t units_cap, uint32_t* unit_off,
+                               hipStream_t stream) {
+    const int64_t n = units_cap + 1;        // threads: one per unit offset
     hipLaunchKernelGGL(k_unit_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sorted_keys,
                        nrec_dev, nrec_cap, nunits_dev, unit_off);
     return hipGetLastError();

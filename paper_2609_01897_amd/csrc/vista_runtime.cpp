@@ -985,7 +985,7 @@ class Launcher {
         int bits = 1;
         while (bits < 32 && (int64_t(1) << bits) < cap_.units) ++bits;
         check_launch(radix_sort_pairs(keys_, vals_, nrec_dev(), cap_.recs, bits, stmp_, s_), "sort");
-        check_launch(launch_unit_offsets(keys_, nrec_dev(), cap_.recs, nunits_dev(), unit_off_, s_), "unit offsets");
+        check_launch(launch_unit_offsets(keys_, nrec_dev(), cap_.recs, nunits_dev(), cap_.units, unit_off_, s_), "unit offsets");
         check_launch(launch_record_prefix(vals_, nrec_dev(), cap_.recs, lens_, pre_, psums_, s_), "record prefix");
         check_launch(launch_unit_order(d_L_, unit_off_, pre_, nunits_dev(), cap_.units, okeys_, order_, otmp_, s_),
                      "unit order");
