@@ -853,10 +853,10 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
             // ---- window: records wb .. wb + 63, one per lane, clipped to the slice
             const uint32_t nwin = min((uint32_t)kWave, re - wb);
             const bool v = (uint32_t)lane < nwin;
-            // a full window is taken in the order 17 q mod 64, so that records next to each
+            // a full window is taken in the order 25 q mod 64, so that records next to each
             // other in row order (often one baseline at consecutive times, in one cell) fall
             // in different chunks
-            const uint32_t q = nwin == (uint32_t)kWave ? (uint32_t)(lane * 17) & (kWave - 1) : (uint32_t)lane;
+            const uint32_t q = nwin == (uint32_t)kWave ? (uint32_t)(lane * 25) & (kWave - 1) : (uint32_t)lane;
             const uint64_t rec = v ? grecs[wb + q] : 0ull;
             const uint32_t g = (uint32_t)(rec >> 32);
             int32_t kin = (int32_t)((rec >> 16) & 0xffffu), kout = (int32_t)(rec & 0xffffu);
