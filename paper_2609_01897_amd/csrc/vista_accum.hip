@@ -710,9 +710,11 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 // different rows can still meet in a cell; they take turns: every waiting lane bids for
 // its cells with an LDS max of a stamp (the wavefront's turn count, then its lane id), the
 // lanes that hold every cell they bid for add, the others bid again.  A turn's stamps
-// exceed every earlier turn's, so stale bids lose without being cleared.  The order of the
-// additions to a cell thus depends on the records and lane ids only.  Sums are FP32 with a Kahan compensation per addition (KAHAN)
-// or FP64, read and written plainly.
+// exceed every earlier turn's, so stale bids lose without being cleared, and a turn reads
+// the bids and the cells' state together (a winner holds its cells alone that turn, so
+// what it read is current): one LDS round trip a turn.  The order of the additions to a
+// cell thus depends on the records and lane ids only.  Sums are FP32 with a Kahan
+// compensation per addition (KAHAN) or FP64, read and written plainly.
 
 // Keeps the compiler from moving LDS accesses across this point: the lanes of a wavefront
 // read what other lanes of it wrote just before (the LDS serves one wavefront's
@@ -744,10 +746,15 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
     // compensation) and (w, its compensation) in FP32; else (re, im) and w in FP64
     using Sri = typename std::conditional<KAHAN, float4, double2>::type;
     using Sw = typename std::conditional<KAHAN, float2, double>::type;
+    // the rest of a cell's state in one 16-byte access: w, the count, and the highest stamp
+    // bid for the cell (0 at a unit's start)
+    struct alignas(16) Cw {
+        Sw w;
+        uint32_t n, bid;
+    };
+    static_assert(sizeof(Cw) == 16, "one 16-byte LDS access per cell");
     __shared__ Sri s_ri[NC];
-    __shared__ Sw s_w[NC];
-    __shared__ uint32_t s_n[NC];
-    __shared__ uint32_t s_bid[NC];        // highest stamp bid for a cell; 0 at a unit's start
+    __shared__ Cw s_c[NC];
     __shared__ uint32_t s_unit;
 
     const LaunchDesc& L = *Lp;
@@ -783,9 +790,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
 
         for (int i = threadIdx.x; i < NC; i += blockDim.x) {
             s_ri[i] = Sri{};
-            s_w[i] = Sw{};
-            s_n[i] = 0u;
-            s_bid[i] = 0u;
+            s_c[i] = Cw{};
         }
         __syncthreads();
 
@@ -824,29 +829,11 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
         // one addition to cell cc; no other lane writes cc meanwhile
         auto add = [&](int cc, float f, float pr, float pi, float q, uint32_t n) __attribute__((always_inline)) {
             Sri ri = s_ri[cc];
-            Sw w = s_w[cc];
-            uint32_t cnt = s_n[cc];
-            accum(ri, w, cnt, f, pr, pi, q, n);
+            Cw c = s_c[cc];
+            accum(ri, c.w, c.n, f, pr, pi, q, n);
             s_ri[cc] = ri;
-            s_w[cc] = w;
-            s_n[cc] = cnt;
+            s_c[cc] = c;
             st_contrib += n;
-        };
-        // a lane's additions to its two cells c0 and c1 (< 0: none), which differ: every read
-        // is issued before any write, so the pair costs one LDS round trip
-        auto add2 = [&](int c0, int c1, float f0, float f1, float pr, float pi, float q, uint32_t n)
-                        __attribute__((always_inline)) {
-            const bool h0 = c0 >= 0, h1 = c1 >= 0;
-            Sri ri0{}, ri1{};
-            Sw w0{}, w1{};
-            uint32_t n0 = 0u, n1 = 0u;
-            if (h0) { ri0 = s_ri[c0]; w0 = s_w[c0]; n0 = s_n[c0]; }
-            if (h1) { ri1 = s_ri[c1]; w1 = s_w[c1]; n1 = s_n[c1]; }
-            accum(ri0, w0, n0, f0, pr, pi, q, n);
-            accum(ri1, w1, n1, f1, pr, pi, q, n);
-            if (h0) { s_ri[c0] = ri0; s_w[c0] = w0; s_n[c0] = n0; }
-            if (h1) { s_ri[c1] = ri1; s_w[c1] = w1; s_n[c1] = n1; }
-            st_contrib += (h0 ? n : 0u) + (h1 ? n : 0u);
         };
 
         for (uint32_t wb = rb; js0 < js1 && wb < re; wb += (uint32_t)kWave) {
@@ -994,30 +981,48 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                 // record fewer than nphw apart get different phases; so do the same channel
                 // of consecutive records (rows of one baseline often share a cell)
                 const int32_t ph_l = (ci + x.rec) % nphw;
+                // a lane with one cell bids for it twice (a max with the same stamp changes
+                // nothing); a lane with none reads cell 0 and never bids
+                const int b0 = a0 >= 0 ? a0 : max(a1, 0), b1 = a1 >= 0 ? a1 : max(a0, 0);
                 for (int32_t ph = 0; ph < nphw; ++ph) {
                     bool pend = (a0 >= 0 || a1 >= 0) && ph_l == ph;
+                    if (turns >= (1u << 25)) {
+                        // the stamps would wrap within this phase's 64 turns: clear this
+                        // wavefront's bids and start again
+                        for (int c = lane; c < NC; c += kWave) {
+                            const int j = c % JP + jb0;
+                            if (j >= js0 && j < js1) s_c[c].bid = 0u;
+                        }
+                        lds_order();
+                        turns = 0;
+                    }
                     // each turn the highest waiting lane adds, so 64 turns always suffice
                     for (int turn = 0; turn < kWave && __ballot(pend); ++turn) {
-                        if (turns == (1u << 25)) {
-                            // the stamps would wrap: clear this slice's bids and start again
-                            for (int c = lane; c < TU * TV * JP; c += kWave) {
-                                const int j = c % JP + jb0;
-                                if (j >= js0 && j < js1) s_bid[c] = 0u;
-                            }
-                            lds_order();
-                            turns = 0;
-                        }
                         ++turns;
                         const uint32_t id = (turns << 6 | (uint32_t)lane) + 1u;
                         if (pend) {
-                            if (a0 >= 0) atomicMax(&s_bid[a0], id);
-                            if (a1 >= 0) atomicMax(&s_bid[a1], id);
+                            atomicMax(&s_c[b0].bid, id);
+                            atomicMax(&s_c[b1].bid, id);
                         }
                         lds_order();
-                        bool win = false;
-                        if (pend) win = (a0 < 0 || s_bid[a0] == id) && (a1 < 0 || s_bid[a1] == id);
+                        // the cells' state is read with the bids: a winner holds its cells
+                        // alone this turn, so what it read is current
+                        Sri ri0 = s_ri[b0], ri1 = s_ri[b1];
+                        Cw c0 = s_c[b0], c1 = s_c[b1];
+                        const bool win = pend && c0.bid == id && c1.bid == id;
                         lds_order();
-                        if (win) add2(a0, a1, s.f0, s.f1, pr, pi, q, n);
+                        if (win) {
+                            const bool h0 = a0 >= 0, h1 = a1 >= 0;
+                            if (h0) {
+                                accum(ri0, c0.w, c0.n, s.f0, pr, pi, q, n);
+                                s_ri[a0] = ri0; s_c[a0] = c0;
+                            }
+                            if (h1) {
+                                accum(ri1, c1.w, c1.n, s.f1, pr, pi, q, n);
+                                s_ri[a1] = ri1; s_c[a1] = c1;
+                            }
+                            st_contrib += (h0 ? n : 0u) + (h1 ? n : 0u);
+                        }
                         pend = pend && !win;
                         lds_order();
                     }
@@ -1079,7 +1084,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                                 [&](int c, double& dre, double& dim, double& dw, uint32_t& n)
                                     __attribute__((always_inline)) {
             const Sri ri = s_ri[c];
-            const Sw w = s_w[c];
+            const Sw w = s_c[c].w;
             if constexpr (KAHAN) {
                 dre = (double)ri.x - (double)ri.y;
                 dim = (double)ri.z - (double)ri.w;
@@ -1087,7 +1092,7 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
             } else {
                 dre = ri.x; dim = ri.y; dw = w;
             }
-            n = s_n[c];
+            n = s_c[c].n;
         });
         __syncthreads();
     }
