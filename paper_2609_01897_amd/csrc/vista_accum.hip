@@ -712,8 +712,10 @@ __global__ void __launch_bounds__(1024, 4) k_accum_packed(const LaunchDesc* __re
 // lanes that hold every cell they bid for add, the others bid again.  A turn's stamps
 // exceed every earlier turn's, so stale bids lose without being cleared, and a turn reads
 // the bids and the cells' state together (a winner holds its cells alone that turn, so
-// what it read is current): one LDS round trip a turn.  The order of the additions to a
-// cell thus depends on the records and lane ids only.  Sums are FP32 with a Kahan
+// what it read is current): one LDS round trip a turn.  Where channels are fine (long runs
+// of lanes with the same cells), each run is summed first in lane order and only its last
+// lane bids, in one phase.  The order of the additions to a cell thus depends on the
+// records and lane ids only.  Sums are FP32 with a Kahan
 // compensation per addition (KAHAN) or FP64, read and written plainly.
 
 // Keeps the compiler from moving LDS accesses across this point: the lanes of a wavefront
@@ -746,6 +748,9 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
     // compensation) and (w, its compensation) in FP32; else (re, im) and w in FP64
     using Sri = typename std::conditional<KAHAN, float4, double2>::type;
     using Sw = typename std::conditional<KAHAN, float2, double>::type;
+    // a lane's terms: FP32 products (KAHAN), else exact FP64 products
+    using AccR = typename std::conditional<KAHAN, float, double>::type;
+    static_assert(NC < (1 << 13) - 1, "two cell indices form one run key");
     // the rest of a cell's state in one 16-byte access: w, the count, and the highest stamp
     // bid for the cell (0 at a unit's start)
     struct alignas(16) Cw {
@@ -823,6 +828,25 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                 ri.x += (double)f * (double)pr;     // exact products, one rounding each
                 ri.y += (double)f * (double)pi;
                 w += (double)f * (double)q;
+            }
+            cnt += n;
+        };
+        // one addition of precomputed terms (vr, vi, vq) and count n to a cell's state
+        auto accumv = [&](Sri& ri, Sw& w, uint32_t& cnt, AccR vr, AccR vi, AccR vq, uint32_t n)
+                          __attribute__((always_inline)) {
+            if constexpr (KAHAN) {
+                auto kadd = [](float& sum, float& comp, float x) __attribute__((always_inline)) {
+                    const float y = x - comp, t = sum + y;
+                    comp = (t - sum) - y;
+                    sum = t;
+                };
+                kadd(ri.x, ri.y, vr);
+                kadd(ri.z, ri.w, vi);
+                kadd(w.x, w.y, vq);
+            } else {
+                ri.x += vr;
+                ri.y += vi;
+                w += vq;
             }
             cnt += n;
         };
@@ -977,15 +1001,57 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                 const int cell = (lv * TU + lu) * JP - jb0;
                 const int a0 = (live_add && j0 >= js0 && j0 < js1) ? cell + j0 : -1;
                 const int a1 = (live_add && nj > 1 && j0 + 1 >= js0 && j0 + 1 < js1) ? cell + j0 + 1 : -1;
+                // the lane's terms for its two cells
+                AccR r0 = 0, i0 = 0, q0 = 0, r1 = 0, i1 = 0, q1 = 0;
+                uint32_t nn = n;
+                if (a0 >= 0) { r0 = (AccR)s.f0 * (AccR)pr; i0 = (AccR)s.f0 * (AccR)pi; q0 = (AccR)s.f0 * (AccR)q; }
+                if (a1 >= 0) { r1 = (AccR)s.f1 * (AccR)pr; i1 = (AccR)s.f1 * (AccR)pi; q1 = (AccR)s.f1 * (AccR)q; }
+                bool mine = a0 >= 0 || a1 >= 0;
                 // phase: channel plus window lane of the record, modulo nphw.  Channels of one
                 // record fewer than nphw apart get different phases; so do the same channel
                 // of consecutive records (rows of one baseline often share a cell)
-                const int32_t ph_l = (ci + x.rec) % nphw;
+                int32_t ph_l = (ci + x.rec) % nphw, nph_c = nphw;
+                // fine channels: neighbouring lanes share cells in long runs, which phases
+                // would take one lane at a time.  Where the chunk's runs of lanes with the same
+                // two cells are 4 lanes long or more on average (a choice uniform over the
+                // wavefront), each run is summed first, in lane order (a segmented scan: the
+                // run's last lane ends with its total), and only that lane bids, in one phase;
+                // the bids order runs that share a cell
+                const int key = mine ? ((a0 + 1) << 13 | (a1 + 1)) : -1;
+                uint64_t act = 0, heads = 0;
+                if (nphw > kOrdPhases) {
+                    const int prev = __shfl_up(key, 1, kWave);
+                    act = __ballot(key >= 0);
+                    heads = __ballot(key >= 0 && (lane == 0 || prev != key));
+                }
+                if (act != 0 && __popcll(heads) * 4 <= __popcll(act)) {
+                    const uint64_t upto = heads & ((2ull << lane) - 1ull);
+                    const int start = upto ? 63 - (int)__clzll(upto) : lane;
+                    const int span = key >= 0 ? lane - start : -1;
+                    const int c16 = lane & 15;
+                    uint32_t nx = 0u;
+                    scan_dpp<0x111, 0xf>(r0, i0, q0, nn, span >= 1);
+                    scan_dpp<0x111, 0xf>(r1, i1, q1, nx, span >= 1);
+                    scan_dpp<0x112, 0xf>(r0, i0, q0, nn, span >= 2);
+                    scan_dpp<0x112, 0xf>(r1, i1, q1, nx, span >= 2);
+                    scan_dpp<0x114, 0xf>(r0, i0, q0, nn, span >= 4);
+                    scan_dpp<0x114, 0xf>(r1, i1, q1, nx, span >= 4);
+                    scan_dpp<0x118, 0xf>(r0, i0, q0, nn, span >= 8);
+                    scan_dpp<0x118, 0xf>(r1, i1, q1, nx, span >= 8);
+                    scan_dpp<0x142, 0xa>(r0, i0, q0, nn, span >= c16 + 1);
+                    scan_dpp<0x142, 0xa>(r1, i1, q1, nx, span >= c16 + 1);
+                    scan_dpp<0x143, 0xc>(r0, i0, q0, nn, span >= lane - 31);
+                    scan_dpp<0x143, 0xc>(r1, i1, q1, nx, span >= lane - 31);
+                    const uint64_t ends = heads | ~act;
+                    mine = key >= 0 && (lane == kWave - 1 || ((ends >> (lane + 1)) & 1ull));
+                    ph_l = 0;
+                    nph_c = 1;
+                }
                 // a lane with one cell bids for it twice (a max with the same stamp changes
                 // nothing); a lane with none reads cell 0 and never bids
                 const int b0 = a0 >= 0 ? a0 : max(a1, 0), b1 = a1 >= 0 ? a1 : max(a0, 0);
-                for (int32_t ph = 0; ph < nphw; ++ph) {
-                    bool pend = (a0 >= 0 || a1 >= 0) && ph_l == ph;
+                for (int32_t ph = 0; ph < nph_c; ++ph) {
+                    bool pend = mine && ph_l == ph;
                     if (turns >= (1u << 25)) {
                         // the stamps would wrap within this phase's 64 turns: clear this
                         // wavefront's bids and start again
@@ -1014,14 +1080,14 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                         if (win) {
                             const bool h0 = a0 >= 0, h1 = a1 >= 0;
                             if (h0) {
-                                accum(ri0, c0.w, c0.n, s.f0, pr, pi, q, n);
+                                accumv(ri0, c0.w, c0.n, r0, i0, q0, nn);
                                 s_ri[a0] = ri0; s_c[a0] = c0;
                             }
                             if (h1) {
-                                accum(ri1, c1.w, c1.n, s.f1, pr, pi, q, n);
+                                accumv(ri1, c1.w, c1.n, r1, i1, q1, nn);
                                 s_ri[a1] = ri1; s_c[a1] = c1;
                             }
-                            st_contrib += (h0 ? n : 0u) + (h1 ? n : 0u);
+                            st_contrib += (h0 ? nn : 0u) + (h1 ? nn : 0u);
                         }
                         pend = pend && !win;
                         lds_order();
