@@ -1012,14 +1012,14 @@ __global__ void __launch_bounds__(1024, 4) k_accum_ordered(const LaunchDesc* __r
                 // of consecutive records (rows of one baseline often share a cell)
                 int32_t ph_l = (ci + x.rec) % nphw, nph_c = nphw;
                 // fine channels: neighbouring lanes share cells in long runs, which phases
-                // would take one lane at a time.  Where the chunk's runs of lanes with the same
-                // two cells are 4 lanes long or more on average (a choice uniform over the
-                // wavefront), each run is summed first, in lane order (a segmented scan: the
+                // would take one lane at a time.  Where the window has more than four phases
+                // and the chunk's runs of lanes with the same two cells are 4 lanes long or
+                // more on average (a choice uniform over the wavefront), each run is summed first, in lane order (a segmented scan: the
                 // run's last lane ends with its total), and only that lane bids, in one phase;
                 // the bids order runs that share a cell
                 const int key = mine ? ((a0 + 1) << 13 | (a1 + 1)) : -1;
                 uint64_t act = 0, heads = 0;
-                if (nphw > kOrdPhases) {
+                if (nphw > 4) {
                     const int prev = __shfl_up(key, 1, kWave);
                     act = __ballot(key >= 0);
                     heads = __ballot(key >= 0 && (lane == 0 || prev != key));
