@@ -380,6 +380,23 @@ def test_deterministic_mode_is_bit_identical():
             assert np.array_equal(out[k].view(np.uint8), ref[k].view(np.uint8))
 
 
+@pytest.mark.parametrize("flags", [vista.F_DETERMINISTIC, vista.F_DETERMINISTIC | vista.F_KAHAN], ids=["fp64", "kahan"])
+def test_deterministic_fine_channels_are_bit_identical(flags):
+    """Fine channels (thousands of input channels per rest channel), where the ordered kernel
+    sums each run of lanes with the same cells before one bid per run: the same bits from
+    run to run, and the oracle's sums."""
+    cfg = synth.config("small")
+    g = synth.make_grid(cfg)
+    hs = [synth.make_target(cfg, 1, nchan=65535, n_int=2), synth.make_target(cfg, 2, nchan=20000, n_int=3)]
+    ds = [h.to("cuda") for h in hs]
+    ref, st = gpu_stack(g, ds, flags=flags)
+    compare(oracle.stack(g, hs), ref, st=st)
+    for _ in range(3):
+        out, _ = gpu_stack(g, ds, flags=flags)
+        for k in ("sum_wvis", "sum_w", "count"):
+            assert np.array_equal(out[k].view(np.uint8), ref[k].view(np.uint8))
+
+
 @pytest.mark.parametrize("flags", ["kahan", "deterministic_kahan"])
 def test_kahan_fp64_outputs(flags):
     """The FP64 outputs (FP64 tile sums, or s - c of the compensated FP32 tile sums) are
