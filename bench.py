@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = "stacked vis·chan·pol/s + HBM GB/s vs peak; batched/compensated vs plain speedup"
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, AMD public specification
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "accum_c2_counters.json")
+PROFILE_ORDERED = os.path.join(ROOT, "profiles", "ordered_c2_counters.json")
 PROFILE_REBIN = os.path.join(ROOT, "profiles", "rebin_c2_counters.json")
 PROFILE_BATCHED = os.path.join(ROOT, "profiles", "batched_c4_counters.json")
 PROFILE_IMAGE = os.path.join(ROOT, "profiles", "image_c2_counters.json")
@@ -73,11 +74,12 @@ def roofline(nbytes, ms, traffic=None):
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic}
 
 
-def counter_traffic(config_name, shape):
-    """Counter-measured HBM bytes of one accumulation launch, if the committed summary was
-    taken on the current kernel source, on this workload and in this launch shape."""
+def counter_traffic(config_name, shape, path=None):
+    """Counter-measured HBM bytes of one accumulation launch, if the committed summary (the
+    packed kernel's unless `path` names another) was taken on the current kernel source, on
+    this workload and in this launch shape."""
     try:
-        d = json.load(open(PROFILE_COUNTERS))
+        d = json.load(open(path or PROFILE_COUNTERS))
         h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         want = {k: int(shape[k]) for k in ("tile_u", "tile_v", "jblock", "waves")} if shape else None
         if d.get("kernel_sha256") == h and d.get("config") == config_name and d.get("launch_shape") == want:
@@ -330,7 +332,7 @@ def stack_step(grid, targets, flags, tuning, out):
 FORMS_SLAB = (432, 528)     # 96 rest channels around the line, reached by every target
 
 
-def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps=3, autotune=True):
+def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps=3, autotune=True, config_name="c2"):
     """The c2 workload in the plain FP32 form (FP32 per-tile sums) and the deterministic
     form (fixed-order compensated FP32 per-tile sums), timed on all targets, each in the
     launch shape the autotuner picks for it (as the main step's compensated form is); the
@@ -354,8 +356,9 @@ def forms_leg(targets, grid, nbytes, ref, ref_targets, compensated_tuning, steps
                 s.close()
                 log("form %s: autotuned launch shape %s in %.1f s" % (name, tuning, time.perf_counter() - t0))
             ms, acc_ms, (st, tim) = timed_steps(stack_step(grid, targets, flags, tuning, out), steps)
+            traffic = counter_traffic(config_name, tuning, PROFILE_ORDERED) if name == "deterministic" else None
             rec.update(ms_per_step=ms, accumulate_ms=acc_ms, samples_per_s=st["n_samples"] / (ms / 1e3),
-                       roofline=roofline(nbytes, acc_ms),
+                       roofline=roofline(nbytes, acc_ms, traffic=traffic),
                        launch_shape=dict(tuning or {}, source="autotuned" if autotune else "default"))
             log("form %s: step %.2f ms, accumulate %.2f ms" % (name, ms, acc_ms))
         if ref is not None:
@@ -902,7 +905,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_forms and flags == 0:
         res["forms"] = forms_leg(targets, grid, nbytes, ref, targets[:args.cpu_targets], tuning,
-                                 autotune=not args.no_autotune)
+                                 autotune=not args.no_autotune, config_name=cfg.name)
     ref = None
     if not args.no_rebinned:
         res["rebinned"] = rebinned_leg(targets, cfg, grid)

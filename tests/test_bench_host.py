@@ -65,6 +65,18 @@ def test_counter_traffic_needs_the_profiled_source_workload_and_shape(tmp_path, 
     assert bench.counter_traffic("c2", dict(shape)) is None
 
 
+def test_ordered_counter_traffic_reads_its_own_summary(tmp_path, monkeypatch):
+    """The deterministic form's traffic comes from the ordered kernel's summary, never from
+    the packed kernel's (same source file, workload and test, another launch shape)."""
+    shape = dict(tile_u=2, tile_v=2, jblock=64, waves=1)
+    src, prof = _profile(tmp_path, b"kernel", config="c2", launch_shape=shape, hbm_bytes_per_launch=9.0)
+    monkeypatch.setattr(bench, "KERNEL_SRC", src)
+    monkeypatch.setattr(bench, "PROFILE_COUNTERS", str(tmp_path / "missing.json"))
+    assert bench.counter_traffic("c2", dict(shape), prof) == 9.0
+    assert bench.counter_traffic("c2", dict(shape)) is None
+    assert bench.counter_traffic("c2", dict(shape, waves=16), prof) is None
+
+
 def test_batched_counter_traffic_needs_the_profiled_shape(tmp_path, monkeypatch):
     shape = dict(tile_u=8, tile_v=4, jblock=64, waves=8)
     src, prof = _profile(tmp_path, b"kernel", config="c4", launch_shape=shape, hbm_bytes_per_launch=7.0)
